@@ -1,0 +1,182 @@
+"""Named synthetic workloads: network shape, model constants and drive.
+
+The paper's own model (Sec. V: 10 billion neurons from a scanned brain on
+2,000 GPUs) is not public.  These workloads stand in for it at the per-GPU
+shapes the paper implies: 10e9 / 2,000 = 5e6 neurons per GPU, about 1,000
+synapses per neuron (Sec. I quotes 86e9 neurons and 86e12 synapses), 2,000
+partitions (GPUs) grouped into nodes of 8 (the groups of Sec. IV-B), and the
+4,000-GPU / 20e9-neuron row of Table II for the sparser variant.
+
+Numbers here are inputs: LIF constants as stated per workload, network sizes,
+seeds.  Quantities derived from them by the method (the decay factor, the
+Poisson inversion table, spike thresholds) are computed separately by the GPU
+path's binding and by the oracle.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass
+
+TOPO_MATERIALIZED = 0
+TOPO_LOOPBACK = 1
+TOPO_LOOPBACK_SETS = 2
+TOPO_BATCHED = 3
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n_neurons: int
+    k_in: int
+    n_partitions: int
+    gpus_per_node: int
+    topology: int
+    seed: int
+    n_steps: int = 1000
+    remote_frac: float = 0.0
+    vp_set_size: int = 0
+    # uneven partitions (TOPO_BATCHED)
+    size_median: float = 0.0
+    size_sigma_ln: float = 0.0
+    size_lo: int = 0
+    size_hi: int = 0
+    size_scale: float = 1.0
+    cross_lo: float = 0.0
+    cross_hi: float = 0.0
+    # synapses
+    max_delay: int = 10
+    w_exc: float = 0.5
+    w_inh: float = -2.5
+    w_jitter: float = 0.0
+    weight_type: str = "fp32"
+    # LIF neuron (current-based, delta synapses)
+    dt_ms: float = 0.1
+    tau_m_ms: float = 20.0
+    v_rest_mv: float = -65.0
+    v_reset_mv: float = -65.0
+    v_thresh_mv: float = -50.0
+    t_ref_ms: float = 2.0
+    # Poisson drive: rate nu_ext_hz, jump w_ext_mv per event
+    nu_ext_hz: float = 5000.0
+    w_ext_mv: float = 0.1
+    # forced raster (traffic generator): 0 = off; else spikes drawn at
+    # rate_on_hz during the first on_steps of every period_steps, rate_off_hz
+    # otherwise
+    forced: int = 0
+    rate_on_hz: float = 0.0
+    rate_off_hz: float = 0.0
+    period_steps: int = 1
+    on_steps: int = 0
+    description: str = ""
+
+    @property
+    def theta_rel_mv(self) -> float:
+        """Threshold relative to rest (the state variable is u = V - V_rest)."""
+        return self.v_thresh_mv - self.v_rest_mv
+
+    @property
+    def u_reset_mv(self) -> float:
+        return self.v_reset_mv - self.v_rest_mv
+
+    @property
+    def n_ref_steps(self) -> int:
+        return int(round(self.t_ref_ms / self.dt_ms))
+
+    @property
+    def n_nodes(self) -> int:
+        return (self.n_partitions + self.gpus_per_node - 1) // self.gpus_per_node
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+    def scaled(self, n_neurons: int, name: str | None = None, **kw) -> "Workload":
+        """Same structure at another size (tests, CPU baselines).  For uneven
+        partitions every size is scaled and the total is what they sum to."""
+        name = name or f"{self.name}@{n_neurons}"
+        if self.topology == TOPO_BATCHED:
+            full = _resolve(self)
+            w = dataclasses.replace(full, name=name, n_neurons=0,
+                                    size_scale=full.size_scale * n_neurons / full.n_neurons, **kw)
+            return _resolve(w)
+        return dataclasses.replace(self, name=name, n_neurons=n_neurons, **kw)
+
+
+_W = {}
+
+
+def _add(w: Workload):
+    _W[w.name] = w
+    return w
+
+
+# Tiny plain FP32 net: 4,096 LIF neurons, 80/20 exc/inh, fixed in-degree 100,
+# w_exc 0.5 mV / w_inh -2.5 mV, delays 1-10 steps, Poisson 5 kHz x 0.1 mV,
+# 8 partitions on 2 nodes of 4, 1,000 steps.
+TINY = _add(Workload(
+    name="tiny", n_neurons=4096, k_in=100, n_partitions=8, gpus_per_node=4,
+    topology=TOPO_MATERIALIZED, seed=1,
+    description="4,096 LIF neurons, K=100, 8 partitions on 2 nodes of 4, FP32"))
+
+# Same net with a suprathreshold drive so that routing and delivery run on
+# every step (the stated drive keeps the net near silent after the initial
+# transient: mean 10 mV against a 15 mV gap).
+TINY_ACTIVE = _add(TINY.replace(name="tiny_active", w_ext_mv=0.2,
+                                description="tiny net, drive 5 kHz x 0.2 mV"))
+
+# One GPU's share at paper scale: 5e6 neurons, in-degree 1,000, 20 % of the
+# synapses remote over 2,000 virtual partitions on 250 nodes of 8, ~5 Hz.
+PAPER_SHARE = _add(Workload(
+    name="paper_share", n_neurons=5_000_000, k_in=1000, n_partitions=2000, gpus_per_node=8,
+    topology=TOPO_LOOPBACK, remote_frac=0.2, seed=11, w_ext_mv=0.3,
+    description="5e6 neurons, K=1000, 2,000 virtual partitions / 250 nodes, FP32 weights"))
+
+PAPER_SHARE_BF16 = _add(PAPER_SHARE.replace(
+    name="paper_share_bf16", weight_type="bf16",
+    description="paper_share with BF16 weights, FP32 accumulation"))
+
+# Jittered weights: not dyadic, so BF16 rounding actually loses information.
+PAPER_SHARE_JITTER = _add(PAPER_SHARE.replace(
+    name="paper_share_jitter", w_jitter=0.2,
+    description="paper_share with per-synapse weight jitter of +-10 %"))
+
+# Batched uneven partitions: 64 partitions lognormal in [10k, 500k], K=500,
+# 10-60 % of each partition's inputs from other partitions, 8 nodes of 8.
+BATCHED = _add(Workload(
+    name="batched", n_neurons=0, k_in=500, n_partitions=64, gpus_per_node=8,
+    topology=TOPO_BATCHED, seed=13, size_median=70710.678, size_sigma_ln=0.9780057,
+    size_lo=10_000, size_hi=500_000, cross_lo=0.1, cross_hi=0.6, w_ext_mv=0.3,
+    description="64 uneven partitions (lognormal 10k-500k), K=500, 8 nodes of 8"))
+
+# Heavy-traffic routing: 1e6 neurons, in-degree 10,000, BF16 weights, every
+# source fans out to 200 of 2,000 virtual partitions; bursts of 100 Hz for
+# 10 ms every 50 ms (20 Hz mean).
+HEAVY = _add(Workload(
+    name="heavy", n_neurons=1_000_000, k_in=10_000, n_partitions=2000, gpus_per_node=8,
+    topology=TOPO_LOOPBACK_SETS, vp_set_size=200, remote_frac=0.2, seed=14,
+    weight_type="bf16", forced=1, rate_on_hz=100.0, rate_off_hz=0.0,
+    period_steps=500, on_steps=100, w_ext_mv=0.1,
+    description="1e6 neurons, K=10,000, 200 vps per source, bursty forced raster, BF16"))
+
+# Second per-GPU shape from the 4,000-GPU row of Table II: 20e9 / 4,000 =
+# 5e6 neurons per GPU with sparser synapses over 4,000 partitions.
+PAPER_SHARE_4K = _add(PAPER_SHARE.replace(
+    name="paper_share_4k", k_in=500, n_partitions=4000, seed=12,
+    description="5e6 neurons, K=500, 4,000 virtual partitions / 500 nodes"))
+
+WORKLOADS = dict(_W)
+
+
+def _resolve(w: Workload) -> Workload:
+    """Uneven partitions: the neuron count is the sum of the drawn sizes."""
+    if w.topology == TOPO_BATCHED and w.n_neurons == 0:
+        from . import batched_sizes
+        n = int(batched_sizes(w.seed, w.n_partitions, w.size_median, w.size_sigma_ln,
+                              w.size_lo, w.size_hi, w.size_scale).sum())
+        w = dataclasses.replace(w, n_neurons=n)
+    return w
+
+
+def get_workload(name: str) -> Workload:
+    if name not in _W:
+        raise KeyError(f"unknown workload {name!r}; known: {sorted(_W)}")
+    return _resolve(_W[name])

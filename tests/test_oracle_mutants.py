@@ -1,0 +1,56 @@
+"""The oracle's pins catch plausible mistakes: each mutant below plants one
+mistake in a copy of oracle.c (on the CPU), and the pin tests must fail
+against it."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PIN_TESTS = ["tests/test_oracle_rng.py", "tests/test_oracle_lif.py",
+             "tests/test_oracle_routing.py", "tests/test_oracle_delivery.py"]
+
+MUTANTS = {
+    "philox_word_swap": ("uint32_t y0 = hi1 ^ x1 ^ k0;", "uint32_t y0 = hi1 ^ x3 ^ k0;"),
+    "philox_key_bump": ("k1 += W1;", "k1 += W0;"),
+    "poisson_strict": ("if (thr[j] <= r) k++;", "if (thr[j] < r) k++;"),
+    "drop_drive": ("float I = f32((double)syn + (double)ext);", "float I = f32((double)syn);"),
+    "strict_threshold": ("(integrating && s->u[i] >= s->theta)",
+                         "(integrating && s->u[i] > s->theta)"),
+    "short_refractory": ("s->ref[i] = (uint8_t)s->n_ref;", "s->ref[i] = (uint8_t)s->n_ref - 1;"),
+    "fused_update": ("float v = f32((double)s->u[i] * (double)s->alpha);\n"
+                     "      s->u[i] = f32((double)v + (double)I);",
+                     "s->u[i] = f32((double)s->u[i] * (double)s->alpha + (double)I);"),
+    "mask_bit_shift": ("s->node_mask[node] |= 1u << (s->vps[j] - s->G * node);",
+                       "s->node_mask[node] |= 1u << (s->vps[j] - s->G * node + 1);"),
+    "own_partition": ("if (v == own) continue;", "if (v == own + 1) continue;"),
+    "level_swap": ("if (node == own_node) s->stats[ORC_MSG_L1]++;",
+                   "if (node != own_node) s->stats[ORC_MSG_L1]++;"),
+    "delay_slot": ("size_t at = (size_t)((t + s->e_delay[e]) % s->D) * s->N + s->e_tgt[e];\n"
+                   "      s->ring[at]",
+                   "size_t at = (size_t)((t + s->e_delay[e] - 1) % s->D) * s->N + s->e_tgt[e];\n"
+                   "      s->ring[at]"),
+    "expand_bit_order": ("uint32_t p = s->G * n + b;", "uint32_t p = s->G * n + (s->G - 1 - b);"),
+    "bf16_ties_up": ("return ((lo_b >> 16) & 1) == 0 ? lo : hi;", "return hi;"),
+    "no_slot_clear": ("s->ring[(size_t)slot * s->N + i] = 0.0f;", ""),
+    "fp64_weight": ("s->ring64[at] += s->e_w64[e];",
+                    "s->ring64[at] += (double)(float)s->e_w64[e] * 1.0000001;"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    old, new = MUTANTS[name]
+    assert old in src, f"mutation site of {name} not found"
+    c = tmp_path / "oracle_mutant.c"
+    c.write_text(src.replace(old, new, 1))
+    so = tmp_path / "liboracle_mutant.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-shared", "-fPIC",
+                    "-I", os.path.join(ROOT, "oracle"), "-o", str(so), str(c), "-lm"], check=True)
+    env = dict(os.environ, SNN_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", *PIN_TESTS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"mutant {name} survived:\n{r.stdout[-2000:]}"
