@@ -1,0 +1,243 @@
+/*
+ * snn.h — C ABI of one GPU's share of a spiking-network simulation step with
+ * two-level spike routing, for AMD Instinct MI355X (gfx950).
+ *
+ * The paper this follows ("A Low-latency Communication Design for Brain
+ * Simulations") states the problem as: neurons are partitioned over GPUs
+ * (the neuron-GPU mapping PM of Algorithm 1, Sec. IV-A); GPUs are grouped
+ * (Algorithm 2, Sec. IV-B) so that traffic inside a group goes directly
+ * (level 1) and traffic to another group goes once to that group, where a
+ * bridge GPU forwards it (level 2); the simulation alternates computation on
+ * the GPUs with this exchange (Sec. I).  The direct peer-to-peer exchange
+ * it improves on (Sec. II, Table II) is kept beside it.
+ *
+ * On one GPU every partition and node other than the GPU's own is a virtual
+ * buffer in HBM; groups are nodes of gpus_per_node (<= 8) partitions, so a
+ * node's destination set is an 8-bit mask.  One step is three calls, always
+ * in this order:
+ *
+ *   snn_step     neuron update and threshold for step t, then compaction of
+ *                the fired neuron IDs into an ascending list
+ *   snn_route    two-level: one message (source, mask) per destination node
+ *                into per-node send buckets, then expansion of each mask into
+ *                per-partition receive lists (what the bridge of Sec. IV-B
+ *                does); flat: one entry per (source, destination partition)
+ *   snn_deliver  synaptic delivery: each fired source's own-partition
+ *                synapses, then the synapses reached through the receive
+ *                lists, accumulated into a delay ring; t advances
+ *
+ * Neuron model (the paper only names LIF as a model class, Table I):
+ * current-based leaky integrate-and-fire with delta synapses, state
+ * u = V - V_rest in binary32.  Per neuron i at step t, with D = max_delay + 1:
+ *   syn = ring[t mod D][i]; ring[t mod D][i] = 0
+ *   r   = Philox4x32-10(counter (i/4, t, 1, 0), key seed) word i mod 4
+ *   k   = #{ j < 15 : poisson_thr[j] <= r };  ext = fl(k * w_ext)
+ *   if ref[i] > 0: ref[i] -= 1            (input discarded, u unchanged)
+ *   else:          u = fl(fl(u * alpha) + fl(syn + ext))
+ *   spike = forced ? (r2 < raster threshold of step t) : (integrating && u >= theta)
+ *           with r2 the Philox word on stream 2
+ *   if spike: u = u_reset; ref[i] = n_ref
+ * and every synapse (s -> tgt, w, d) of a fired s adds w to ring[(t+d) mod D][tgt].
+ *
+ * Conventions for every call:
+ *  - Return value: SNN_OK or a negative snn_status; calls never abort.  The
+ *    message of the last failure on the calling thread is snn_last_error().
+ *  - Device pointers are caller-owned (e.g. torch tensors), borrowed for the
+ *    handle's lifetime, never freed by the library.  Host pointers are only
+ *    read or written during the call.
+ *  - step/route/deliver/run only enqueue work on the handle's stream and
+ *    never synchronise.  Device-side capacity overflow is sticky and is
+ *    reported as SNN_ERR_CAPACITY by the next synchronising call
+ *    (snn_read_*, snn_sync, snn_destroy); buffers are never silently
+ *    truncated.
+ *  - One handle per stream; a handle is not thread-safe.
+ */
+#ifndef SNN_H
+#define SNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct snn_ctx* snn_handle;
+
+typedef enum {
+  SNN_OK = 0,
+  SNN_ERR_INVALID_ARG = -1,
+  SNN_ERR_BAD_STATE = -2,   /* calls out of the step -> route -> deliver order */
+  SNN_ERR_CAPACITY = -3,    /* a bucket, receive list or the spike log overflowed */
+  SNN_ERR_HIP = -4,         /* a HIP runtime call failed */
+  SNN_ERR_UNSUPPORTED = -5
+} snn_status;
+
+/* Routing modes (snn_route). */
+enum {
+  SNN_ROUTE_TWO_LEVEL = 0,  /* Sec. IV-B: per-node masked messages, then expansion */
+  SNN_ROUTE_FLAT = 1,       /* direct peer-to-peer: one entry per destination partition */
+  SNN_ROUTE_BOTH = 2        /* both buffers filled (for checking); delivery reads the
+                               two-level receive lists */
+};
+
+/* Weight storage (snn_params.weight_type). */
+enum { SNN_W_FP32 = 0, SNN_W_BF16 = 1 };
+
+/* snn_params.flags */
+enum {
+  SNN_FORCED_RASTER = 1u    /* spikes are Bernoulli draws (traffic generator); the
+                               membrane update still runs and fired neurons reset */
+};
+
+/* Per-step counters (snn_read_counters), in this order. */
+enum {
+  SNN_STAT_SPIKES = 0,
+  SNN_STAT_LOCAL_EVENTS = 1,   /* synapses delivered inside the source's partition */
+  SNN_STAT_REMOTE_EVENTS = 2,  /* synapses delivered through receive lists */
+  SNN_STAT_MSG_L1 = 3,         /* two-level messages to the source's own node */
+  SNN_STAT_MSG_L2 = 4,         /* two-level messages to other nodes */
+  SNN_STAT_FLAT_MSGS = 5,      /* flat entries (one per spike and destination partition) */
+  SNN_STAT_RECV_ENTRIES = 6,   /* receive-list entries produced by mask expansion */
+  SNN_NSTAT = 7
+};
+
+/* Largest supported sizes. */
+#define SNN_MAX_GPUS_PER_NODE 8u
+#define SNN_MAX_DELAY 15u
+#define SNN_MAX_NEURONS (1u << 27)    /* target ids share 32 bits with the delay */
+#define SNN_MAX_PARTITIONS 65535u
+
+/* All by value; validated by snn_workspace_size and snn_create. */
+typedef struct {
+  uint32_t n_neurons;         /* neurons on this GPU (all materialised partitions) */
+  uint32_t n_partitions;      /* partitions (GPUs), real and virtual */
+  uint32_t gpus_per_node;     /* group size G, 1..8: mask bit b <-> partition G*n + b */
+  uint32_t max_delay;         /* synaptic delays in [1, max_delay], max_delay <= 15 */
+  float alpha;                /* membrane decay per step, fl32(exp(-dt/tau_m)) */
+  float theta;                /* threshold relative to rest (mV) */
+  float u_reset;              /* reset relative to rest (mV) */
+  float w_ext;                /* jump per external Poisson event (mV) */
+  uint32_t n_ref;             /* refractory steps, <= 255 */
+  uint32_t poisson_thr[15];   /* floor(2^32 * CDF_lambda(j)), j = 0..14, nondecreasing */
+  uint64_t seed;              /* Philox key */
+  uint32_t weight_type;       /* SNN_W_FP32 or SNN_W_BF16 */
+  uint32_t flags;             /* SNN_FORCED_RASTER */
+  uint32_t raster_thr_on;     /* forced raster: spike iff r2 < thr; thr_on during the first */
+  uint32_t raster_thr_off;    /*   raster_on steps of every raster_period steps, */
+  uint32_t raster_period;     /*   thr_off otherwise (period >= 1) */
+  uint32_t raster_on;
+  uint64_t bucket_total;      /* total per-node bucket capacity (messages) */
+  uint64_t recv_total;        /* total per-partition receive-list capacity (entries) */
+  uint32_t log_steps;         /* steps kept for snn_read_spikes / snn_read_counters (>= 1);
+                                 older steps are overwritten */
+  uint32_t reserved0;
+  uint64_t log_cap;           /* spike-log capacity in neuron ids */
+} snn_params;
+
+/* Network arrays in device memory.  nnz = row_ptr[n_neurons]; pairs =
+   vp_ptr[n_neurons]; n_nodes = ceil(n_partitions / gpus_per_node). */
+typedef struct {
+  const int64_t* row_ptr;          /* [N+1] out-synapses of source s: [row_ptr[s], row_ptr[s+1]) */
+  const uint32_t* n_local;         /* [N] the first n_local[s] synapses of the row stay in
+                                      the source's own partition */
+  const uint32_t* tgt_delay;       /* [nnz] (delay << 27) | target neuron */
+  const void* weight;              /* [nnz] float (SNN_W_FP32) or bfloat16 bits (SNN_W_BF16) */
+  const int64_t* vp_ptr;           /* [N+1] destination partitions of s:
+                                      vp_part[vp_ptr[s] .. vp_ptr[s+1]) */
+  const uint16_t* vp_part;         /* [pairs] distinct, ascending, never s's own partition;
+                                      this is the routing table TB of Sec. IV-B restricted
+                                      to one source */
+  const uint32_t* vp_seg;          /* [pairs] first synapse (relative to row_ptr[s]) of the
+                                      row segment going to vp_part[j]; segments follow the
+                                      local part in vp order and end where the next begins
+                                      (the last at the row's end) */
+  const int32_t* part_of_neuron;   /* [N] the neuron-GPU mapping PM of Sec. IV-A */
+  const uint64_t* bucket_off;      /* [n_nodes+1] bucket of node n holds at most
+                                      bucket_off[n+1] - bucket_off[n] messages */
+  const uint64_t* recv_off;        /* [P+1] receive list of partition p holds at most
+                                      recv_off[p+1] - recv_off[p] entries */
+  float* u;                        /* [N] membrane state, relative to rest (read/write) */
+  uint8_t* ref;                    /* [N] refractory steps left (read/write) */
+  float* ring;                     /* [(max_delay+1) * ring_stride] delay ring, slot-major,
+                                      ring_stride = snn_ring_stride(N); zero-initialised by
+                                      the caller (read/write) */
+} snn_network_dev;
+
+/* Slot stride of the delay ring: n_neurons rounded up to a multiple of 256. */
+uint64_t snn_ring_stride(uint32_t n_neurons);
+
+/* Device workspace the caller must provide to snn_create (bytes, 256-byte
+   aligned base).  Depends on n_neurons, n_partitions, gpus_per_node,
+   bucket_total, recv_total, log_steps and log_cap. */
+snn_status snn_workspace_size(const snn_params* params, size_t* bytes);
+
+/* Validates params and array pointers, carves the workspace, zeroes its
+   counters on `stream` and returns a handle at step t = 0.  `stream` is a
+   hipStream_t (NULL = the default stream).  Does not allocate device
+   memory. */
+snn_status snn_create(const snn_params* params, const snn_network_dev* net,
+                      void* workspace, size_t workspace_bytes, void* stream,
+                      snn_handle* out);
+
+/* Neuron update, threshold and ascending compaction of fired ids for the
+   current step t (ring slot t mod D is read and cleared).  Order: must follow
+   snn_create or snn_deliver. */
+snn_status snn_step(snn_handle h);
+
+/* Routes the spikes of the current step (mode SNN_ROUTE_*).  Order: must
+   follow snn_step. */
+snn_status snn_route(snn_handle h, int mode);
+
+/* Delivers the current step's synaptic events (own partition and receive
+   lists) into ring slots (t + d) mod D, then advances t.  Order: must follow
+   snn_route. */
+snn_status snn_deliver(snn_handle h);
+
+/* n_steps full steps (step, route(mode), deliver).  use_graph != 0 captures
+   one step into a HIP graph once and replays it (all step-dependent values
+   live in device memory).  Order: as snn_step. */
+snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph);
+
+/* Blocks until the handle's work is done; reports sticky device errors. */
+snn_status snn_sync(snn_handle h);
+
+/* Steps completed so far (host-side count of enqueued steps). */
+uint64_t snn_time(snn_handle h);
+
+/* Fired ids of steps [first_step, first_step + n_steps), which must be among
+   the last log_steps steps; ids ascending within a step, concatenated.
+   per_step_counts[n_steps] (may be NULL); ids may be NULL to query *n_ids.
+   Fails with SNN_ERR_CAPACITY if more than cap ids or if the spike log
+   overflowed for a requested step.  Synchronises. */
+snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps,
+                           int32_t* ids, uint64_t cap, uint32_t* per_step_counts,
+                           uint64_t* n_ids);
+
+/* Routing buffers of the last routed step, copied to host memory.
+   which = 0: flat receive lists (uint32 source ids, per partition);
+   which = 1: expanded two-level receive lists (uint32 source ids);
+   which = 2: per-node send buckets (uint64 messages: bits 0..31 source id,
+              bits 32..39 partition mask of the node; upper bits unspecified).
+   sizes[n_partitions or n_nodes] receives the counts; entries (may be NULL)
+   receives the lists concatenated in partition / node order, at most cap
+   entries (elements of 4 or 8 bytes).  Order inside a list is unspecified.
+   Synchronises. */
+snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entries,
+                           uint64_t cap, uint64_t* n_entries);
+
+/* Counters of steps [first_step, first_step + n_steps) (the last log_steps
+   steps), out[n_steps][SNN_NSTAT].  Synchronises. */
+snn_status snn_read_counters(snn_handle h, uint64_t first_step, uint32_t n_steps,
+                             uint64_t* out);
+
+/* Releases the handle (NULL is a no-op).  Synchronises first. */
+snn_status snn_destroy(snn_handle h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* snn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNN_H */

@@ -1,0 +1,91 @@
+/*
+ * snn_setup.h — host-side setup of the arrays that snn_create consumes.
+ *
+ * Partition assignment and the routing table are setup steps of the paper's
+ * design, run before the simulation (Algorithm 1 produces the neuron-GPU
+ * mapping PM, Sec. IV-A; Algorithm 2 the routing table TB, Sec. IV-B).  Here
+ * PM is taken as given by the seeded network description (contiguous
+ * partitions, or every neuron in partition 0 for one GPU's share with virtual
+ * remote partitions) and TB degenerates to each source's ascending list of
+ * destination partitions, grouped into nodes of gpus_per_node.
+ *
+ * The setup regenerates the synapse list twice from the counter-based
+ * generator (once to count out-degrees, once to place synapses), so host
+ * memory holds only the output arrays plus one 16-bit partition tag per
+ * synapse while rows are sorted.  Multithreaded with OpenMP; the output does
+ * not depend on the thread count.
+ *
+ * Usage:
+ *   snn_setup_create(...)               count out-degrees -> nnz
+ *   snn_setup_fill_rows(...)            row_ptr, n_local, tgt_delay, weight
+ *   snn_setup_sizes(...)                pairs, bucket_total, recv_total
+ *   snn_setup_fill_routes(...)          vp_ptr, vp_part, vp_seg, part_of_neuron,
+ *                                       bucket_off, recv_off
+ *   snn_setup_destroy(...)
+ * All output pointers are caller-owned HOST arrays of the sizes stated.
+ */
+#ifndef SNN_SETUP_H
+#define SNN_SETUP_H
+
+#include <stdint.h>
+
+#include "snn.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct snn_setup* snn_setup_handle;
+
+/* Network description; the same fields the seeded generator takes. */
+typedef struct {
+  uint64_t seed;
+  uint32_t n_neurons;
+  uint32_t k_in;            /* incoming synapses per target */
+  uint32_t max_delay;       /* delays in [1, max_delay], <= 15 */
+  uint32_t n_partitions;
+  uint32_t topology;        /* 0 materialised, 1 loopback, 2 loopback with per-source
+                               partition sets, 3 uneven partitions */
+  uint32_t vp_set_size;
+  double remote_frac;
+  double w_exc, w_inh;      /* mV */
+  double w_jitter;
+  uint32_t gpus_per_node;   /* 1..8 */
+  uint32_t weight_type;     /* SNN_W_FP32 or SNN_W_BF16 (round to nearest even) */
+  uint32_t n_threads;       /* 0: OpenMP default */
+  uint32_t reserved;
+} snn_setup_spec;
+
+/* part_start: n_partitions+1 ascending neuron offsets for topologies 0 and 3
+   (NULL otherwise); cross_frac: n_partitions probabilities for topology 3.
+   Counts out-degrees (first pass over the synapses). */
+snn_status snn_setup_create(const snn_setup_spec* spec, const uint32_t* part_start,
+                            const double* cross_frac, snn_setup_handle* out);
+
+/* nnz = total synapses (known after create); pairs, bucket_total and
+   recv_total are known after snn_setup_fill_rows (0 before). */
+snn_status snn_setup_sizes(snn_setup_handle h, uint64_t* nnz, uint64_t* pairs,
+                           uint64_t* bucket_total, uint64_t* recv_total);
+
+/* Second pass: places every synapse in its source row and sorts each row into
+   [own-partition synapses | destination partitions ascending], ties by
+   (target, delay, weight).  row_ptr[N+1], n_local[N], tgt_delay[nnz],
+   weight[nnz] (float or uint16 per weight_type). */
+snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n_local,
+                               uint32_t* tgt_delay, void* weight);
+
+/* Destination-partition lists and capacity bounds: vp_ptr[N+1], vp_part[pairs],
+   vp_seg[pairs], part_of_neuron[N], bucket_off[n_nodes+1] (bucket of node n:
+   number of sources with a destination partition in n), recv_off[P+1] (list of
+   partition p: number of sources with destination p).  These bounds are exact
+   maxima per step, so routing can never overflow. */
+snn_status snn_setup_fill_routes(snn_setup_handle h, int64_t* vp_ptr, uint16_t* vp_part,
+                                 uint32_t* vp_seg, int32_t* part_of_neuron,
+                                 uint64_t* bucket_off, uint64_t* recv_off);
+
+void snn_setup_destroy(snn_setup_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNN_SETUP_H */

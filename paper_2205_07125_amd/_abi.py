@@ -1,0 +1,171 @@
+"""ctypes mirror of include/snn.h and include/snn_setup.h (argument
+marshalling only; every step of the simulation runs in libsnn's kernels)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("SNN_LIB") or os.path.join(_PKG, "libsnn.so")
+
+SNN_OK = 0
+SNN_ERR_INVALID_ARG = -1
+SNN_ERR_BAD_STATE = -2
+SNN_ERR_CAPACITY = -3
+SNN_ERR_HIP = -4
+SNN_ERR_UNSUPPORTED = -5
+
+SNN_ROUTE_TWO_LEVEL = 0
+SNN_ROUTE_FLAT = 1
+SNN_ROUTE_BOTH = 2
+
+SNN_W_FP32 = 0
+SNN_W_BF16 = 1
+SNN_FORCED_RASTER = 1
+
+STAT_NAMES = ["spikes", "local_events", "remote_events", "msg_l1", "msg_l2", "flat_msgs",
+              "recv_entries"]
+SNN_NSTAT = len(STAT_NAMES)
+
+EXPORTED = [
+    "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route",
+    "snn_deliver", "snn_run", "snn_sync", "snn_time", "snn_read_spikes", "snn_read_routes",
+    "snn_read_counters", "snn_destroy", "snn_last_error",
+    "snn_setup_create", "snn_setup_sizes", "snn_setup_fill_rows", "snn_setup_fill_routes",
+    "snn_setup_destroy",
+]
+
+u32, u64, i32, f32, f64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
+vp = ctypes.c_void_p
+
+
+class snn_params(ctypes.Structure):
+    _fields_ = [
+        ("n_neurons", u32), ("n_partitions", u32), ("gpus_per_node", u32), ("max_delay", u32),
+        ("alpha", f32), ("theta", f32), ("u_reset", f32), ("w_ext", f32),
+        ("n_ref", u32), ("poisson_thr", u32 * 15),
+        ("seed", u64), ("weight_type", u32), ("flags", u32),
+        ("raster_thr_on", u32), ("raster_thr_off", u32), ("raster_period", u32), ("raster_on", u32),
+        ("bucket_total", u64), ("recv_total", u64),
+        ("log_steps", u32), ("reserved0", u32), ("log_cap", u64),
+    ]
+
+
+class snn_network_dev(ctypes.Structure):
+    _fields_ = [(n, vp) for n in (
+        "row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_seg",
+        "part_of_neuron", "bucket_off", "recv_off", "u", "ref", "ring")]
+
+
+class snn_setup_spec(ctypes.Structure):
+    _fields_ = [
+        ("seed", u64), ("n_neurons", u32), ("k_in", u32), ("max_delay", u32),
+        ("n_partitions", u32), ("topology", u32), ("vp_set_size", u32),
+        ("remote_frac", f64), ("w_exc", f64), ("w_inh", f64), ("w_jitter", f64),
+        ("gpus_per_node", u32), ("weight_type", u32), ("n_threads", u32), ("reserved", u32),
+    ]
+
+
+class SNNError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"snn status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The HIP library.  There is no fallback: without it nothing runs."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2205_07125_amd/build.py` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        I = ctypes.c_int
+        sig = {
+            "snn_ring_stride": (u64, [u32]),
+            "snn_workspace_size": (I, [ctypes.POINTER(snn_params), ctypes.POINTER(ctypes.c_size_t)]),
+            "snn_create": (I, [ctypes.POINTER(snn_params), ctypes.POINTER(snn_network_dev), vp,
+                               ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+            "snn_step": (I, [vp]),
+            "snn_route": (I, [vp, I]),
+            "snn_deliver": (I, [vp]),
+            "snn_run": (I, [vp, u32, I, I]),
+            "snn_sync": (I, [vp]),
+            "snn_time": (u64, [vp]),
+            "snn_read_spikes": (I, [vp, u64, u32, vp, u64, vp, ctypes.POINTER(u64)]),
+            "snn_read_routes": (I, [vp, I, vp, vp, u64, ctypes.POINTER(u64)]),
+            "snn_read_counters": (I, [vp, u64, u32, vp]),
+            "snn_destroy": (I, [vp]),
+            "snn_last_error": (ctypes.c_char_p, []),
+            "snn_setup_create": (I, [ctypes.POINTER(snn_setup_spec), vp, vp, ctypes.POINTER(vp)]),
+            "snn_setup_sizes": (I, [vp] + [ctypes.POINTER(u64)] * 4),
+            "snn_setup_fill_rows": (I, [vp, vp, vp, vp, vp]),
+            "snn_setup_fill_routes": (I, [vp] * 7),
+            "snn_setup_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != SNN_OK:
+        raise SNNError(status, lib().snn_last_error().decode(errors="replace"))
+    return status
+
+
+# Same names as the C ABI; each one marshals its arguments and checks the status.
+def snn_ring_stride(n: int) -> int:
+    return int(lib().snn_ring_stride(n))
+
+
+def snn_workspace_size(params: snn_params) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib().snn_workspace_size(ctypes.byref(params), ctypes.byref(out)))
+    return out.value
+
+
+def snn_create(params: snn_params, net: snn_network_dev, workspace: int, ws_bytes: int,
+               stream: int) -> int:
+    h = vp()
+    check(lib().snn_create(ctypes.byref(params), ctypes.byref(net), workspace, ws_bytes, stream,
+                           ctypes.byref(h)))
+    return h.value
+
+
+def snn_step(h):
+    check(lib().snn_step(h))
+
+
+def snn_route(h, mode: int):
+    check(lib().snn_route(h, mode))
+
+
+def snn_deliver(h):
+    check(lib().snn_deliver(h))
+
+
+def snn_run(h, n_steps: int, mode: int, use_graph: bool):
+    check(lib().snn_run(h, n_steps, mode, 1 if use_graph else 0))
+
+
+def snn_sync(h):
+    check(lib().snn_sync(h))
+
+
+def snn_time(h) -> int:
+    return int(lib().snn_time(h))
+
+
+def snn_destroy(h):
+    check(lib().snn_destroy(h))
+
+
+def snn_last_error() -> str:
+    return lib().snn_last_error().decode(errors="replace")

@@ -1,0 +1,431 @@
+// snn_runtime.hip — host side of the C ABI declared in include/snn.h:
+// parameter validation, workspace carve-up, the step -> route -> deliver
+// state machine, HIP-graph replay of whole steps, and read-back.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "snn_internal.h"
+
+using namespace snn;
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+// Records the message returned by snn_last_error; shared with the host
+// setup code of the same library (not exported).
+extern "C" __attribute__((visibility("hidden"))) snn_status snn_fail_v(snn_status s,
+                                                                       const char* fmt,
+                                                                       va_list ap) {
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  return s;
+}
+
+namespace {
+
+snn_status fail(snn_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  snn_fail_v(s, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define HIP_TRY(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) return fail(SNN_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+uint32_t n_nodes_of(const snn_params* p) {
+  return (p->n_partitions + p->gpus_per_node - 1) / p->gpus_per_node;
+}
+
+uint32_t update_blocks(uint32_t n) { return (n + UPDATE_NPB - 1) / UPDATE_NPB; }
+
+// Byte offsets of the workspace regions.
+struct Layout {
+  uint64_t st, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat, stats,
+      log_off, log, total;
+};
+
+Layout layout(const snn_params* p) {
+  Layout L{};
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.st = take(sizeof(DevState));
+  L.lookback = take(sizeof(uint64_t) * update_blocks(p->n_neurons));
+  L.fired = take(sizeof(uint32_t) * uint64_t(p->n_neurons));
+  L.bucket_cnt = take(sizeof(uint32_t) * n_nodes_of(p));
+  L.bucket = take(sizeof(uint64_t) * p->bucket_total);
+  L.recv_cnt = take(sizeof(uint32_t) * p->n_partitions);
+  L.recv = take(sizeof(uint32_t) * p->recv_total);
+  L.flat_cnt = take(sizeof(uint32_t) * p->n_partitions);
+  L.flat = take(sizeof(uint32_t) * p->recv_total);
+  L.stats = take(sizeof(uint64_t) * SNN_NSTAT * uint64_t(p->log_steps));
+  L.log_off = take(sizeof(uint64_t) * uint64_t(p->log_steps));
+  L.log = take(sizeof(uint32_t) * p->log_cap);
+  L.total = o;
+  return L;
+}
+
+snn_status check_params(const snn_params* p) {
+  if (!p) return fail(SNN_ERR_INVALID_ARG, "params is NULL");
+  if (p->n_neurons == 0 || p->n_neurons > SNN_MAX_NEURONS)
+    return fail(SNN_ERR_INVALID_ARG, "n_neurons=%u outside [1, 2^27]", p->n_neurons);
+  if (p->n_partitions == 0 || p->n_partitions > SNN_MAX_PARTITIONS)
+    return fail(SNN_ERR_INVALID_ARG, "n_partitions=%u outside [1, 65535]", p->n_partitions);
+  if (p->gpus_per_node == 0 || p->gpus_per_node > SNN_MAX_GPUS_PER_NODE)
+    return fail(SNN_ERR_INVALID_ARG, "gpus_per_node=%u outside [1, 8]", p->gpus_per_node);
+  if (p->max_delay == 0 || p->max_delay > SNN_MAX_DELAY)
+    return fail(SNN_ERR_INVALID_ARG, "max_delay=%u outside [1, 15]", p->max_delay);
+  if (p->n_ref > 255) return fail(SNN_ERR_INVALID_ARG, "n_ref=%u > 255", p->n_ref);
+  for (int j = 1; j < 15; ++j)
+    if (p->poisson_thr[j] < p->poisson_thr[j - 1])
+      return fail(SNN_ERR_INVALID_ARG, "poisson_thr is not nondecreasing at %d", j);
+  if (p->weight_type != SNN_W_FP32 && p->weight_type != SNN_W_BF16)
+    return fail(SNN_ERR_INVALID_ARG, "weight_type=%u", p->weight_type);
+  if (p->flags & ~uint32_t(SNN_FORCED_RASTER))
+    return fail(SNN_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+  if ((p->flags & SNN_FORCED_RASTER) && p->raster_period == 0)
+    return fail(SNN_ERR_INVALID_ARG, "raster_period must be >= 1");
+  if (p->log_steps == 0) return fail(SNN_ERR_INVALID_ARG, "log_steps must be >= 1");
+  return SNN_OK;
+}
+
+}  // namespace
+
+struct snn_ctx {
+  snn_params prm;
+  snn_network_dev net;
+  hipStream_t stream;
+  KParams kp;
+  uint32_t k1_blocks;
+  int phase;          // 0: expects step, 1: route, 2: deliver
+  int route_mode;     // mode of the step in flight
+  uint64_t t_host;    // steps enqueued
+  uint64_t routed_t;  // step whose routes are in the buffers (+1), 0 = none
+  hipGraphExec_t graph[3];
+};
+
+extern "C" {
+
+uint64_t snn_ring_stride(uint32_t n_neurons) { return (uint64_t(n_neurons) + 255) & ~uint64_t(255); }
+
+const char* snn_last_error(void) { return g_err; }
+
+snn_status snn_workspace_size(const snn_params* params, size_t* bytes) {
+  snn_status s = check_params(params);
+  if (s != SNN_OK) return s;
+  if (!bytes) return fail(SNN_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = layout(params).total;
+  return SNN_OK;
+}
+
+snn_status snn_create(const snn_params* params, const snn_network_dev* net, void* workspace,
+                      size_t workspace_bytes, void* stream, snn_handle* out) {
+  if (!out) return fail(SNN_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  snn_status s = check_params(params);
+  if (s != SNN_OK) return s;
+  if (!net) return fail(SNN_ERR_INVALID_ARG, "net is NULL");
+  const void* req[] = {net->row_ptr, net->n_local, net->tgt_delay, net->weight, net->vp_ptr,
+                       net->vp_part, net->vp_seg, net->part_of_neuron, net->bucket_off,
+                       net->recv_off, net->u, net->ref, net->ring};
+  const char* names[] = {"row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part",
+                         "vp_seg", "part_of_neuron", "bucket_off", "recv_off", "u", "ref", "ring"};
+  for (int i = 0; i < 13; ++i)
+    if (!req[i]) return fail(SNN_ERR_INVALID_ARG, "net->%s is NULL", names[i]);
+  if ((reinterpret_cast<uintptr_t>(net->u) & 15) || (reinterpret_cast<uintptr_t>(net->ring) & 15) ||
+      (reinterpret_cast<uintptr_t>(net->ref) & 3))
+    return fail(SNN_ERR_INVALID_ARG, "u and ring must be 16-byte aligned, ref 4-byte aligned");
+  const Layout L = layout(params);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(SNN_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(SNN_ERR_INVALID_ARG, "workspace has %zu bytes, needs %llu", workspace_bytes,
+                (unsigned long long)L.total);
+
+  snn_ctx* c = new snn_ctx();
+  c->prm = *params;
+  c->net = *net;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->k1_blocks = update_blocks(params->n_neurons);
+  KParams& k = c->kp;
+  k.N = params->n_neurons;
+  k.P = params->n_partitions;
+  k.G = params->gpus_per_node;
+  k.D = params->max_delay + 1;
+  k.n_nodes = n_nodes_of(params);
+  k.n_ref = params->n_ref;
+  k.ring_stride = snn_ring_stride(params->n_neurons);
+  k.alpha = params->alpha;
+  k.theta = params->theta;
+  k.u_reset = params->u_reset;
+  k.w_ext = params->w_ext;
+  std::memcpy(k.thr, params->poisson_thr, sizeof(k.thr));
+  k.seed_lo = uint32_t(params->seed);
+  k.seed_hi = uint32_t(params->seed >> 32);
+  k.forced = (params->flags & SNN_FORCED_RASTER) ? 1u : 0u;
+  k.raster_on_thr = params->raster_thr_on;
+  k.raster_off_thr = params->raster_thr_off;
+  k.raster_period = params->raster_period ? params->raster_period : 1u;
+  k.raster_on = params->raster_on;
+  k.bf16 = params->weight_type == SNN_W_BF16 ? 1u : 0u;
+  k.log_steps = params->log_steps;
+  k.log_cap = params->log_cap;
+  k.row_ptr = net->row_ptr;
+  k.n_local = net->n_local;
+  k.tgt_delay = net->tgt_delay;
+  k.weight = net->weight;
+  k.vp_ptr = net->vp_ptr;
+  k.vp_part = net->vp_part;
+  k.vp_seg = net->vp_seg;
+  k.part = net->part_of_neuron;
+  k.bucket_off = net->bucket_off;
+  k.recv_off = net->recv_off;
+  k.u = net->u;
+  k.ref = net->ref;
+  k.ring = net->ring;
+  char* ws = static_cast<char*>(workspace);
+  k.st = reinterpret_cast<DevState*>(ws + L.st);
+  k.lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  k.fired = reinterpret_cast<uint32_t*>(ws + L.fired);
+  k.bucket_cnt = reinterpret_cast<uint32_t*>(ws + L.bucket_cnt);
+  k.bucket = reinterpret_cast<uint64_t*>(ws + L.bucket);
+  k.recv_cnt = reinterpret_cast<uint32_t*>(ws + L.recv_cnt);
+  k.recv = reinterpret_cast<uint32_t*>(ws + L.recv);
+  k.flat_cnt = reinterpret_cast<uint32_t*>(ws + L.flat_cnt);
+  k.flat = reinterpret_cast<uint32_t*>(ws + L.flat);
+  k.stats = reinterpret_cast<uint64_t*>(ws + L.stats);
+  k.log_off = reinterpret_cast<uint64_t*>(ws + L.log_off);
+  k.log = reinterpret_cast<uint32_t*>(ws + L.log);
+  // Only the small regions need zeros: state, look-back words, counters.
+  hipError_t e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ws + L.recv_cnt, 0, L.recv - L.recv_cnt, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ws + L.flat_cnt, 0, L.flat - L.flat_cnt, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ws + L.stats, 0, L.log - L.stats, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(SNN_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return SNN_OK;
+}
+
+snn_status snn_step(snn_handle h) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_step called before snn_deliver");
+  HIP_TRY(launch_update(h->kp, h->k1_blocks, h->stream));
+  h->phase = 1;
+  return SNN_OK;
+}
+
+snn_status snn_route(snn_handle h, int mode) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  if (mode < SNN_ROUTE_TWO_LEVEL || mode > SNN_ROUTE_BOTH)
+    return fail(SNN_ERR_INVALID_ARG, "route mode %d", mode);
+  if (h->phase != 1) return fail(SNN_ERR_BAD_STATE, "snn_route must follow snn_step");
+  HIP_TRY(launch_route(h->kp, mode, h->stream));
+  h->route_mode = mode;
+  h->phase = 2;
+  h->routed_t = h->t_host + 1;
+  return SNN_OK;
+}
+
+snn_status snn_deliver(snn_handle h) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  if (h->phase != 2) return fail(SNN_ERR_BAD_STATE, "snn_deliver must follow snn_route");
+  HIP_TRY(launch_deliver(h->kp, h->route_mode, h->stream));
+  h->phase = 0;
+  h->t_host += 1;
+  return SNN_OK;
+}
+
+snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  if (mode < SNN_ROUTE_TWO_LEVEL || mode > SNN_ROUTE_BOTH)
+    return fail(SNN_ERR_INVALID_ARG, "route mode %d", mode);
+  if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_run called in the middle of a step");
+  if (n_steps == 0) return SNN_OK;
+  if (!use_graph) {
+    for (uint32_t i = 0; i < n_steps; ++i) {
+      HIP_TRY(launch_update(h->kp, h->k1_blocks, h->stream));
+      HIP_TRY(launch_route(h->kp, mode, h->stream));
+      HIP_TRY(launch_deliver(h->kp, mode, h->stream));
+    }
+  } else {
+    if (!h->graph[mode]) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e1 = launch_update(h->kp, h->k1_blocks, h->stream);
+      hipError_t e2 = e1 == hipSuccess ? launch_route(h->kp, mode, h->stream) : e1;
+      hipError_t e3 = e2 == hipSuccess ? launch_deliver(h->kp, mode, h->stream) : e2;
+      hipError_t ec = hipStreamEndCapture(h->stream, &g);
+      if (e3 != hipSuccess || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(SNN_ERR_HIP, "graph capture failed: %s",
+                    hipGetErrorString(e3 != hipSuccess ? e3 : ec));
+      }
+      hipError_t ei = hipGraphInstantiate(&h->graph[mode], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        h->graph[mode] = nullptr;
+        return fail(SNN_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+      }
+    }
+    for (uint32_t i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(h->graph[mode], h->stream));
+  }
+  h->route_mode = mode;
+  h->t_host += n_steps;
+  h->routed_t = h->t_host;
+  return SNN_OK;
+}
+
+static snn_status sync_and_check(snn_handle h) {
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  DevState st;
+  HIP_TRY(hipMemcpy(&st, h->kp.st, sizeof(st), hipMemcpyDeviceToHost));
+  if (st.error & ERR_ROUTE)
+    return fail(SNN_ERR_HIP, "receive entry without a matching destination partition");
+  if (st.error)
+    return fail(SNN_ERR_CAPACITY, "device capacity overflow (bits 0x%x: 1 bucket, 2 receive "
+                "list, 4 flat list, 8 spike log)", st.error);
+  return SNN_OK;
+}
+
+snn_status snn_sync(snn_handle h) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  return sync_and_check(h);
+}
+
+uint64_t snn_time(snn_handle h) { return h ? h->t_host : 0; }
+
+snn_status snn_read_counters(snn_handle h, uint64_t first_step, uint32_t n_steps, uint64_t* out) {
+  if (!h || (!out && n_steps)) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  const uint64_t L = h->prm.log_steps;
+  if (first_step + n_steps > h->t_host || first_step + L < h->t_host)
+    return fail(SNN_ERR_INVALID_ARG, "steps [%llu, %llu) not among the last %llu of %llu",
+                (unsigned long long)first_step, (unsigned long long)(first_step + n_steps),
+                (unsigned long long)L, (unsigned long long)h->t_host);
+  if (n_steps > L) return fail(SNN_ERR_INVALID_ARG, "n_steps exceeds log_steps");
+  snn_status s = sync_and_check(h);
+  if (s != SNN_OK && s != SNN_ERR_CAPACITY) return s;
+  std::vector<uint64_t> all(SNN_NSTAT * L);
+  HIP_TRY(hipMemcpy(all.data(), h->kp.stats, all.size() * 8, hipMemcpyDeviceToHost));
+  for (uint32_t i = 0; i < n_steps; ++i)
+    std::memcpy(out + uint64_t(i) * SNN_NSTAT, all.data() + ((first_step + i) % L) * SNN_NSTAT,
+                SNN_NSTAT * 8);
+  return s;
+}
+
+snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps, int32_t* ids,
+                           uint64_t cap, uint32_t* per_step_counts, uint64_t* n_ids) {
+  if (!h || !n_ids) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  *n_ids = 0;
+  const uint64_t L = h->prm.log_steps;
+  if (first_step + n_steps > h->t_host || first_step + L < h->t_host || n_steps > L)
+    return fail(SNN_ERR_INVALID_ARG, "steps [%llu, %llu) not among the last %llu of %llu",
+                (unsigned long long)first_step, (unsigned long long)(first_step + n_steps),
+                (unsigned long long)L, (unsigned long long)h->t_host);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  DevState st;
+  HIP_TRY(hipMemcpy(&st, h->kp.st, sizeof(st), hipMemcpyDeviceToHost));
+  std::vector<uint64_t> stats(SNN_NSTAT * L), offs(L);
+  HIP_TRY(hipMemcpy(stats.data(), h->kp.stats, stats.size() * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(offs.data(), h->kp.log_off, offs.size() * 8, hipMemcpyDeviceToHost));
+  const uint64_t logcap = h->prm.log_cap;
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < n_steps; ++i) {
+    const uint64_t r = (first_step + i) % L;
+    const uint64_t cnt = stats[r * SNN_NSTAT + SNN_STAT_SPIKES];
+    if (per_step_counts) per_step_counts[i] = uint32_t(cnt);
+    // still in the log ring?
+    if (cnt && (logcap == 0 || st.log_total - offs[r] > logcap))
+      return fail(SNN_ERR_CAPACITY, "spikes of step %llu are no longer in the spike log",
+                  (unsigned long long)(first_step + i));
+    total += cnt;
+  }
+  *n_ids = total;
+  if (!ids) return SNN_OK;
+  if (total > cap) return fail(SNN_ERR_CAPACITY, "%llu ids do not fit cap %llu",
+                               (unsigned long long)total, (unsigned long long)cap);
+  uint64_t at = 0;
+  for (uint32_t i = 0; i < n_steps; ++i) {
+    const uint64_t r = (first_step + i) % L;
+    uint64_t cnt = stats[r * SNN_NSTAT + SNN_STAT_SPIKES];
+    if (!cnt) continue;
+    uint64_t pos = offs[r] % logcap;
+    while (cnt) {
+      const uint64_t piece = std::min(cnt, logcap - pos);
+      HIP_TRY(hipMemcpy(ids + at, h->kp.log + pos, piece * 4, hipMemcpyDeviceToHost));
+      at += piece;
+      cnt -= piece;
+      pos = 0;
+    }
+  }
+  return SNN_OK;
+}
+
+snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entries, uint64_t cap,
+                           uint64_t* n_entries) {
+  if (!h || !sizes || !n_entries) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  if (which < 0 || which > 2) return fail(SNN_ERR_INVALID_ARG, "which=%d", which);
+  if (!h->routed_t) return fail(SNN_ERR_BAD_STATE, "no step has been routed yet");
+  const int mode = h->route_mode;
+  if ((which == 0 && mode == SNN_ROUTE_TWO_LEVEL) || (which != 0 && mode == SNN_ROUTE_FLAT))
+    return fail(SNN_ERR_BAD_STATE, "the last step was not routed in a mode that fills these buffers");
+  snn_status s = sync_and_check(h);
+  if (s != SNN_OK) return s;
+  const uint32_t nl = which == 2 ? h->kp.n_nodes : h->kp.P;
+  std::vector<uint32_t> cnt(nl);
+  std::vector<uint64_t> off(nl + 1);
+  const uint32_t* cnt_dev = which == 0 ? h->kp.flat_cnt : which == 1 ? h->kp.recv_cnt : h->kp.bucket_cnt;
+  const uint64_t* off_dev = which == 2 ? h->kp.bucket_off : h->kp.recv_off;
+  HIP_TRY(hipMemcpy(cnt.data(), cnt_dev, nl * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(off.data(), off_dev, (nl + 1) * 8, hipMemcpyDeviceToHost));
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < nl; ++i) {
+    sizes[i] = cnt[i];
+    total += cnt[i];
+  }
+  *n_entries = total;
+  if (!entries) return SNN_OK;
+  if (total > cap) return fail(SNN_ERR_CAPACITY, "%llu entries do not fit cap %llu",
+                               (unsigned long long)total, (unsigned long long)cap);
+  const size_t el = which == 2 ? 8 : 4;
+  const char* base = which == 0 ? reinterpret_cast<const char*>(h->kp.flat)
+                     : which == 1 ? reinterpret_cast<const char*>(h->kp.recv)
+                                  : reinterpret_cast<const char*>(h->kp.bucket);
+  uint64_t at = 0;
+  for (uint32_t i = 0; i < nl; ++i) {
+    if (!cnt[i]) continue;
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(entries) + at * el, base + off[i] * el, cnt[i] * el,
+                           hipMemcpyDeviceToHost, h->stream));
+    at += cnt[i];
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return SNN_OK;
+}
+
+snn_status snn_destroy(snn_handle h) {
+  if (!h) return SNN_OK;
+  snn_status s = SNN_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) s = fail(SNN_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  for (auto& g : h->graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  delete h;
+  return s;
+}
+
+}  // extern "C"

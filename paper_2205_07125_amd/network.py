@@ -1,0 +1,104 @@
+"""Host setup of a workload's network through libsnn's setup entry points,
+then upload to device memory (torch tensors, caller-owned by the
+Simulation)."""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+
+import numpy as np
+
+from . import _abi
+
+_P = ctypes.c_void_p
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+def derived_params(wl) -> dict:
+    """Constants the kernels take ready-made: the per-step decay factor
+    fl32(exp(-dt / tau_m)), the Poisson inversion table floor(2^32 CDF(j))
+    for lambda = nu_ext dt, the refractory length and the forced-raster
+    thresholds floor(2^32 rate dt)."""
+    alpha = np.float32(math.exp(-wl.dt_ms / wl.tau_m_ms))
+    lam = wl.nu_ext_hz * wl.dt_ms * 1e-3
+    thr = []
+    pmf, cdf = math.exp(-lam), 0.0
+    for j in range(15):
+        if j:
+            pmf = pmf * lam / j
+        cdf += pmf
+        thr.append(min(int(math.floor(math.ldexp(cdf, 32))), 2**32 - 1))
+
+    def raster(rate_hz):
+        v = math.floor(math.ldexp(rate_hz * wl.dt_ms * 1e-3, 32))
+        return max(0, min(v, 2**32 - 1))
+
+    return dict(alpha=float(alpha), theta=float(np.float32(wl.theta_rel_mv)),
+                u_reset=float(np.float32(wl.u_reset_mv)), w_ext=float(np.float32(wl.w_ext_mv)),
+                n_ref=int(round(wl.t_ref_ms / wl.dt_ms)), poisson_thr=thr,
+                raster_thr_on=raster(wl.rate_on_hz), raster_thr_off=raster(wl.rate_off_hz))
+
+
+class HostNetwork:
+    """Arrays of include/snn.h's snn_network_dev, built on the host."""
+
+    def __init__(self, wl, n_threads: int = 0, verbose: bool = False):
+        import synth  # seeded input description (partition starts, cross fractions)
+        self.wl = wl
+        L = _abi.lib()
+        spec = _abi.snn_setup_spec(
+            seed=wl.seed, n_neurons=wl.n_neurons, k_in=wl.k_in, max_delay=wl.max_delay,
+            n_partitions=wl.n_partitions, topology=wl.topology, vp_set_size=wl.vp_set_size,
+            remote_frac=wl.remote_frac, w_exc=wl.w_exc, w_inh=wl.w_inh, w_jitter=wl.w_jitter,
+            gpus_per_node=wl.gpus_per_node,
+            weight_type=_abi.SNN_W_BF16 if wl.weight_type == "bf16" else _abi.SNN_W_FP32,
+            n_threads=n_threads)
+        starts = synth.partition_starts(wl)
+        fracs = synth.cross_fracs(wl)
+        h = _P()
+        t0 = time.time()
+        _abi.check(L.snn_setup_create(ctypes.byref(spec), None if starts is None else _ptr(starts),
+                                      None if fracs is None else _ptr(fracs), ctypes.byref(h)))
+        try:
+            sizes = [ctypes.c_uint64() for _ in range(4)]
+            _abi.check(L.snn_setup_sizes(h, *[ctypes.byref(s) for s in sizes]))
+            nnz = sizes[0].value
+            N = wl.n_neurons
+            if verbose:
+                print(f"[setup] {wl.name}: counted {nnz:,} synapses in {time.time() - t0:.1f}s",
+                      flush=True)
+            self.row_ptr = np.empty(N + 1, np.int64)
+            self.n_local = np.empty(N, np.uint32)
+            self.tgt_delay = np.empty(nnz, np.uint32)
+            self.weight = np.empty(nnz, np.uint16 if wl.weight_type == "bf16" else np.float32)
+            t1 = time.time()
+            _abi.check(L.snn_setup_fill_rows(h, _ptr(self.row_ptr), _ptr(self.n_local),
+                                             _ptr(self.tgt_delay), _ptr(self.weight)))
+            _abi.check(L.snn_setup_sizes(h, *[ctypes.byref(s) for s in sizes]))
+            pairs, self.bucket_total, self.recv_total = (s.value for s in sizes[1:])
+            if verbose:
+                print(f"[setup] rows placed and sorted in {time.time() - t1:.1f}s; "
+                      f"{pairs:,} destination pairs", flush=True)
+            n_nodes = wl.n_nodes
+            self.vp_ptr = np.empty(N + 1, np.int64)
+            self.vp_part = np.empty(max(pairs, 1), np.uint16)
+            self.vp_seg = np.empty(max(pairs, 1), np.uint32)
+            self.part = np.empty(N, np.int32)
+            self.bucket_off = np.empty(n_nodes + 1, np.uint64)
+            self.recv_off = np.empty(wl.n_partitions + 1, np.uint64)
+            _abi.check(L.snn_setup_fill_routes(h, _ptr(self.vp_ptr), _ptr(self.vp_part),
+                                               _ptr(self.vp_seg), _ptr(self.part),
+                                               _ptr(self.bucket_off), _ptr(self.recv_off)))
+        finally:
+            L.snn_setup_destroy(h)
+        self.nnz, self.pairs = nnz, pairs
+        self.setup_seconds = time.time() - t0
+
+    def host_bytes(self) -> int:
+        return sum(a.nbytes for a in (self.row_ptr, self.n_local, self.tgt_delay, self.weight,
+                                      self.vp_ptr, self.vp_part, self.vp_seg, self.part,
+                                      self.bucket_off, self.recv_off))

@@ -1,0 +1,105 @@
+"""The C ABI library loads, exports every entry point the headers declare,
+and rejects invalid arguments on the host (no kernel is launched)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2205_07125_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in ("snn.h", "snn_setup.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(snn_[a-z_0-9]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.lib()
+    declared = _declared()
+    assert {"snn_create", "snn_step", "snn_route", "snn_deliver", "snn_read_spikes"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(_abi.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (snn_[a-z_0-9]+)", out))
+    assert declared <= exported
+
+
+def test_library_has_gfx950_code():
+    blob = open(_abi.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob
+
+
+def _params(**kw):
+    p = _abi.snn_params(n_neurons=1000, n_partitions=8, gpus_per_node=4, max_delay=10,
+                        alpha=0.995, theta=15.0, u_reset=0.0, w_ext=0.1, n_ref=20, seed=1,
+                        raster_period=1, bucket_total=100, recv_total=100, log_steps=10,
+                        log_cap=1000)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_workspace_size_and_ring_stride():
+    assert _abi.snn_ring_stride(1) == 256 and _abi.snn_ring_stride(256) == 256
+    assert _abi.snn_ring_stride(5_000_000) % 256 == 0
+    a = _abi.snn_workspace_size(_params())
+    b = _abi.snn_workspace_size(_params(recv_total=10_000))
+    assert b - a >= 2 * 4 * 9_900   # flat and expanded lists
+    assert a % 256 == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_neurons", 0), ("n_neurons", (1 << 27) + 1), ("n_partitions", 0),
+    ("n_partitions", 65536), ("gpus_per_node", 0), ("gpus_per_node", 9), ("max_delay", 0),
+    ("max_delay", 16), ("n_ref", 256), ("weight_type", 2), ("flags", 2), ("log_steps", 0),
+])
+def test_invalid_params_rejected(field, value):
+    with pytest.raises(_abi.SNNError) as ei:
+        _abi.snn_workspace_size(_params(**{field: value}))
+    assert ei.value.status == _abi.SNN_ERR_INVALID_ARG
+    assert _abi.snn_last_error()
+
+
+def test_nonmonotone_poisson_table_rejected():
+    p = _params()
+    p.poisson_thr[3] = 10
+    p.poisson_thr[4] = 5
+    with pytest.raises(_abi.SNNError):
+        _abi.snn_workspace_size(p)
+
+
+def test_create_rejects_null_arrays_and_bad_workspace():
+    p = _params()
+    net = _abi.snn_network_dev()
+    with pytest.raises(_abi.SNNError) as ei:
+        _abi.snn_create(p, net, 0, 0, 0)
+    assert ei.value.status == _abi.SNN_ERR_INVALID_ARG
+    assert "row_ptr" in _abi.snn_last_error()
+    # every array present (fake, never dereferenced), workspace misaligned
+    fake = {n: 4096 * (i + 1) for i, (n, _) in enumerate(_abi.snn_network_dev._fields_)}
+    net = _abi.snn_network_dev(**fake)
+    with pytest.raises(_abi.SNNError) as ei:
+        _abi.snn_create(p, net, 4096 + 8, 1 << 30, 0)
+    assert "aligned" in _abi.snn_last_error()
+    with pytest.raises(_abi.SNNError):
+        _abi.snn_create(p, net, 4096, 16, 0)   # too small
+
+
+def test_null_handle_calls():
+    L = _abi.lib()
+    assert L.snn_step(None) == _abi.SNN_ERR_INVALID_ARG
+    assert L.snn_route(None, 0) == _abi.SNN_ERR_INVALID_ARG
+    assert L.snn_deliver(None) == _abi.SNN_ERR_INVALID_ARG
+    assert L.snn_destroy(None) == _abi.SNN_OK
+    n = ctypes.c_uint64()
+    assert L.snn_read_spikes(None, 0, 1, None, 0, None, ctypes.byref(n)) == _abi.SNN_ERR_INVALID_ARG

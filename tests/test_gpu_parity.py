@@ -1,0 +1,159 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by
+element on the same seeded inputs: fired ids, routing buffers (as sorted
+multisets per bucket / list), per-step counters, and the full state (u, ref,
+delay ring) bit-exactly; the FP64 trajectory within 1e-4 mV."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ROUTE_BOTH = 2
+ROUTE_TWO_LEVEL = 0
+ROUTE_FLAT = 1
+
+# oracle counter order -> device counter order (both list the same 7 counters)
+STAT_MAP = [oracle.SPIKES, oracle.LOCAL_EVENTS, oracle.REMOTE_EVENTS, oracle.MSG_L1,
+            oracle.MSG_L2, oracle.FLAT_MSGS, oracle.RECV_ENTRIES]
+
+
+def _pair(wl, **simkw):
+    from paper_2205_07125_amd import Simulation
+    print(f"[gpu] building {wl.name} N={wl.n_neurons} K={wl.k_in}", flush=True)
+    sim = Simulation(wl, **simkw)
+    orc = oracle.sim_for_workload(wl)
+    return sim, orc
+
+
+def _same_state(sim, orc, where):
+    g = sim.state()
+    o = orc.state()
+    assert np.array_equal(g["u"].view(np.uint32), o["u"].view(np.uint32)), f"u differs at {where}"
+    assert np.array_equal(g["ref"], o["ref"]), f"ref differs at {where}"
+    assert np.array_equal(g["ring"].view(np.uint32), o["ring"].view(np.uint32)), \
+        f"ring differs at {where}"
+    return g, o
+
+
+def _same_routes(sim, orc, wl, where):
+    flat_g, x_g, b_g = sim.read_routes(0), sim.read_routes(1), sim.read_routes(2)
+    flat_o, x_o, b_o = orc.recv(0), orc.recv(1), orc.buckets()
+    for p in range(wl.n_partitions):
+        assert np.array_equal(np.sort(flat_g[p]), np.sort(flat_o[p])), f"flat {p} at {where}"
+        assert np.array_equal(np.sort(x_g[p]), np.sort(x_o[p])), f"expanded {p} at {where}"
+    for n in range(wl.n_nodes):
+        # device messages carry an implementation index above bit 40
+        g = np.sort(b_g[n] & np.uint64((1 << 40) - 1))
+        assert np.array_equal(g, np.sort(b_o[n])), f"bucket {n} at {where}"
+
+
+def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH):
+    sim, orc = _pair(wl, log_steps=n_steps)
+    stats_o = np.zeros((n_steps, 7), np.uint64)
+    fired_o = []
+    for t in range(n_steps):
+        sim.full_step(mode)
+        orc.step()
+        fired_o.append(orc.fired())
+        stats_o[t] = orc.counters()[STAT_MAP]
+        if route_every and t % route_every == 0:
+            _same_routes(sim, orc, wl, f"step {t}")
+        if state_every and (t + 1) % state_every == 0:
+            _same_state(sim, orc, f"after step {t}")
+    ids, counts = sim.read_spikes(0, n_steps)
+    assert np.array_equal(counts, np.array([len(f) for f in fired_o], np.uint32))
+    assert np.array_equal(ids, np.concatenate(fired_o).astype(np.int32))
+    stats_g = sim.read_counters(0, n_steps)
+    if mode == ROUTE_TWO_LEVEL:
+        stats_o[:, 5] = 0          # flat entries are only counted when flat routing runs
+    if mode == ROUTE_FLAT:
+        stats_o[:, 3:5] = 0
+        stats_o[:, 6] = 0
+    assert np.array_equal(stats_g, stats_o)
+    g, o = _same_state(sim, orc, "end")
+    # FP64 trajectory: device u within 1e-4 mV while the rasters agree
+    acc = orc.accuracy()
+    if acc["first_divergence"] < 0:
+        assert np.max(np.abs(g["u"].astype(np.float64) - o["u64"])) < 1e-4
+    assert acc["max_dv"] < 1e-4
+    return sim, orc, stats_o
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("name", ["tiny", "tiny_active"])
+def test_tiny_lockstep_1000_steps(name, seed):
+    wl = synth.get_workload(name).replace(seed=seed)
+    _, _, stats = _lockstep(wl, 1000, route_every=25, state_every=100)
+    spikes = int(stats[:, 0].sum())
+    print(f"[gpu] {name} seed {seed}: {spikes} spikes", flush=True)
+    assert spikes > (10_000 if name == "tiny_active" else 100)
+
+
+def test_route_modes_give_identical_rasters():
+    wl = synth.get_workload("tiny_active")
+    from paper_2205_07125_amd import Simulation
+    a = Simulation(wl, log_steps=400)
+    b = Simulation(wl, log_steps=400)
+    for _ in range(400):
+        a.full_step(ROUTE_TWO_LEVEL)
+        b.full_step(ROUTE_FLAT)
+    ia, ca = a.read_spikes(0, 400)
+    ib, cb = b.read_spikes(0, 400)
+    assert np.array_equal(ia, ib) and np.array_equal(ca, cb)
+    sa, sb = a.state(), b.state()
+    for k in ("u", "ref", "ring"):
+        assert np.array_equal(sa[k], sb[k])
+    ka, kb = a.read_counters(0, 400), b.read_counters(0, 400)
+    # same deliveries; two-level sends fewer messages than flat
+    assert np.array_equal(ka[:, :3], kb[:, :3])
+    assert np.array_equal(ka[:, 6], kb[:, 5])           # expanded entries = flat entries
+    assert np.all(ka[:, 3] + ka[:, 4] <= kb[:, 5])
+
+
+def test_graph_replay_matches_oracle():
+    """snn_run with a captured step replayed 300 times equals the oracle."""
+    wl = synth.get_workload("tiny_active").replace(seed=7)
+    sim, orc = _pair(wl, log_steps=300)
+    sim.run(150, ROUTE_TWO_LEVEL, use_graph=True)
+    sim.sync()
+    counts_o, stats_o = orc.run(150)
+    _same_state(sim, orc, "after 150 graph steps")
+    sim.run(150, ROUTE_FLAT, use_graph=True)
+    c2, s2 = orc.run(150)
+    _same_state(sim, orc, "after 300 graph steps")
+    ids, counts = sim.read_spikes(0, 300)
+    assert np.array_equal(counts, np.concatenate([counts_o, c2]))
+    st = sim.read_counters(0, 300)
+    assert np.array_equal(st[:, :3], np.concatenate([stats_o, s2])[:, STAT_MAP][:, :3])
+
+
+def test_graph_and_eager_agree():
+    wl = synth.get_workload("tiny_active").replace(seed=9)
+    from paper_2205_07125_amd import Simulation
+    a = Simulation(wl, log_steps=200)
+    b = Simulation(wl, log_steps=200)
+    a.run(200, ROUTE_TWO_LEVEL, use_graph=True)
+    b.run(200, ROUTE_TWO_LEVEL, use_graph=False)
+    sa, sb = a.state(), b.state()
+    for k in ("u", "ref", "ring"):
+        assert np.array_equal(sa[k], sb[k])
+
+
+def test_bf16_weights_identical_for_dyadic():
+    wl = synth.get_workload("tiny_active")
+    from paper_2205_07125_amd import Simulation
+    a = Simulation(wl, log_steps=300)
+    b = Simulation(wl.replace(weight_type="bf16"), log_steps=300)
+    a.run(300, ROUTE_TWO_LEVEL, use_graph=False)
+    b.run(300, ROUTE_TWO_LEVEL, use_graph=False)
+    sa, sb = a.state(), b.state()
+    for k in ("u", "ref", "ring"):
+        assert np.array_equal(sa[k], sb[k])
+
+
+def test_forced_raster_matches_oracle():
+    wl = synth.get_workload("heavy").scaled(3000, k_in=300, vp_set_size=40, period_steps=50,
+                                            on_steps=10)
+    _lockstep(wl, 120, route_every=10, state_every=40)

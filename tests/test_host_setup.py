@@ -1,0 +1,105 @@
+"""The GPU path's host setup (libsnn's snn_setup_* entry points) against the
+seeded generator's synapse list, and its derived constants against the
+oracle's.  CPU only: no kernel runs here."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2205_07125_amd import HostNetwork, derived_params
+
+
+def _check_network(wl, host):
+    """Vectorised comparison of the CSR layout with the canonical list."""
+    gen = synth.Generator(wl)
+    e = gen.edges()
+    part = gen.part_map().astype(np.int64)
+    N, G, P = wl.n_neurons, wl.gpus_per_node, wl.n_partitions
+    assert np.array_equal(host.part, part)
+    row_ptr = host.row_ptr
+    row_len = np.diff(row_ptr)
+    assert np.array_equal(row_len, np.bincount(e["src"], minlength=N))
+    nnz = int(row_ptr[-1])
+    src_h = np.repeat(np.arange(N), row_len)
+    pos = np.arange(nnz) - row_ptr[src_h]
+    nl = host.n_local.astype(np.int64)
+    local = pos < nl[src_h]
+    # destination-partition lists: distinct, ascending, never the own partition
+    vp_ptr = host.vp_ptr
+    n_vp = np.diff(vp_ptr)
+    pairs = int(vp_ptr[-1])
+    assert host.pairs == pairs
+    vp_part = host.vp_part[:pairs].astype(np.int64)
+    vp_seg = host.vp_seg[:pairs].astype(np.int64)
+    owner = np.repeat(np.arange(N), n_vp)
+    first = np.zeros(pairs, bool)
+    first[vp_ptr[:-1][n_vp > 0]] = True
+    assert np.all(vp_part != part[owner])
+    assert np.all(np.diff(vp_part)[~first[1:]] > 0)          # ascending within a source
+    assert np.all(vp_seg[first] == nl[owner[first]])          # segments follow the local part
+    seg_end = np.append(vp_seg[1:], 0)
+    last = np.append(~first[1:], False) == False               # noqa: E712
+    seg_end[last] = row_len[owner[last]]
+    seg_len = seg_end - vp_seg
+    assert np.all(seg_len > 0)
+    assert seg_len.sum() == (~local).sum()
+    vp_h = np.empty(nnz, np.int64)
+    vp_h[local] = part[src_h[local]]
+    vp_h[~local] = np.repeat(vp_part, seg_len)
+    # same multiset of synapses as the generator
+    tgt_h = (host.tgt_delay & 0x07FFFFFF).astype(np.int64)
+    d_h = (host.tgt_delay >> 27).astype(np.int64)
+    if wl.weight_type == "bf16":
+        import torch
+        w_h = host.weight.astype(np.uint32) << 16
+        w_g = torch.from_numpy(e["w"]).to(torch.bfloat16).to(torch.float32).numpy().view(np.uint32)
+    else:
+        w_h = host.weight.view(np.uint32)
+        w_g = e["w"].view(np.uint32)
+    a = np.stack([src_h, vp_h, tgt_h, d_h, w_h.astype(np.int64)])
+    b = np.stack([e["src"], e["vp"], e["tgt"], e["delay"], w_g]).astype(np.int64)
+    a = a[:, np.lexsort(a[::-1])]
+    b = b[:, np.lexsort(b[::-1])]
+    assert np.array_equal(a, b)
+    # local segment = exactly the synapses whose destination is the own partition
+    assert np.array_equal(local, vp_h == part[src_h])
+    # exact capacity bounds: sources per destination partition / per node
+    assert np.array_equal(np.diff(host.recv_off.astype(np.int64)), np.bincount(vp_part, minlength=P))
+    node_pairs = np.unique(owner * (P // G + 1) + vp_part // G)
+    assert np.array_equal(np.diff(host.bucket_off.astype(np.int64)),
+                          np.bincount(node_pairs % (P // G + 1), minlength=wl.n_nodes))
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_bf16", "loopback_small", "sets_small",
+                                  "batched_small"])
+def test_setup_matches_generator(name):
+    base = {
+        "tiny": synth.get_workload("tiny"),
+        "tiny_bf16": synth.get_workload("tiny").replace(weight_type="bf16", w_jitter=0.2),
+        "loopback_small": synth.get_workload("paper_share").scaled(3000, k_in=60),
+        "sets_small": synth.get_workload("heavy").scaled(1500, k_in=200, vp_set_size=30),
+        "batched_small": synth.get_workload("batched").scaled(3000),
+    }[name]
+    host = HostNetwork(base, n_threads=4)
+    _check_network(base, host)
+
+
+def test_setup_independent_of_threads():
+    wl = synth.get_workload("paper_share").scaled(4000, k_in=50)
+    a = HostNetwork(wl, n_threads=1)
+    b = HostNetwork(wl, n_threads=7)
+    for k in ("row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_seg",
+              "bucket_off", "recv_off"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+
+
+@pytest.mark.parametrize("name", ["tiny", "paper_share", "heavy"])
+def test_derived_params_match_oracle(name):
+    wl = synth.get_workload(name)
+    dp = derived_params(wl)
+    p = oracle.params_from_workload(wl)
+    assert np.float32(dp["alpha"]) == oracle.alpha(p)
+    assert list(dp["poisson_thr"]) == list(oracle.poisson_table(wl.nu_ext_hz * wl.dt_ms * 1e-3))
+    assert dp["n_ref"] == oracle.n_ref(p)
+    assert dp["raster_thr_on"] == oracle.raster_threshold(wl.rate_on_hz, wl.dt_ms)
+    assert dp["raster_thr_off"] == oracle.raster_threshold(wl.rate_off_hz, wl.dt_ms)
