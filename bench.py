@@ -1,0 +1,228 @@
+"""Benchmark of one GPU's share of the simulation step on an MI355X.
+
+One step = neuron update + compaction, routing (two-level by default, with
+mask expansion) and synaptic delivery, over the 5e6-neuron / in-degree-1,000
+share with 2,000 virtual partitions on 250 nodes of 8 (synthetic, seeded).
+The network is built and uploaded before timing; the timed region is K whole
+steps replayed from a HIP graph, bracketed by device synchronisation.
+
+Prints one JSON line on stdout (progress goes to stderr):
+  value     synaptic events/s (local + remote deliveries over the timed steps)
+  roofline  the dominant kernel's algorithmic HBM bytes / its average duration,
+            measured with HIP events on the simulation stream
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the same
+            workload structure
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("snn_kernels.hip", "snn_internal.h"):
+        with open(os.path.join(ROOT, "paper_2205_07125_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def phase_times(sim, steps, mode, torch):
+    """Average duration (ms) of the update, route and deliver phases, each
+    bracketed by HIP events on the simulation stream (eager launches)."""
+    s = sim.stream
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for i in range(steps):
+        ev[i][0].record(s)
+        sim.step()
+        ev[i][1].record(s)
+        sim.route(mode)
+        ev[i][2].record(s)
+        sim.deliver()
+        ev[i][3].record(s)
+    s.synchronize()
+    tot = [0.0, 0.0, 0.0]
+    for i in range(steps):
+        for k in range(3):
+            tot[k] += ev[i][k].elapsed_time(ev[i][k + 1])
+    return [x / steps for x in tot]
+
+
+def cpu_baseline(wl_full, seconds_budget=20.0):
+    """The oracle (single-threaded C, FP64 + binary32 trajectories) on the same
+    structure at 1/100 of the neurons (same in-degree, partitions, rate)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    n = max(wl_full.n_neurons // 100, 1000)
+    wl = wl_full.scaled(n)
+    gen = synth.Generator(wl)
+    sim = oracle.Sim(oracle.params_from_workload(wl), gen.edges(), gen.part_map(),
+                     synth.initial_u(wl))
+    sim.run(20)  # warm
+    steps, t0 = 0, time.perf_counter()
+    events = 0
+    while time.perf_counter() - t0 < seconds_budget:
+        c, st = sim.run(50)
+        steps += 50
+        events += int(st[:, oracle.LOCAL_EVENTS].sum() + st[:, oracle.REMOTE_EVENTS].sum())
+    dt = time.perf_counter() - t0
+    return dict(value=events / dt, unit="synaptic events/s", cores=1, kind="oracle",
+                sample=f"{wl_full.name} structure at {n:,} neurons (1/100), K={wl.k_in}, "
+                       f"{steps} steps, {events:,} events, {dt:.1f} s single-threaded; "
+                       f"ms/step {1e3 * dt / steps:.2f}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="paper_share")
+    ap.add_argument("--mode", choices=["two_level", "flat"], default="two_level")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phase-steps", type=int, default=100)
+    ap.add_argument("--neurons", type=int, default=0,
+                    help="run the workload's structure at this many neurons (quick checks)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs one GPU's share on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU exchange is design only in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2205_07125_amd import SNN_ROUTE_FLAT, SNN_ROUTE_TWO_LEVEL, HostNetwork, Simulation
+    from paper_2205_07125_amd.sim import Simulation as _Sim  # noqa: F401
+
+    mode = SNN_ROUTE_TWO_LEVEL if args.mode == "two_level" else SNN_ROUTE_FLAT
+    wl = synth.get_workload(args.workload)
+    if args.neurons:
+        wl = wl.scaled(args.neurons)
+    log(f"workload {wl.name}: N={wl.n_neurons:,} K={wl.k_in} P={wl.n_partitions} "
+        f"G={wl.gpus_per_node} weights={wl.weight_type}")
+    t0 = time.time()
+    host = HostNetwork(wl, verbose=True)
+    log(f"host setup {time.time() - t0:.1f}s, {host.host_bytes() / 1e9:.1f} GB")
+    total_steps = args.warmup + args.steps + args.phase_steps
+    t1 = time.time()
+    sim = Simulation(wl, host=host, log_steps=total_steps,
+                     log_cap=int(wl.n_neurons * max(wl.rate_on_hz, 50.0) * wl.dt_ms * 1e-3 * 4
+                                 * total_steps) + (1 << 20))
+    nnz = host.nnz
+    del host
+    sim.host = None
+    log(f"device upload {time.time() - t1:.1f}s")
+
+    use_graph = not args.no_graph
+    sim.run(args.warmup, mode, use_graph)
+    sim.sync()
+    torch.cuda.synchronize()
+    s = sim.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(s)
+    sim.run(args.steps, mode, use_graph)
+    e1.record(s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    sim.sync()
+    cnt = sim.read_counters(args.warmup, args.steps).astype(np.float64)
+    sec = ms / 1e3
+    spikes = cnt[:, 0].sum()
+    events = cnt[:, 1].sum() + cnt[:, 2].sum()
+    msgs = cnt[:, 3].sum() + cnt[:, 4].sum()
+    flat = cnt[:, 5].sum()
+    entries = cnt[:, 6].sum() if mode == SNN_ROUTE_TWO_LEVEL else flat
+    log(f"timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), "
+        f"{spikes / args.steps:.0f} spikes/step, {events / args.steps:,.0f} events/step")
+
+    # per-phase breakdown, eager launches bracketed by events on the stream
+    ph = phase_times(sim, args.phase_steps, mode, torch)
+    pc = sim.read_counters(args.warmup + args.steps, args.phase_steps).astype(np.float64)
+    log(f"phases (ms/step): update {ph[0]:.4f}  route {ph[1]:.4f}  deliver {ph[2]:.4f}")
+    N = wl.n_neurons
+    bw = 2 if wl.weight_type == "bf16" else 4
+    ph_events = (pc[:, 1].sum() + pc[:, 2].sum()) / args.phase_steps
+    # algorithmic bytes per launch:
+    #   update: ring slot read + clear (8), u read + write (8), ref read + write (2)
+    #   deliver: CSR target+delay (4) and weight (bw) per delivered synapse
+    bytes_update = 18.0 * N
+    bytes_deliver = ph_events * (4 + bw)
+    cand = {
+        "update": (bytes_update, ph[0]),
+        "deliver": (bytes_deliver, ph[2]),
+    }
+    dom = max(cand, key=lambda k: cand[k][1])
+    b, t_ms = cand[dom]
+    achieved = b / (t_ms * 1e-3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            tj = json.load(fh)
+        ent = tj.get(wl.name, {}).get(dom)
+        if ent and ent.get("kernel_hash") == kernel_source_hash():
+            traffic = ent.get("bytes_per_launch")
+    step_bytes = bytes_update + (events / args.steps) * (4 + bw)
+    out = {
+        "metric": "synaptic events/s + routed spike msgs/s per GPU; % of HBM peak BW",
+        "value": events / sec,
+        "unit": "synaptic events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl.weight_type == "fp32" else "bf16 weights, f32 accumulate",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_neurons": N, "in_degree": wl.k_in,
+                   "partitions": wl.n_partitions, "gpus_per_node": wl.gpus_per_node,
+                   "remote_frac": wl.remote_frac, "rate_hz": wl.rate_on_hz if wl.forced else None,
+                   "route": args.mode, "graph": use_graph, "synapses": int(nnz)},
+        "routed_msgs_per_s": (msgs if mode == SNN_ROUTE_TWO_LEVEL else flat) / sec,
+        "recv_entries_per_s": entries / sec,
+        "spikes_per_step": spikes / args.steps,
+        "events_per_step": events / args.steps,
+        "msgs_per_step": {"two_level_l1": cnt[:, 3].sum() / args.steps,
+                          "two_level_l2": cnt[:, 4].sum() / args.steps,
+                          "flat": flat / args.steps},
+        "hbm_frac_step": step_bytes / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "phase_ms": {"update": ph[0], "route": ph[1], "deliver": ph[2]},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": b, "avg_launch_ms": t_ms},
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

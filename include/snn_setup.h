@@ -53,7 +53,7 @@ typedef struct {
   uint32_t gpus_per_node;   /* 1..8 */
   uint32_t weight_type;     /* SNN_W_FP32 or SNN_W_BF16 (round to nearest even) */
   uint32_t n_threads;       /* 0: OpenMP default */
-  uint32_t reserved;
+  uint32_t verbose;         /* nonzero: progress lines on stderr during long passes */
 } snn_setup_spec;
 
 /* part_start: n_partitions+1 ascending neuron offsets for topologies 0 and 3

@@ -62,7 +62,7 @@ class snn_setup_spec(ctypes.Structure):
         ("seed", u64), ("n_neurons", u32), ("k_in", u32), ("max_delay", u32),
         ("n_partitions", u32), ("topology", u32), ("vp_set_size", u32),
         ("remote_frac", f64), ("w_exc", f64), ("w_inh", f64), ("w_jitter", f64),
-        ("gpus_per_node", u32), ("weight_type", u32), ("n_threads", u32), ("reserved", u32),
+        ("gpus_per_node", u32), ("weight_type", u32), ("n_threads", u32), ("verbose", u32),
     ]
 
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -39,6 +40,30 @@ uint16_t to_bf16(float x) {
   b += 0x7FFFu + lsb;
   return uint16_t(b >> 16);
 }
+
+// Progress lines for passes that take minutes at 5e9-1e10 synapses.
+struct Progress {
+  const char* what;
+  int64_t total;
+  bool on;
+  int64_t done = 0;
+  int next = 1;
+  Progress(const char* w, int64_t t, bool v) : what(w), total(t), on(v) {}
+  void add(int64_t n) {
+    if (!on) return;
+    const int64_t d = __atomic_add_fetch(&done, n, __ATOMIC_RELAXED);
+    const int tenth = int(10 * d / (total ? total : 1));
+    int cur = __atomic_load_n(&next, __ATOMIC_RELAXED);
+    while (tenth >= cur && cur <= 10) {
+      if (__atomic_compare_exchange_n(&next, &cur, cur + 1, false, __ATOMIC_RELAXED,
+                                      __ATOMIC_RELAXED)) {
+        std::fprintf(stderr, "[setup] %s %d%%\n", what, 10 * cur);
+        std::fflush(stderr);
+        cur += 1;
+      }
+    }
+  }
+};
 
 struct RowItem {
   uint64_t key;   // (partition tag << 32) | tgt_delay; tag 0 = own partition
@@ -110,6 +135,7 @@ snn_status snn_setup_create(const snn_setup_spec* spec, const uint32_t* part_sta
   // Pass 1: out-degree of every source.
   std::vector<uint32_t> outdeg(N, 0);
   uint32_t* od = outdeg.data();
+  Progress prog("count", N, spec->verbose != 0);
 #pragma omp parallel for num_threads(h->threads) schedule(dynamic, 256)
   for (int64_t t = 0; t < int64_t(N); ++t) {
     for (uint32_t k = 0; k < K; ++k) {
@@ -118,6 +144,7 @@ snn_status snn_setup_create(const snn_setup_spec* spec, const uint32_t* part_sta
       syn_edge(gen, uint32_t(t), k, &src, &d, &vp, &w);
       __atomic_fetch_add(od + src, 1u, __ATOMIC_RELAXED);
     }
+    if ((t & 4095) == 0) prog.add(std::min<int64_t>(4096, int64_t(N) - t));
   }
   h->row_ptr.assign(size_t(N) + 1, 0);
   for (uint32_t i = 0; i < N; ++i) h->row_ptr[i + 1] = h->row_ptr[i] + od[i];
@@ -158,8 +185,10 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
   syn_gen* gen = h->gen;
 
   // Pass 2: place every synapse in its source row (order fixed by the sort).
+  Progress prog("place", N, h->spec.verbose != 0);
 #pragma omp parallel for num_threads(h->threads) schedule(dynamic, 256)
   for (int64_t t = 0; t < int64_t(N); ++t) {
+    if ((t & 4095) == 0) prog.add(std::min<int64_t>(4096, int64_t(N) - t));
     for (uint32_t k = 0; k < K; ++k) {
       uint32_t src, d, vp;
       float w;
@@ -176,6 +205,7 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
   // per-node / per-partition capacity bounds.
   std::vector<std::vector<uint64_t>> bcap(h->threads, std::vector<uint64_t>(n_nodes, 0));
   std::vector<std::vector<uint64_t>> rcap(h->threads, std::vector<uint64_t>(P, 0));
+  Progress sprog("sort", N, h->spec.verbose != 0);
 #pragma omp parallel num_threads(h->threads)
   {
     std::vector<RowItem> items;
@@ -183,6 +213,7 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
     std::vector<uint64_t>& rc = rcap[omp_get_thread_num()];
 #pragma omp for schedule(dynamic, 256)
     for (int64_t s = 0; s < int64_t(N); ++s) {
+      if ((s & 4095) == 0) sprog.add(std::min<int64_t>(4096, int64_t(N) - s));
       const uint64_t r0 = uint64_t(h->row_ptr[s]), r1 = uint64_t(h->row_ptr[s + 1]);
       items.resize(r1 - r0);
       for (uint64_t e = r0; e < r1; ++e) {

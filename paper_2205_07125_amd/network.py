@@ -56,7 +56,7 @@ class HostNetwork:
             remote_frac=wl.remote_frac, w_exc=wl.w_exc, w_inh=wl.w_inh, w_jitter=wl.w_jitter,
             gpus_per_node=wl.gpus_per_node,
             weight_type=_abi.SNN_W_BF16 if wl.weight_type == "bf16" else _abi.SNN_W_FP32,
-            n_threads=n_threads)
+            n_threads=n_threads, verbose=1 if verbose else 0)
         starts = synth.partition_starts(wl)
         fracs = synth.cross_fracs(wl)
         h = _P()

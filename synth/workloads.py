@@ -125,10 +125,22 @@ TINY_ACTIVE = _add(TINY.replace(name="tiny_active", w_ext_mv=0.2,
 
 # One GPU's share at paper scale: 5e6 neurons, in-degree 1,000, 20 % of the
 # synapses remote over 2,000 virtual partitions on 250 nodes of 8, ~5 Hz.
+# With the stated weights (0.5 / -2.5 mV, K = 1,000) and sub-millisecond
+# delays the LIF-driven net is bistable: silent below a drive of about
+# 0.13 mV per Poisson event, synchronous bursts of >= 11 Hz above it.  The
+# 5 Hz traffic is therefore a forced Bernoulli raster (the membrane update
+# still runs and fired neurons reset).
 PAPER_SHARE = _add(Workload(
     name="paper_share", n_neurons=5_000_000, k_in=1000, n_partitions=2000, gpus_per_node=8,
-    topology=TOPO_LOOPBACK, remote_frac=0.2, seed=11, w_ext_mv=0.3,
-    description="5e6 neurons, K=1000, 2,000 virtual partitions / 250 nodes, FP32 weights"))
+    topology=TOPO_LOOPBACK, remote_frac=0.2, seed=11, w_ext_mv=0.1,
+    forced=1, rate_on_hz=5.0, rate_off_hz=5.0, period_steps=1, on_steps=1,
+    description="5e6 neurons, K=1000, 2,000 virtual partitions / 250 nodes, FP32, 5 Hz"))
+
+# The same network driven by its own dynamics (drive 0.16 mV per event):
+# bursty, about 14 Hz at 1/100 scale.
+PAPER_SHARE_LIF = _add(PAPER_SHARE.replace(
+    name="paper_share_lif", forced=0, w_ext_mv=0.16,
+    description="paper_share with LIF-driven spikes (bursty)"))
 
 PAPER_SHARE_BF16 = _add(PAPER_SHARE.replace(
     name="paper_share_bf16", weight_type="bf16",
@@ -144,7 +156,8 @@ PAPER_SHARE_JITTER = _add(PAPER_SHARE.replace(
 BATCHED = _add(Workload(
     name="batched", n_neurons=0, k_in=500, n_partitions=64, gpus_per_node=8,
     topology=TOPO_BATCHED, seed=13, size_median=70710.678, size_sigma_ln=0.9780057,
-    size_lo=10_000, size_hi=500_000, cross_lo=0.1, cross_hi=0.6, w_ext_mv=0.3,
+    size_lo=10_000, size_hi=500_000, cross_lo=0.1, cross_hi=0.6, w_ext_mv=0.1,
+    forced=1, rate_on_hz=5.0, rate_off_hz=5.0, period_steps=1, on_steps=1,
     description="64 uneven partitions (lognormal 10k-500k), K=500, 8 nodes of 8"))
 
 # Heavy-traffic routing: 1e6 neurons, in-degree 10,000, BF16 weights, every
