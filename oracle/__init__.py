@@ -97,6 +97,12 @@ def lib() -> ctypes.CDLL:
         L.orc_raster_threshold.restype = ctypes.c_uint32
         L.orc_raster_threshold.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_forced_raster.restype = ctypes.c_uint32
+        L.orc_forced_raster.argtypes = [ctypes.POINTER(Params), ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.c_uint32, P]
+        L.orc_forced_neuron.restype = ctypes.c_int
+        L.orc_forced_neuron.argtypes = [ctypes.POINTER(Params), ctypes.c_uint32, ctypes.c_float,
+                                        ctypes.c_uint32, P, P, P, ctypes.c_uint32, P, P, P, P]
         L.orc_bf16_round.restype = ctypes.c_float
         L.orc_bf16_round.argtypes = [ctypes.c_float]
         _lib = L
@@ -140,6 +146,33 @@ def poisson_k(thr: np.ndarray, r: int) -> int:
 
 def bf16_round(x: float) -> float:
     return float(lib().orc_bf16_round(float(x)))
+
+
+def forced_raster(params: Params, t: int, lo: int = 0, hi: int | None = None) -> np.ndarray:
+    """Fired ids of step t under a forced raster, computed from the random
+    draws alone (any network size)."""
+    hi = params.n_neurons if hi is None else hi
+    out = np.zeros(max(hi - lo, 1), np.uint32)
+    n = lib().orc_forced_raster(ctypes.byref(params), t, lo, hi, _p(out))
+    return out[:n].copy()
+
+
+def forced_neuron(params: Params, j: int, u0: float, in_src, in_delay, in_w, n_steps: int):
+    """Neuron j alone under a forced raster from its incoming synapses:
+    -> (u, ref, spike count, pending input of the next max_delay steps)."""
+    src = np.ascontiguousarray(in_src, np.uint32)
+    dly = np.ascontiguousarray(in_delay, np.uint8)
+    w = np.ascontiguousarray(in_w, np.float32)
+    u = ctypes.c_float()
+    ref = ctypes.c_uint8()
+    ns = ctypes.c_uint32()
+    pend = np.zeros(params.max_delay, np.float32)
+    rc = lib().orc_forced_neuron(ctypes.byref(params), j, float(u0), len(src), _p(src), _p(dly),
+                                 _p(w), n_steps, ctypes.byref(u), ctypes.byref(ref), _p(pend),
+                                 ctypes.byref(ns))
+    if rc != 0:
+        raise ValueError("forced_neuron needs a forced-raster parameter set")
+    return np.float32(u.value), int(ref.value), int(ns.value), pend
 
 
 def alpha(params: Params) -> np.float32:

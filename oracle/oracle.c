@@ -317,6 +317,28 @@ static int cmp_u32(const void* a, const void* b) {
   return x < y ? -1 : x > y;
 }
 
+/* One neuron's binary32 update with input syn and k drive events; returns
+   1 if it fires.  Refractory neurons count down and ignore input; a forced
+   raster decides the spike by its own draw. */
+static int lif32(float alpha, float theta, float u_reset, float w_ext, uint32_t n_ref,
+                 int forced, int forced_spike, uint32_t k, float syn, float* u, uint8_t* ref) {
+  float ext = f32((double)k * (double)w_ext);
+  int integrating = *ref == 0;
+  if (!integrating) {
+    *ref -= 1;
+  } else {
+    float I = f32((double)syn + (double)ext);
+    float v = f32((double)*u * (double)alpha);
+    *u = f32((double)v + (double)I);
+  }
+  int spike = forced ? forced_spike : (integrating && *u >= theta);
+  if (spike) {
+    *u = u_reset;
+    *ref = (uint8_t)n_ref;
+  }
+  return spike;
+}
+
 /* Step 1: neuron update of both trajectories. */
 static void update_neurons(orc_sim* s) {
   const uint64_t t = s->t;
@@ -335,21 +357,9 @@ static void update_neurons(orc_sim* s) {
     /* binary32 trajectory */
     float syn = s->ring[(size_t)slot * s->N + i];
     s->ring[(size_t)slot * s->N + i] = 0.0f;
-    float ext = f32((double)k * (double)s->w_ext);
-    int integrating = s->ref[i] == 0;
-    if (!integrating) {
-      s->ref[i] -= 1;
-    } else {
-      float I = f32((double)syn + (double)ext);
-      float v = f32((double)s->u[i] * (double)s->alpha);
-      s->u[i] = f32((double)v + (double)I);
-    }
-    int spike = forced ? forced_spike : (integrating && s->u[i] >= s->theta);
-    if (spike) {
-      s->u[i] = s->u_reset;
-      s->ref[i] = (uint8_t)s->n_ref;
+    if (lif32(s->alpha, s->theta, s->u_reset, s->w_ext, s->n_ref, forced, forced_spike, k, syn,
+              &s->u[i], &s->ref[i]))
       s->fired[s->n_fired++] = i;
-    }
 
     /* FP64 trajectory */
     double syn64 = s->ring64[(size_t)slot * s->N + i];
@@ -539,4 +549,64 @@ void orc_accuracy(const orc_sim* s, double* out) {
   out[1] = (double)s->first_div;
   out[2] = (double)s->agree_steps;
   out[3] = s->min_margin;
+}
+
+/* ---- Forced raster at any size, without the synapse list of the whole
+   network.  With a forced raster a neuron's spike at step t is a pure
+   function of (seed, neuron, t), so the raster of a step and the complete
+   trajectory of one neuron (from its own incoming synapses) can be computed
+   for a network of any size. ---- */
+
+static uint32_t raster_thr_at(const orc_params* p, uint64_t t) {
+  double rate = (t % p->period_steps) < p->on_steps ? p->rate_on_hz : p->rate_off_hz;
+  return orc_raster_threshold(rate, p->dt_ms);
+}
+
+uint32_t orc_forced_raster(const orc_params* p, uint64_t t, uint32_t lo, uint32_t hi,
+                           uint32_t* out) {
+  const uint32_t thr = raster_thr_at(p, t);
+  uint32_t n = 0;
+  for (uint32_t i = lo; i < hi; ++i)
+    if (draw(p->seed, i, t, STREAM_RASTER) < thr) {
+      if (out) out[n] = i;
+      n++;
+    }
+  return n;
+}
+
+int orc_forced_neuron(const orc_params* p, uint32_t j, float u0, uint32_t n_in,
+                      const uint32_t* in_src, const uint8_t* in_delay, const float* in_w,
+                      uint32_t n_steps, float* u_out, uint8_t* ref_out, float* pending,
+                      uint32_t* n_spikes) {
+  if (!p->forced || p->max_delay == 0 || p->period_steps == 0) return -1;
+  const float alpha = orc_alpha(p), theta = f32(p->theta_mv), u_reset = f32(p->u_reset_mv);
+  const float w_ext = f32(p->w_ext_mv);
+  const uint32_t n_ref = orc_n_ref(p);
+  uint32_t poisson[15];
+  orc_poisson_table(p->nu_ext_hz * p->dt_ms * 1e-3, poisson);
+  /* input arriving at neuron j at step t: in-synapses whose source fired at
+     step t - delay (t - delay >= 0) */
+  const uint64_t horizon = (uint64_t)n_steps + p->max_delay;
+  float* arrive = (float*)xcalloc(horizon, sizeof(float));
+  for (uint32_t m = 0; m < n_in; ++m) {
+    const float w = p->bf16_weights ? orc_bf16_round(in_w[m]) : in_w[m];
+    for (uint64_t ts = 0; ts < n_steps; ++ts)
+      if (draw(p->seed, in_src[m], ts, STREAM_RASTER) < raster_thr_at(p, ts))
+        arrive[ts + in_delay[m]] = f32((double)arrive[ts + in_delay[m]] + (double)w);
+  }
+  float u = u0;
+  uint8_t ref = 0;
+  uint32_t spikes = 0;
+  for (uint64_t t = 0; t < n_steps; ++t) {
+    uint32_t k = orc_poisson_k(poisson, draw(p->seed, j, t, STREAM_POISSON));
+    int fs = draw(p->seed, j, t, STREAM_RASTER) < raster_thr_at(p, t);
+    spikes += (uint32_t)lif32(alpha, theta, u_reset, w_ext, n_ref, 1, fs, k, arrive[t], &u, &ref);
+  }
+  *u_out = u;
+  *ref_out = ref;
+  if (n_spikes) *n_spikes = spikes;
+  /* pending[d-1]: input already scheduled for step n_steps - 1 + d */
+  for (uint32_t d = 1; d <= p->max_delay; ++d) pending[d - 1] = arrive[n_steps - 1 + d];
+  free(arrive);
+  return 0;
 }

@@ -93,6 +93,21 @@ uint32_t orc_poisson_k(const uint32_t* thr15, uint32_t r);
 uint32_t orc_n_ref(const orc_params* p);
 uint32_t orc_raster_threshold(double rate_hz, double dt_ms);
 
+/* Forced raster at any network size (p->forced must be set):
+   orc_forced_raster writes the fired ids in [lo, hi) of step t (ascending)
+   and returns their count (out may be NULL).  orc_forced_neuron runs neuron
+   j alone for n_steps from state (u0, ref 0, empty ring), given its incoming
+   synapses (in_src, in_delay, in_w: n_in entries), and returns its final u
+   and ref, its spike count, and pending[max_delay]: the input already
+   scheduled for steps n_steps .. n_steps + max_delay - 1.  Returns 0, or -1
+   for a non-forced parameter set. */
+uint32_t orc_forced_raster(const orc_params* p, uint64_t t, uint32_t lo, uint32_t hi,
+                           uint32_t* out);
+int orc_forced_neuron(const orc_params* p, uint32_t j, float u0, uint32_t n_in,
+                      const uint32_t* in_src, const uint8_t* in_delay, const float* in_w,
+                      uint32_t n_steps, float* u_out, uint8_t* ref_out, float* pending,
+                      uint32_t* n_spikes);
+
 /* Building blocks, exposed for pinning tests. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 float orc_bf16_round(float x);

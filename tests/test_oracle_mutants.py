@@ -16,12 +16,11 @@ MUTANTS = {
     "philox_key_bump": ("k1 += W1;", "k1 += W0;"),
     "poisson_strict": ("if (thr[j] <= r) k++;", "if (thr[j] < r) k++;"),
     "drop_drive": ("float I = f32((double)syn + (double)ext);", "float I = f32((double)syn);"),
-    "strict_threshold": ("(integrating && s->u[i] >= s->theta)",
-                         "(integrating && s->u[i] > s->theta)"),
-    "short_refractory": ("s->ref[i] = (uint8_t)s->n_ref;", "s->ref[i] = (uint8_t)s->n_ref - 1;"),
-    "fused_update": ("float v = f32((double)s->u[i] * (double)s->alpha);\n"
-                     "      s->u[i] = f32((double)v + (double)I);",
-                     "s->u[i] = f32((double)s->u[i] * (double)s->alpha + (double)I);"),
+    "strict_threshold": ("(integrating && *u >= theta)", "(integrating && *u > theta)"),
+    "short_refractory": ("*ref = (uint8_t)n_ref;", "*ref = (uint8_t)n_ref - 1;"),
+    "fused_update": ("float v = f32((double)*u * (double)alpha);\n"
+                     "    *u = f32((double)v + (double)I);",
+                     "*u = f32((double)*u * (double)alpha + (double)I);"),
     "mask_bit_shift": ("s->node_mask[node] |= 1u << (s->vps[j] - s->G * node);",
                        "s->node_mask[node] |= 1u << (s->vps[j] - s->G * node + 1);"),
     "own_partition": ("if (v == own) continue;", "if (v == own + 1) continue;"),
