@@ -33,8 +33,7 @@ enum : uint32_t { STREAM_POISSON = 1u, STREAM_RASTER = 2u };
 
 // Kernel launch geometry.
 constexpr int UPDATE_THREADS = 256;
-constexpr int UPDATE_NPT = 4;                                  // neurons per thread
-constexpr int UPDATE_NPB = UPDATE_THREADS * UPDATE_NPT;        // neurons per block
+constexpr int UPDATE_NPT_MIN = 4;   // neurons per thread: 4, 8 or 16 (tuning knob)
 constexpr int ROUTE_THREADS = 256;
 constexpr int DELIVER_THREADS = 256;
 
@@ -81,7 +80,8 @@ struct KParams {
 };
 
 // Launchers (snn_kernels.hip); all enqueue on `s` and return the launch error.
-hipError_t launch_update(const KParams& p, uint32_t blocks, hipStream_t s);
+uint32_t update_blocks(uint32_t n, int npt);
+hipError_t launch_update(const KParams& p, int npt, hipStream_t s);
 hipError_t launch_route(const KParams& p, int mode, hipStream_t s);
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s);
 

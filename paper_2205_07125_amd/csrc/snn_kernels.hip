@@ -132,8 +132,16 @@ __device__ uint32_t lookback_exclusive(uint64_t* lb, uint32_t b, uint32_t agg, u
   return excl;
 }
 
+// One thread owns NPT neurons as NPT/4 quads.  Quad q of thread tid covers
+// neurons blk0 + q*4*UPDATE_THREADS + 4*tid .. +3, so every load and store
+// instruction of a wave touches one contiguous 1 KiB span.  Ids are ordered
+// quad-major across the block, which the compaction follows.
+template <int NPT>
 __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
-  __shared__ uint32_t s_wave_tot[UPDATE_THREADS / 64];
+  static_assert(NPT % 4 == 0 && NPT >= 4, "NPT is a multiple of 4");
+  constexpr int NQ = NPT / 4;
+  constexpr int NW = UPDATE_THREADS / 64;
+  __shared__ uint32_t s_cnt[NQ][NW];
   __shared__ uint32_t s_excl;
 
   // Read once: the last block advances both when the step is complete.
@@ -143,8 +151,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   const uint32_t slot = static_cast<uint32_t>(t % p.D);
   const uint32_t row = static_cast<uint32_t>(t % p.log_steps);
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t gthread = blockIdx.x * UPDATE_THREADS + tid;
-  const uint32_t base = gthread * UPDATE_NPT;
+  const uint32_t blk0 = blockIdx.x * (UPDATE_THREADS * NPT);
 
   // Per-step counters of the routing and delivery kernels that follow.
   if (blockIdx.x == 0) {
@@ -156,97 +163,112 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (tid >= 1 && tid < SNN_NSTAT) p.stats[static_cast<uint64_t>(row) * SNN_NSTAT + tid] = 0;
   }
 
-  // Random words: one Philox call serves the 4 neurons of this thread.
-  const uint4 rnd = philox4x32_10(gthread, static_cast<uint32_t>(t), STREAM_POISSON, 0u,
-                                  p.seed_lo, p.seed_hi);
-  uint4 rnd2 = make_uint4(0, 0, 0, 0);
   uint32_t thr_raster = 0;
-  if (p.forced) {
-    rnd2 = philox4x32_10(gthread, static_cast<uint32_t>(t), STREAM_RASTER, 0u, p.seed_lo,
-                         p.seed_hi);
-    thr_raster = (t % p.raster_period) < p.raster_on ? p.raster_on_thr : p.raster_off_thr;
-  }
-  const uint32_t r1[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
-  const uint32_t r2[4] = {rnd2.x, rnd2.y, rnd2.z, rnd2.w};
-
+  if (p.forced) thr_raster = (t % p.raster_period) < p.raster_on ? p.raster_on_thr : p.raster_off_thr;
   float* ring_slot = p.ring + static_cast<uint64_t>(slot) * p.ring_stride;
-  float uu[4] = {0.f, 0.f, 0.f, 0.f}, syn[4] = {0.f, 0.f, 0.f, 0.f};
-  uint32_t rf[4] = {0, 0, 0, 0};
-  const bool full = base + UPDATE_NPT <= p.N;
-  if (full) {
-    const float4 u4 = *reinterpret_cast<const float4*>(p.u + base);
-    const float4 s4 = *reinterpret_cast<const float4*>(ring_slot + base);
-    const uint32_t r4 = *reinterpret_cast<const uint32_t*>(p.ref + base);
-    uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
-    syn[0] = s4.x; syn[1] = s4.y; syn[2] = s4.z; syn[3] = s4.w;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) rf[k] = (r4 >> (8 * k)) & 0xFFu;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (base + k < p.N) {
-        uu[k] = p.u[base + k];
-        syn[k] = ring_slot[base + k];
-        rf[k] = p.ref[base + k];
-      }
-  }
 
-  bool fire[4];
+  uint32_t fire_bits = 0;   // bit 4q + k: neuron k of quad q fired
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    uint32_t kk = 0;
+  for (int q = 0; q < NQ; ++q) {
+    const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
+    // Philox counter word 0 is i0 / 4: one call serves the quad's 4 neurons.
+    const uint4 rnd = philox4x32_10(i0 >> 2, static_cast<uint32_t>(t), STREAM_POISSON, 0u,
+                                    p.seed_lo, p.seed_hi);
+    uint4 rnd2 = make_uint4(0, 0, 0, 0);
+    if (p.forced)
+      rnd2 = philox4x32_10(i0 >> 2, static_cast<uint32_t>(t), STREAM_RASTER, 0u, p.seed_lo,
+                           p.seed_hi);
+    const uint32_t r1[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
+    const uint32_t r2[4] = {rnd2.x, rnd2.y, rnd2.z, rnd2.w};
+    float uu[4] = {0.f, 0.f, 0.f, 0.f}, syn[4] = {0.f, 0.f, 0.f, 0.f};
+    uint32_t rf[4] = {0, 0, 0, 0};
+    const bool full = i0 + 4 <= p.N;
+    if (full) {
+      const float4 u4 = *reinterpret_cast<const float4*>(p.u + i0);
+      const float4 s4 = *reinterpret_cast<const float4*>(ring_slot + i0);
+      const uint32_t r4 = *reinterpret_cast<const uint32_t*>(p.ref + i0);
+      uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
+      syn[0] = s4.x; syn[1] = s4.y; syn[2] = s4.z; syn[3] = s4.w;
 #pragma unroll
-    for (int j = 0; j < 15; ++j) kk += p.thr[j] <= r1[k] ? 1u : 0u;
-    const float ext = __fmul_rn(static_cast<float>(kk), p.w_ext);
-    const bool integrating = rf[k] == 0;
-    if (!integrating) {
-      rf[k] -= 1;
+      for (int k = 0; k < 4; ++k) rf[k] = (r4 >> (8 * k)) & 0xFFu;
     } else {
-      const float I = __fadd_rn(syn[k], ext);
-      const float v = __fmul_rn(uu[k], p.alpha);
-      uu[k] = __fadd_rn(v, I);
-    }
-    bool s = p.forced ? (r2[k] < thr_raster) : (integrating && uu[k] >= p.theta);
-    s = s && (base + k < p.N);
-    if (s) {
-      uu[k] = p.u_reset;
-      rf[k] = p.n_ref;
-    }
-    fire[k] = s;
-  }
-
-  if (full) {
-    *reinterpret_cast<float4*>(p.u + base) = make_float4(uu[0], uu[1], uu[2], uu[3]);
-    *reinterpret_cast<float4*>(ring_slot + base) = make_float4(0.f, 0.f, 0.f, 0.f);
-    *reinterpret_cast<uint32_t*>(p.ref + base) = rf[0] | (rf[1] << 8) | (rf[2] << 16) | (rf[3] << 24);
-  } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (base + k < p.N) {
-        p.u[base + k] = uu[k];
-        ring_slot[base + k] = 0.f;
-        p.ref[base + k] = static_cast<uint8_t>(rf[k]);
+      for (int k = 0; k < 4; ++k)
+        if (i0 + k < p.N) {
+          uu[k] = p.u[i0 + k];
+          syn[k] = ring_slot[i0 + k];
+          rf[k] = p.ref[i0 + k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t kk = 0;
+#pragma unroll
+      for (int j = 0; j < 15; ++j) kk += p.thr[j] <= r1[k] ? 1u : 0u;
+      const float ext = __fmul_rn(static_cast<float>(kk), p.w_ext);
+      const bool integrating = rf[k] == 0;
+      if (!integrating) {
+        rf[k] -= 1;
+      } else {
+        const float I = __fadd_rn(syn[k], ext);
+        const float v = __fmul_rn(uu[k], p.alpha);
+        uu[k] = __fadd_rn(v, I);
       }
+      bool s = p.forced ? (r2[k] < thr_raster) : (integrating && uu[k] >= p.theta);
+      s = s && (i0 + k < p.N);
+      if (s) {
+        uu[k] = p.u_reset;
+        rf[k] = p.n_ref;
+      }
+      fire_bits |= static_cast<uint32_t>(s) << (4 * q + k);
+    }
+    if (full) {
+      *reinterpret_cast<float4*>(p.u + i0) = make_float4(uu[0], uu[1], uu[2], uu[3]);
+      *reinterpret_cast<float4*>(ring_slot + i0) = make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<uint32_t*>(p.ref + i0) =
+          rf[0] | (rf[1] << 8) | (rf[2] << 16) | (rf[3] << 24);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (i0 + k < p.N) {
+          p.u[i0 + k] = uu[k];
+          ring_slot[i0 + k] = 0.f;
+          p.ref[i0 + k] = static_cast<uint8_t>(rf[k]);
+        }
+    }
   }
 
-  // Compaction: ids are ordered thread-major (thread j owns 4j..4j+3), so the
-  // rank of a fired id is the number of fired ids in lower lanes (4 ballots)
-  // plus those before it in the same thread.
+  // Compaction.  Within quad q, ids ascend with (wave, lane, k); across
+  // quads, quad q of every wave precedes quad q + 1.  The rank of a fired id
+  // is: fired ids of earlier quads (whole block) + of earlier waves in this
+  // quad + of lower lanes in this wave and quad (4 ballots) + earlier k.
   const uint64_t lt = (1ull << lane) - 1ull;
-  uint32_t prefix = 0, wave_tot = 0;
+  uint32_t lane_pre[NQ];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint64_t b = __ballot(fire[k]);
-    prefix += __popcll(b & lt);
-    wave_tot += __popcll(b);
+  for (int q = 0; q < NQ; ++q) {
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t b = __ballot((fire_bits >> (4 * q + k)) & 1u);
+      pre += __popcll(b & lt);
+      tot += __popcll(b);
+    }
+    lane_pre[q] = pre;
+    if (lane == 0) s_cnt[q][wave] = tot;
   }
-  if (lane == 0) s_wave_tot[wave] = wave_tot;
   __syncthreads();
-  uint32_t wave_off = 0, block_tot = 0;
+  uint32_t block_tot = 0;
+  uint32_t quad_off[NQ];
 #pragma unroll
-  for (int w = 0; w < UPDATE_THREADS / 64; ++w) {
-    wave_off += w < static_cast<int>(wave) ? s_wave_tot[w] : 0u;
-    block_tot += s_wave_tot[w];
+  for (int q = 0; q < NQ; ++q) {
+    uint32_t before_wave = 0, quad_tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      before_wave += w < static_cast<int>(wave) ? s_cnt[q][w] : 0u;
+      quad_tot += s_cnt[q][w];
+    }
+    quad_off[q] = block_tot + before_wave + lane_pre[q];
+    block_tot += quad_tot;
   }
   const uint32_t tag = static_cast<uint32_t>(t % 0x3FFFFFFFull) + 1u;
   if (wave == 0) {
@@ -254,14 +276,20 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (lane == 0) s_excl = excl;
   }
   __syncthreads();
-  uint32_t pos = s_excl + wave_off + prefix;
+  if (fire_bits) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (fire[k]) {
-      p.fired[pos] = base + k;
-      if (p.log_cap) p.log[(log_base + pos) % p.log_cap] = base + k;
-      ++pos;
+    for (int q = 0; q < NQ; ++q) {
+      uint32_t pos = s_excl + quad_off[q];
+      const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if ((fire_bits >> (4 * q + k)) & 1u) {
+          p.fired[pos] = i0 + k;
+          if (p.log_cap) p.log[(log_base + pos) % p.log_cap] = i0 + k;
+          ++pos;
+        }
     }
+  }
 
   // The last block holds the step total once its look-back is done; every
   // other block has read t and log_total by then (they published first).
@@ -434,8 +462,19 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver_recv(KParams p, int
 // ---------------------------------------------------------------------------
 // launchers
 
-hipError_t launch_update(const KParams& p, uint32_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(blocks), dim3(UPDATE_THREADS), 0, s, p);
+uint32_t update_blocks(uint32_t n, int npt) {
+  const uint32_t per = UPDATE_THREADS * static_cast<uint32_t>(npt);
+  return (n + per - 1) / per;
+}
+
+hipError_t launch_update(const KParams& p, int npt, hipStream_t s) {
+  const dim3 grid(update_blocks(p.N, npt)), block(UPDATE_THREADS);
+  switch (npt) {
+    case 4: hipLaunchKernelGGL(k_update<4>, grid, block, 0, s, p); break;
+    case 8: hipLaunchKernelGGL(k_update<8>, grid, block, 0, s, p); break;
+    case 16: hipLaunchKernelGGL(k_update<16>, grid, block, 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -46,7 +47,16 @@ uint32_t n_nodes_of(const snn_params* p) {
   return (p->n_partitions + p->gpus_per_node - 1) / p->gpus_per_node;
 }
 
-uint32_t update_blocks(uint32_t n) { return (n + UPDATE_NPB - 1) / UPDATE_NPB; }
+// Launch configuration knobs; SNN_UPDATE_NPT overrides the default (for
+// sweeps of the block size).
+int tuned_update_npt() {
+  const char* e = std::getenv("SNN_UPDATE_NPT");
+  if (e) {
+    int v = std::atoi(e);
+    if (v == 4 || v == 8 || v == 16) return v;
+  }
+  return 8;
+}
 
 // Byte offsets of the workspace regions.
 struct Layout {
@@ -63,7 +73,7 @@ Layout layout(const snn_params* p) {
     return at;
   };
   L.st = take(sizeof(DevState));
-  L.lookback = take(sizeof(uint64_t) * update_blocks(p->n_neurons));
+  L.lookback = take(sizeof(uint64_t) * update_blocks(p->n_neurons, UPDATE_NPT_MIN));
   L.fired = take(sizeof(uint32_t) * uint64_t(p->n_neurons));
   L.bucket_cnt = take(sizeof(uint32_t) * n_nodes_of(p));
   L.bucket = take(sizeof(uint64_t) * p->bucket_total);
@@ -109,7 +119,7 @@ struct snn_ctx {
   snn_network_dev net;
   hipStream_t stream;
   KParams kp;
-  uint32_t k1_blocks;
+  int update_npt;
   int phase;          // 0: expects step, 1: route, 2: deliver
   int route_mode;     // mode of the step in flight
   uint64_t t_host;    // steps enqueued
@@ -159,7 +169,7 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   c->prm = *params;
   c->net = *net;
   c->stream = static_cast<hipStream_t>(stream);
-  c->k1_blocks = update_blocks(params->n_neurons);
+  c->update_npt = tuned_update_npt();
   KParams& k = c->kp;
   k.N = params->n_neurons;
   k.P = params->n_partitions;
@@ -225,7 +235,7 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
 snn_status snn_step(snn_handle h) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
   if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_step called before snn_deliver");
-  HIP_TRY(launch_update(h->kp, h->k1_blocks, h->stream));
+  HIP_TRY(launch_update(h->kp, h->update_npt, h->stream));
   h->phase = 1;
   return SNN_OK;
 }
@@ -259,7 +269,7 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
   if (n_steps == 0) return SNN_OK;
   if (!use_graph) {
     for (uint32_t i = 0; i < n_steps; ++i) {
-      HIP_TRY(launch_update(h->kp, h->k1_blocks, h->stream));
+      HIP_TRY(launch_update(h->kp, h->update_npt, h->stream));
       HIP_TRY(launch_route(h->kp, mode, h->stream));
       HIP_TRY(launch_deliver(h->kp, mode, h->stream));
     }
@@ -267,7 +277,7 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
     if (!h->graph[mode]) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e1 = launch_update(h->kp, h->k1_blocks, h->stream);
+      hipError_t e1 = launch_update(h->kp, h->update_npt, h->stream);
       hipError_t e2 = e1 == hipSuccess ? launch_route(h->kp, mode, h->stream) : e1;
       hipError_t e3 = e2 == hipSuccess ? launch_deliver(h->kp, mode, h->stream) : e2;
       hipError_t ec = hipStreamEndCapture(h->stream, &g);
