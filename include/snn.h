@@ -23,8 +23,14 @@
  *                per-partition receive lists (what the bridge of Sec. IV-B
  *                does); flat: one entry per (source, destination partition)
  *   snn_deliver  synaptic delivery: each fired source's own-partition
- *                synapses, then the synapses reached through the receive
- *                lists, accumulated into a delay ring; t advances
+ *                synapses, and the synapses the receive lists reach, are
+ *                scheduled for step t + d (d = the synapse's delay) and summed
+ *                into the target's input when that step's update runs
+ *
+ * Scheduled input lives in per-(step mod D, tile of neurons) bins, with a
+ * dense delay ring ring[(max_delay+1)][n] as the overflow path for bins that
+ * are full; snn_flush moves all binned input into the ring, after which the
+ * ring alone holds the input of the coming steps.
  *
  * Neuron model (the paper only names LIF as a model class, Table I):
  * current-based leaky integrate-and-fire with delta synapses, state
@@ -37,7 +43,8 @@
  *   spike = forced ? (r2 < raster threshold of step t) : (integrating && u >= theta)
  *           with r2 the Philox word on stream 2
  *   if spike: u = u_reset; ref[i] = n_ref
- * and every synapse (s -> tgt, w, d) of a fired s adds w to ring[(t+d) mod D][tgt].
+ * and every synapse (s -> tgt, w, d) of a fired s adds w to the input of tgt
+ * at step t + d (ring slot (t+d) mod D).
  *
  * Conventions for every call:
  *  - Return value: SNN_OK or a negative snn_status; calls never abort.  The
@@ -133,6 +140,11 @@ typedef struct {
                                  older steps are overwritten */
   uint32_t reserved0;
   uint64_t log_cap;           /* spike-log capacity in neuron ids */
+  uint64_t bin_cap;           /* events per delivery bin: one bin per (ring slot, tile of
+                                 16384 neurons, delay, delivery block of 32 per delay);
+                                 events beyond it take the (slower) dense-ring path */
+  uint64_t stage_cap;         /* remote events per (delay, receive-side block of 256) and
+                                 step; beyond it, the dense-ring path */
 } snn_params;
 
 /* Network arrays in device memory.  nnz = row_ptr[n_neurons]; pairs =
@@ -140,7 +152,10 @@ typedef struct {
 typedef struct {
   const int64_t* row_ptr;          /* [N+1] out-synapses of source s: [row_ptr[s], row_ptr[s+1]) */
   const uint32_t* n_local;         /* [N] the first n_local[s] synapses of the row stay in
-                                      the source's own partition */
+                                      the source's own partition, sorted by delay */
+  const uint16_t* delay_off;       /* [N][max_delay+1] delay_off[s][d-1] = first synapse
+                                      (relative to row_ptr[s]) of delay d in the local part;
+                                      delay_off[s][max_delay] = n_local[s] (< 65536) */
   const uint32_t* tgt_delay;       /* [nnz] (delay << 27) | target neuron */
   const void* weight;              /* [nnz] float (SNN_W_FP32) or bfloat16 bits (SNN_W_BF16) */
   const int64_t* vp_ptr;           /* [N+1] destination partitions of s:
@@ -190,8 +205,8 @@ snn_status snn_step(snn_handle h);
 snn_status snn_route(snn_handle h, int mode);
 
 /* Delivers the current step's synaptic events (own partition and receive
-   lists) into ring slots (t + d) mod D, then advances t.  Order: must follow
-   snn_route. */
+   lists): each is scheduled for step t + d in its tile's bin (or the ring
+   slot (t + d) mod D when the bin is full).  Order: must follow snn_route. */
 snn_status snn_deliver(snn_handle h);
 
 /* n_steps full steps (step, route(mode), deliver).  use_graph != 0 captures
@@ -199,8 +214,17 @@ snn_status snn_deliver(snn_handle h);
    live in device memory).  Order: as snn_step. */
 snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph);
 
+/* Moves every pending binned synaptic event into the dense ring, so that the
+   ring alone holds the input scheduled for the coming steps (for read-back
+   of the state; the simulation continues unchanged).  Order: between steps. */
+snn_status snn_flush(snn_handle h);
+
 /* Blocks until the handle's work is done; reports sticky device errors. */
 snn_status snn_sync(snn_handle h);
+
+/* Events that took the dense-ring path so far (a bin or a staging queue was
+   full).  Synchronises. */
+snn_status snn_ring_events(snn_handle h, uint64_t* n);
 
 /* Steps completed so far (host-side count of enqueued steps). */
 uint64_t snn_time(snn_handle h);
@@ -214,15 +238,18 @@ snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps,
                            int32_t* ids, uint64_t cap, uint32_t* per_step_counts,
                            uint64_t* n_ids);
 
-/* Routing buffers of the last routed step, copied to host memory.
-   which = 0: flat receive lists (uint32 source ids, per partition);
-   which = 1: expanded two-level receive lists (uint32 source ids);
-   which = 2: per-node send buckets (uint64 messages: bits 0..31 source id,
-              bits 32..39 partition mask of the node; upper bits unspecified).
+/* Routing buffers of the last routed step, copied to host memory, as uint64
+   elements.
+   which = 0: flat receive lists, per partition: bits 0..31 source id, bits
+              32..63 index of the partition in the source's destination list
+              (the routing-table index the receiver uses to find its synapses);
+   which = 1: expanded two-level receive lists, same format;
+   which = 2: per-node send buckets: bits 0..31 source id, bits 32..39
+              partition mask of the node, bits 40..63 index of the node's first
+              destination in the source's destination list.
    sizes[n_partitions or n_nodes] receives the counts; entries (may be NULL)
    receives the lists concatenated in partition / node order, at most cap
-   entries (elements of 4 or 8 bytes).  Order inside a list is unspecified.
-   Synchronises. */
+   entries.  Order inside a list is unspecified.  Synchronises. */
 snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entries,
                            uint64_t cap, uint64_t* n_entries);
 

@@ -68,11 +68,13 @@ snn_status snn_setup_sizes(snn_setup_handle h, uint64_t* nnz, uint64_t* pairs,
                            uint64_t* bucket_total, uint64_t* recv_total);
 
 /* Second pass: places every synapse in its source row and sorts each row into
-   [own-partition synapses | destination partitions ascending], ties by
-   (target, delay, weight).  row_ptr[N+1], n_local[N], tgt_delay[nnz],
-   weight[nnz] (float or uint16 per weight_type). */
+   [own-partition synapses | destination partitions ascending], each part by
+   (delay, target, weight).  row_ptr[N+1], n_local[N], delay_off[N][max_delay+1]
+   (start of each delay's run in the own-partition part; the last entry is
+   n_local, which must stay below 65536), tgt_delay[nnz], weight[nnz] (float or
+   uint16 per weight_type). */
 snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n_local,
-                               uint32_t* tgt_delay, void* weight);
+                               uint16_t* delay_off, uint32_t* tgt_delay, void* weight);
 
 /* Destination-partition lists and capacity bounds: vp_ptr[N+1], vp_part[pairs],
    vp_seg[pairs], part_of_neuron[N], bucket_off[n_nodes+1] (bucket of node n:

@@ -29,7 +29,8 @@ SNN_NSTAT = len(STAT_NAMES)
 
 EXPORTED = [
     "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route",
-    "snn_deliver", "snn_run", "snn_sync", "snn_time", "snn_read_spikes", "snn_read_routes",
+    "snn_deliver", "snn_run", "snn_flush", "snn_sync", "snn_time", "snn_ring_events",
+    "snn_read_spikes", "snn_read_routes",
     "snn_read_counters", "snn_destroy", "snn_last_error",
     "snn_setup_create", "snn_setup_sizes", "snn_setup_fill_rows", "snn_setup_fill_routes",
     "snn_setup_destroy",
@@ -48,12 +49,13 @@ class snn_params(ctypes.Structure):
         ("raster_thr_on", u32), ("raster_thr_off", u32), ("raster_period", u32), ("raster_on", u32),
         ("bucket_total", u64), ("recv_total", u64),
         ("log_steps", u32), ("reserved0", u32), ("log_cap", u64),
+        ("bin_cap", u64), ("stage_cap", u64),
     ]
 
 
 class snn_network_dev(ctypes.Structure):
     _fields_ = [(n, vp) for n in (
-        "row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_seg",
+        "row_ptr", "n_local", "delay_off", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_seg",
         "part_of_neuron", "bucket_off", "recv_off", "u", "ref", "ring")]
 
 
@@ -93,7 +95,9 @@ def lib() -> ctypes.CDLL:
             "snn_route": (I, [vp, I]),
             "snn_deliver": (I, [vp]),
             "snn_run": (I, [vp, u32, I, I]),
+            "snn_flush": (I, [vp]),
             "snn_sync": (I, [vp]),
+            "snn_ring_events": (I, [vp, ctypes.POINTER(u64)]),
             "snn_time": (u64, [vp]),
             "snn_read_spikes": (I, [vp, u64, u32, vp, u64, vp, ctypes.POINTER(u64)]),
             "snn_read_routes": (I, [vp, I, vp, vp, u64, ctypes.POINTER(u64)]),
@@ -102,7 +106,7 @@ def lib() -> ctypes.CDLL:
             "snn_last_error": (ctypes.c_char_p, []),
             "snn_setup_create": (I, [ctypes.POINTER(snn_setup_spec), vp, vp, ctypes.POINTER(vp)]),
             "snn_setup_sizes": (I, [vp] + [ctypes.POINTER(u64)] * 4),
-            "snn_setup_fill_rows": (I, [vp, vp, vp, vp, vp]),
+            "snn_setup_fill_rows": (I, [vp] * 6),
             "snn_setup_fill_routes": (I, [vp] * 7),
             "snn_setup_destroy": (None, [vp]),
         }
@@ -155,8 +159,18 @@ def snn_run(h, n_steps: int, mode: int, use_graph: bool):
     check(lib().snn_run(h, n_steps, mode, 1 if use_graph else 0))
 
 
+def snn_flush(h):
+    check(lib().snn_flush(h))
+
+
 def snn_sync(h):
     check(lib().snn_sync(h))
+
+
+def snn_ring_events(h) -> int:
+    n = u64()
+    check(lib().snn_ring_events(h, ctypes.byref(n)))
+    return n.value
 
 
 def snn_time(h) -> int:

@@ -15,32 +15,61 @@ enum : uint32_t {
   ERR_RECV = 2u,     // an expanded receive list overflowed
   ERR_FLAT = 4u,     // a flat receive list overflowed
   ERR_LOG = 8u,      // a step had more spikes than the spike log holds
-  ERR_ROUTE = 16u    // a receive entry names a source without that partition
+  ERR_ROUTE = 16u    // a receive entry names a partition its source does not reach
 };
 
 // Device-resident step state.  Every step-dependent value lives here so that
 // a captured step replays unchanged.
+// Residues of t are kept alongside it (advanced by the update kernel's last
+// block) so kernels never divide 64-bit values.
 struct DevState {
   uint64_t t;          // step the next update kernel runs
   uint64_t log_total;  // ids appended to the spike log so far
   uint32_t n_fired;    // spikes of the step in flight (t - 1 after the update)
   uint32_t error;      // sticky ERR_* bits
-  uint32_t pad[10];
+  uint64_t ring_events;  // events that went to the dense ring (bin or staging full)
+  uint32_t slot;       // t mod D
+  uint32_t row;        // t mod log_steps
+  uint32_t phase;      // t mod raster_period
+  uint32_t tag;        // look-back tag of step t, minus 1, in [0, 2^30 - 1)
+  uint32_t cur_slot;   // slot of the step in flight
+  uint32_t cur_row;    // row of the step in flight
+  uint64_t log_head;   // log_total mod log_cap
+  uint32_t pad[2];
 };
 
 // Stream ids of the counter-based generator.
 enum : uint32_t { STREAM_POISSON = 1u, STREAM_RASTER = 2u };
 
-// Kernel launch geometry.
-constexpr int UPDATE_THREADS = 256;
-constexpr int UPDATE_NPT_MIN = 4;   // neurons per thread: 4, 8 or 16 (tuning knob)
+// Geometry.  Neurons are grouped in tiles of TILE neurons: the update kernel
+// runs one block per tile and accumulates the tile's arriving input in LDS;
+// synaptic events are binned per (ring slot, tile).
+constexpr int TILE_SHIFT = 14;
+constexpr uint32_t TILE = 1u << TILE_SHIFT;         // 16384 neurons
+constexpr int UPDATE_THREADS = 1024;
+constexpr int UPDATE_NPT = TILE / UPDATE_THREADS;   // 16 neurons per thread
 constexpr int ROUTE_THREADS = 256;
-constexpr int DELIVER_THREADS = 256;
+constexpr int DELIVER_THREADS = 512;
+constexpr uint32_t CNT_STRIDE = 16;                 // counters padded to 64 bytes
+constexpr uint32_t ROUTE_STAGE = 4096;              // staged messages / entries per round
+constexpr uint32_t ROUTE_BLOCKS = 128;              // two-level routing blocks
+constexpr uint32_t ROUTE_MAX_NODES_LDS = 8192;      // more nodes: unstaged routing
+constexpr uint32_t EXPAND_BLOCKS = 4;               // expansion blocks per node
+constexpr uint32_t DELIVER_STAGE = 6144;            // staged events per round
+constexpr uint32_t DELIVER_BLOCKS = 32;             // deliver blocks per delay
+constexpr uint32_t STAGE_BLOCKS = 256;              // receive-side blocks (one queue each)
+constexpr uint32_t STAGE_PARTS = (SNN_MAX_PARTITIONS + STAGE_BLOCKS - 1) / STAGE_BLOCKS;
+
+// A binned synaptic event: target index inside its tile and weight.
+struct Event {
+  uint32_t tgt;
+  float w;
+};
 
 // Everything a kernel needs, passed by value.
 struct KParams {
   // model
-  uint32_t N, P, G, D, n_nodes;
+  uint32_t N, P, G, D, n_nodes, n_tiles;
   uint32_t n_ref;
   uint64_t ring_stride;
   float alpha, theta, u_reset, w_ext;
@@ -50,9 +79,12 @@ struct KParams {
   uint32_t bf16;
   uint32_t log_steps;
   uint64_t log_cap;
+  uint64_t bin_cap;
+  uint64_t stage_cap;
   // network (caller-owned device memory)
   const int64_t* row_ptr;
   const uint32_t* n_local;
+  const uint16_t* delay_off;   // [N][D] start of each delay's run in the local segment
   const uint32_t* tgt_delay;
   const void* weight;
   const int64_t* vp_ptr;
@@ -66,23 +98,30 @@ struct KParams {
   float* ring;
   // workspace
   DevState* st;
-  uint64_t* lookback;   // [update blocks] decoupled look-back words
+  uint64_t* lookback;   // [n_tiles] decoupled look-back words
   uint32_t* fired;      // [N] ascending fired ids of the step in flight
-  uint32_t* bucket_cnt; // [n_nodes]
+  uint32_t* bucket_cnt; // [n_nodes * CNT_STRIDE]
   uint64_t* bucket;     // [bucket_total]
-  uint32_t* recv_cnt;   // [P] expanded lists
-  uint32_t* recv;       // [recv_total]
-  uint32_t* flat_cnt;   // [P]
-  uint32_t* flat;       // [recv_total]
+  uint32_t* recv_cnt;   // [P * CNT_STRIDE] expanded lists
+  uint64_t* recv;       // [recv_total]
+  uint32_t* flat_cnt;   // [P * CNT_STRIDE]
+  uint64_t* flat;       // [recv_total]
+  uint32_t* stage_cnt;  // [max_delay * CNT_STRIDE] remote events staged per delay
+  Event* stage;         // [max_delay][stage_cap] (global target ids)
+  uint32_t* bin_cnt;    // [D * n_tiles * CNT_STRIDE]
+  uint32_t* dirty;      // [D * n_tiles] ring tile holds events
+  Event* bins;          // [D][n_tiles][bin_cap]
   uint64_t* stats;      // [log_steps][SNN_NSTAT]
   uint64_t* log_off;    // [log_steps] first log position of each step
   uint32_t* log;        // [log_cap] spike-log ring
 };
 
 // Launchers (snn_kernels.hip); all enqueue on `s` and return the launch error.
-uint32_t update_blocks(uint32_t n, int npt);
-hipError_t launch_update(const KParams& p, int npt, hipStream_t s);
+uint32_t tiles_of(uint32_t n);
+hipError_t prepare_kernels(const KParams& p);   // dynamic-LDS limits, once per handle
+hipError_t launch_update(const KParams& p, hipStream_t s);
 hipError_t launch_route(const KParams& p, int mode, hipStream_t s);
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s);
+hipError_t launch_flush(const KParams& p, hipStream_t s);
 
 }  // namespace snn

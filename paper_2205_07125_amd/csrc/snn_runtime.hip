@@ -12,6 +12,7 @@
 
 using namespace snn;
 
+
 namespace {
 thread_local char g_err[512] = "";
 }
@@ -47,21 +48,10 @@ uint32_t n_nodes_of(const snn_params* p) {
   return (p->n_partitions + p->gpus_per_node - 1) / p->gpus_per_node;
 }
 
-// Launch configuration knobs; SNN_UPDATE_NPT overrides the default (for
-// sweeps of the block size).
-int tuned_update_npt() {
-  const char* e = std::getenv("SNN_UPDATE_NPT");
-  if (e) {
-    int v = std::atoi(e);
-    if (v == 4 || v == 8 || v == 16) return v;
-  }
-  return 8;
-}
-
 // Byte offsets of the workspace regions.
 struct Layout {
-  uint64_t st, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat, stats,
-      log_off, log, total;
+  uint64_t st, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat, stage_cnt,
+      stage, bin_cnt, dirty, bins, stats, log_off, log, total;
 };
 
 Layout layout(const snn_params* p) {
@@ -72,17 +62,24 @@ Layout layout(const snn_params* p) {
     o = align256(o + bytes);
     return at;
   };
+  const uint64_t D = p->max_delay + 1, md = p->max_delay, tiles = tiles_of(p->n_neurons);
   L.st = take(sizeof(DevState));
-  L.lookback = take(sizeof(uint64_t) * update_blocks(p->n_neurons, UPDATE_NPT_MIN));
+  L.lookback = take(sizeof(uint64_t) * tiles);
   L.fired = take(sizeof(uint32_t) * uint64_t(p->n_neurons));
-  L.bucket_cnt = take(sizeof(uint32_t) * n_nodes_of(p));
-  L.bucket = take(sizeof(uint64_t) * p->bucket_total);
-  L.recv_cnt = take(sizeof(uint32_t) * p->n_partitions);
-  L.recv = take(sizeof(uint32_t) * p->recv_total);
-  L.flat_cnt = take(sizeof(uint32_t) * p->n_partitions);
-  L.flat = take(sizeof(uint32_t) * p->recv_total);
+  L.bucket_cnt = take(sizeof(uint32_t) * CNT_STRIDE * n_nodes_of(p));
+  L.recv_cnt = take(sizeof(uint32_t) * CNT_STRIDE * p->n_partitions);
+  L.flat_cnt = take(sizeof(uint32_t) * CNT_STRIDE * p->n_partitions);
+  L.stage_cnt = take(sizeof(uint32_t) * md * STAGE_BLOCKS);
+  L.bin_cnt = take(sizeof(uint32_t) * D * tiles * md * DELIVER_BLOCKS);
+  L.dirty = take(sizeof(uint32_t) * D * tiles);
   L.stats = take(sizeof(uint64_t) * SNN_NSTAT * uint64_t(p->log_steps));
   L.log_off = take(sizeof(uint64_t) * uint64_t(p->log_steps));
+  // large buffers last: the region before them is zeroed at create
+  L.bucket = take(sizeof(uint64_t) * p->bucket_total);
+  L.recv = take(sizeof(uint64_t) * p->recv_total);
+  L.flat = take(sizeof(uint64_t) * p->recv_total);
+  L.stage = take(sizeof(Event) * md * STAGE_BLOCKS * p->stage_cap);
+  L.bins = take(sizeof(Event) * D * tiles * md * DELIVER_BLOCKS * p->bin_cap);
   L.log = take(sizeof(uint32_t) * p->log_cap);
   L.total = o;
   return L;
@@ -109,6 +106,8 @@ snn_status check_params(const snn_params* p) {
   if ((p->flags & SNN_FORCED_RASTER) && p->raster_period == 0)
     return fail(SNN_ERR_INVALID_ARG, "raster_period must be >= 1");
   if (p->log_steps == 0) return fail(SNN_ERR_INVALID_ARG, "log_steps must be >= 1");
+  if (p->bin_cap > 0xFFFFFFFFull || p->stage_cap > 0xFFFFFFFFull)
+    return fail(SNN_ERR_INVALID_ARG, "bin_cap and stage_cap must fit 32 bits");
   return SNN_OK;
 }
 
@@ -119,7 +118,6 @@ struct snn_ctx {
   snn_network_dev net;
   hipStream_t stream;
   KParams kp;
-  int update_npt;
   int phase;          // 0: expects step, 1: route, 2: deliver
   int route_mode;     // mode of the step in flight
   uint64_t t_host;    // steps enqueued
@@ -148,12 +146,13 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   snn_status s = check_params(params);
   if (s != SNN_OK) return s;
   if (!net) return fail(SNN_ERR_INVALID_ARG, "net is NULL");
-  const void* req[] = {net->row_ptr, net->n_local, net->tgt_delay, net->weight, net->vp_ptr,
-                       net->vp_part, net->vp_seg, net->part_of_neuron, net->bucket_off,
-                       net->recv_off, net->u, net->ref, net->ring};
-  const char* names[] = {"row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part",
-                         "vp_seg", "part_of_neuron", "bucket_off", "recv_off", "u", "ref", "ring"};
-  for (int i = 0; i < 13; ++i)
+  const void* req[] = {net->row_ptr, net->n_local, net->delay_off, net->tgt_delay, net->weight,
+                       net->vp_ptr, net->vp_part, net->vp_seg, net->part_of_neuron,
+                       net->bucket_off, net->recv_off, net->u, net->ref, net->ring};
+  const char* names[] = {"row_ptr", "n_local", "delay_off", "tgt_delay", "weight", "vp_ptr",
+                         "vp_part", "vp_seg", "part_of_neuron", "bucket_off", "recv_off", "u",
+                         "ref", "ring"};
+  for (int i = 0; i < 14; ++i)
     if (!req[i]) return fail(SNN_ERR_INVALID_ARG, "net->%s is NULL", names[i]);
   if ((reinterpret_cast<uintptr_t>(net->u) & 15) || (reinterpret_cast<uintptr_t>(net->ring) & 15) ||
       (reinterpret_cast<uintptr_t>(net->ref) & 3))
@@ -169,13 +168,13 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   c->prm = *params;
   c->net = *net;
   c->stream = static_cast<hipStream_t>(stream);
-  c->update_npt = tuned_update_npt();
   KParams& k = c->kp;
   k.N = params->n_neurons;
   k.P = params->n_partitions;
   k.G = params->gpus_per_node;
   k.D = params->max_delay + 1;
   k.n_nodes = n_nodes_of(params);
+  k.n_tiles = tiles_of(params->n_neurons);
   k.n_ref = params->n_ref;
   k.ring_stride = snn_ring_stride(params->n_neurons);
   k.alpha = params->alpha;
@@ -193,8 +192,11 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.bf16 = params->weight_type == SNN_W_BF16 ? 1u : 0u;
   k.log_steps = params->log_steps;
   k.log_cap = params->log_cap;
+  k.bin_cap = params->bin_cap;
+  k.stage_cap = params->stage_cap;
   k.row_ptr = net->row_ptr;
   k.n_local = net->n_local;
+  k.delay_off = net->delay_off;
   k.tgt_delay = net->tgt_delay;
   k.weight = net->weight;
   k.vp_ptr = net->vp_ptr;
@@ -213,20 +215,24 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.bucket_cnt = reinterpret_cast<uint32_t*>(ws + L.bucket_cnt);
   k.bucket = reinterpret_cast<uint64_t*>(ws + L.bucket);
   k.recv_cnt = reinterpret_cast<uint32_t*>(ws + L.recv_cnt);
-  k.recv = reinterpret_cast<uint32_t*>(ws + L.recv);
+  k.recv = reinterpret_cast<uint64_t*>(ws + L.recv);
   k.flat_cnt = reinterpret_cast<uint32_t*>(ws + L.flat_cnt);
-  k.flat = reinterpret_cast<uint32_t*>(ws + L.flat);
+  k.flat = reinterpret_cast<uint64_t*>(ws + L.flat);
+  k.stage_cnt = reinterpret_cast<uint32_t*>(ws + L.stage_cnt);
+  k.stage = reinterpret_cast<Event*>(ws + L.stage);
+  k.bin_cnt = reinterpret_cast<uint32_t*>(ws + L.bin_cnt);
+  k.dirty = reinterpret_cast<uint32_t*>(ws + L.dirty);
+  k.bins = reinterpret_cast<Event*>(ws + L.bins);
   k.stats = reinterpret_cast<uint64_t*>(ws + L.stats);
   k.log_off = reinterpret_cast<uint64_t*>(ws + L.log_off);
   k.log = reinterpret_cast<uint32_t*>(ws + L.log);
-  // Only the small regions need zeros: state, look-back words, counters.
+  // Everything before the large buffers starts at zero: state, look-back
+  // words, counters (bin counts are read before their first write).
   hipError_t e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(ws + L.recv_cnt, 0, L.recv - L.recv_cnt, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(ws + L.flat_cnt, 0, L.flat - L.flat_cnt, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(ws + L.stats, 0, L.log - L.stats, c->stream);
+  if (e == hipSuccess) e = prepare_kernels(k);
   if (e != hipSuccess) {
     delete c;
-    return fail(SNN_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    return fail(SNN_ERR_HIP, "create: %s", hipGetErrorString(e));
   }
   *out = c;
   return SNN_OK;
@@ -235,7 +241,7 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
 snn_status snn_step(snn_handle h) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
   if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_step called before snn_deliver");
-  HIP_TRY(launch_update(h->kp, h->update_npt, h->stream));
+  HIP_TRY(launch_update(h->kp, h->stream));
   h->phase = 1;
   return SNN_OK;
 }
@@ -269,7 +275,7 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
   if (n_steps == 0) return SNN_OK;
   if (!use_graph) {
     for (uint32_t i = 0; i < n_steps; ++i) {
-      HIP_TRY(launch_update(h->kp, h->update_npt, h->stream));
+      HIP_TRY(launch_update(h->kp, h->stream));
       HIP_TRY(launch_route(h->kp, mode, h->stream));
       HIP_TRY(launch_deliver(h->kp, mode, h->stream));
     }
@@ -277,7 +283,7 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
     if (!h->graph[mode]) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e1 = launch_update(h->kp, h->update_npt, h->stream);
+      hipError_t e1 = launch_update(h->kp, h->stream);
       hipError_t e2 = e1 == hipSuccess ? launch_route(h->kp, mode, h->stream) : e1;
       hipError_t e3 = e2 == hipSuccess ? launch_deliver(h->kp, mode, h->stream) : e2;
       hipError_t ec = hipStreamEndCapture(h->stream, &g);
@@ -301,10 +307,18 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
   return SNN_OK;
 }
 
-static snn_status sync_and_check(snn_handle h) {
+snn_status snn_flush(snn_handle h) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_flush called in the middle of a step");
+  HIP_TRY(launch_flush(h->kp, h->stream));
+  return SNN_OK;
+}
+
+static snn_status sync_and_check(snn_handle h, DevState* out = nullptr) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   DevState st;
   HIP_TRY(hipMemcpy(&st, h->kp.st, sizeof(st), hipMemcpyDeviceToHost));
+  if (out) *out = st;
   if (st.error & ERR_ROUTE)
     return fail(SNN_ERR_HIP, "receive entry without a matching destination partition");
   if (st.error)
@@ -319,6 +333,14 @@ snn_status snn_sync(snn_handle h) {
 }
 
 uint64_t snn_time(snn_handle h) { return h ? h->t_host : 0; }
+
+snn_status snn_ring_events(snn_handle h, uint64_t* n) {
+  if (!h || !n) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  DevState st;
+  snn_status s = sync_and_check(h, &st);
+  *n = st.ring_events;
+  return s;
+}
 
 snn_status snn_read_counters(snn_handle h, uint64_t first_step, uint32_t n_steps, uint64_t* out) {
   if (!h || (!out && n_steps)) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
@@ -397,31 +419,30 @@ snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entri
   snn_status s = sync_and_check(h);
   if (s != SNN_OK) return s;
   const uint32_t nl = which == 2 ? h->kp.n_nodes : h->kp.P;
-  std::vector<uint32_t> cnt(nl);
+  std::vector<uint32_t> cnt(uint64_t(nl) * CNT_STRIDE);
   std::vector<uint64_t> off(nl + 1);
   const uint32_t* cnt_dev = which == 0 ? h->kp.flat_cnt : which == 1 ? h->kp.recv_cnt : h->kp.bucket_cnt;
   const uint64_t* off_dev = which == 2 ? h->kp.bucket_off : h->kp.recv_off;
-  HIP_TRY(hipMemcpy(cnt.data(), cnt_dev, nl * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(cnt.data(), cnt_dev, cnt.size() * 4, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(off.data(), off_dev, (nl + 1) * 8, hipMemcpyDeviceToHost));
   uint64_t total = 0;
   for (uint32_t i = 0; i < nl; ++i) {
-    sizes[i] = cnt[i];
-    total += cnt[i];
+    sizes[i] = cnt[uint64_t(i) * CNT_STRIDE];
+    total += sizes[i];
   }
   *n_entries = total;
   if (!entries) return SNN_OK;
   if (total > cap) return fail(SNN_ERR_CAPACITY, "%llu entries do not fit cap %llu",
                                (unsigned long long)total, (unsigned long long)cap);
-  const size_t el = which == 2 ? 8 : 4;
   const char* base = which == 0 ? reinterpret_cast<const char*>(h->kp.flat)
                      : which == 1 ? reinterpret_cast<const char*>(h->kp.recv)
                                   : reinterpret_cast<const char*>(h->kp.bucket);
   uint64_t at = 0;
   for (uint32_t i = 0; i < nl; ++i) {
-    if (!cnt[i]) continue;
-    HIP_TRY(hipMemcpyAsync(static_cast<char*>(entries) + at * el, base + off[i] * el, cnt[i] * el,
+    if (!sizes[i]) continue;
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(entries) + at * 8, base + off[i] * 8, sizes[i] * 8,
                            hipMemcpyDeviceToHost, h->stream));
-    at += cnt[i];
+    at += sizes[i];
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
   return SNN_OK;

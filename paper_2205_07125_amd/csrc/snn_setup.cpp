@@ -164,10 +164,12 @@ snn_status snn_setup_sizes(snn_setup_handle h, uint64_t* nnz, uint64_t* pairs,
 }
 
 snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n_local,
-                               uint32_t* tgt_delay, void* weight) {
-  if (!h || !row_ptr || !n_local || !tgt_delay || !weight)
+                               uint16_t* delay_off, uint32_t* tgt_delay, void* weight) {
+  if (!h || !row_ptr || !n_local || !delay_off || !tgt_delay || !weight)
     return fail(SNN_ERR_INVALID_ARG, "NULL argument");
   const uint32_t N = h->N, K = h->spec.k_in, P = h->P, G = h->G, n_nodes = h->n_nodes;
+  const uint32_t md = h->spec.max_delay;
+  int too_long = 0;
   const bool bf16 = h->spec.weight_type == SNN_W_BF16;
   try {
     h->tag.assign(h->nnz, 0);
@@ -249,8 +251,19 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
       }
       n_local[s] = nl;
       h->n_vp[s] = nv;
+      // the own-partition part is sorted by delay: offsets of each delay's run
+      if (nl > 0xFFFFu) __atomic_store_n(&too_long, 1, __ATOMIC_RELAXED);
+      uint16_t* doff = delay_off + uint64_t(s) * (md + 1);
+      uint32_t pos = 0;
+      for (uint32_t d = 1; d <= md; ++d) {
+        doff[d - 1] = uint16_t(pos);
+        while (pos < nl && (tgt_delay[r0 + pos] >> 27) == d) ++pos;
+      }
+      doff[md] = uint16_t(nl);
     }
   }
+  if (too_long)
+    return fail(SNN_ERR_UNSUPPORTED, "a source has 65536 or more own-partition synapses");
   h->bucket_cap.assign(n_nodes, 0);
   h->recv_cap.assign(P, 0);
   for (int th = 0; th < h->threads; ++th) {

@@ -18,6 +18,30 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_P)
 
 
+TILE = 1 << 14            # neurons per tile (update block, delivery bin)
+DELIVER_BLOCKS = 32      # delivery blocks per delay
+STAGE_BLOCKS = 256       # receive-side blocks
+
+
+def default_caps(wl, host) -> tuple[int, int]:
+    """Bin and staging capacities sized at four times the expected events per
+    bin at the workload's highest rate (50 Hz assumed for LIF-driven spikes);
+    events beyond them take the dense-ring path, so these set speed, not
+    correctness."""
+    rate = max(wl.rate_on_hz, wl.rate_off_hz) if wl.forced else 50.0
+    spikes = wl.n_neurons * rate * wl.dt_ms * 1e-3
+    outdeg = host.nnz / max(wl.n_neurons, 1)
+    local = float(host.n_local.sum()) / max(wl.n_neurons, 1)
+    e_local = spikes * local
+    e_remote = spikes * (outdeg - local)
+    md = wl.max_delay
+    tiles = (wl.n_neurons + TILE - 1) // TILE
+    per_bin = (e_local + e_remote) / (md * DELIVER_BLOCKS * tiles)
+    per_queue = e_remote / (md * STAGE_BLOCKS)
+    rnd = lambda x: int(-(-(4 * x + 64) // 32) * 32)
+    return rnd(per_bin), rnd(per_queue)
+
+
 def derived_params(wl) -> dict:
     """Constants the kernels take ready-made: the per-step decay factor
     fl32(exp(-dt / tau_m)), the Poisson inversion table floor(2^32 CDF(j))
@@ -73,11 +97,13 @@ class HostNetwork:
                       flush=True)
             self.row_ptr = np.empty(N + 1, np.int64)
             self.n_local = np.empty(N, np.uint32)
+            self.delay_off = np.empty(N * (wl.max_delay + 1), np.uint16)
             self.tgt_delay = np.empty(nnz, np.uint32)
             self.weight = np.empty(nnz, np.uint16 if wl.weight_type == "bf16" else np.float32)
             t1 = time.time()
             _abi.check(L.snn_setup_fill_rows(h, _ptr(self.row_ptr), _ptr(self.n_local),
-                                             _ptr(self.tgt_delay), _ptr(self.weight)))
+                                             _ptr(self.delay_off), _ptr(self.tgt_delay),
+                                             _ptr(self.weight)))
             _abi.check(L.snn_setup_sizes(h, *[ctypes.byref(s) for s in sizes]))
             pairs, self.bucket_total, self.recv_total = (s.value for s in sizes[1:])
             if verbose:
@@ -99,6 +125,7 @@ class HostNetwork:
         self.setup_seconds = time.time() - t0
 
     def host_bytes(self) -> int:
-        return sum(a.nbytes for a in (self.row_ptr, self.n_local, self.tgt_delay, self.weight,
+        return sum(a.nbytes for a in (self.row_ptr, self.n_local, self.delay_off, self.tgt_delay,
+                                      self.weight,
                                       self.vp_ptr, self.vp_part, self.vp_seg, self.part,
                                       self.bucket_off, self.recv_off))

@@ -8,7 +8,7 @@ import ctypes
 import numpy as np
 
 from . import _abi
-from .network import HostNetwork, derived_params
+from .network import HostNetwork, default_caps, derived_params
 
 
 def _dev(torch, a: np.ndarray, device):
@@ -23,7 +23,8 @@ def _dev(torch, a: np.ndarray, device):
 class Simulation:
     def __init__(self, wl, host: HostNetwork | None = None, device: str = "cuda",
                  log_steps: int | None = None, log_cap: int | None = None,
-                 bucket_off=None, recv_off=None, verbose: bool = False):
+                 bucket_off=None, recv_off=None, bin_cap: int | None = None,
+                 stage_cap: int | None = None, verbose: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the simulation runs only in libsnn's HIP kernels")
@@ -45,6 +46,7 @@ class Simulation:
         d = lambda a: _dev(torch, a, self.device)
         self.t_row_ptr = d(host.row_ptr)
         self.t_n_local = d(host.n_local)
+        self.t_delay_off = d(host.delay_off)
         self.t_tgt_delay = d(host.tgt_delay)
         self.t_weight = d(host.weight)
         self.t_vp_ptr = d(host.vp_ptr)
@@ -59,6 +61,9 @@ class Simulation:
         self.ring = torch.zeros(D * self.ring_stride, dtype=torch.float32, device=self.device)
 
         dp = derived_params(wl)
+        cb, cs = default_caps(wl, host)
+        bin_cap = cb if bin_cap is None else bin_cap
+        stage_cap = cs if stage_cap is None else stage_cap
         forced = bool(wl.forced)
         if log_steps is None:
             log_steps = max(wl.n_steps, 1)
@@ -74,13 +79,14 @@ class Simulation:
             raster_thr_on=dp["raster_thr_on"], raster_thr_off=dp["raster_thr_off"],
             raster_period=max(wl.period_steps, 1), raster_on=wl.on_steps,
             bucket_total=int(bucket_off[-1]), recv_total=int(recv_off[-1]),
-            log_steps=log_steps, log_cap=log_cap)
+            log_steps=log_steps, log_cap=log_cap, bin_cap=bin_cap, stage_cap=stage_cap)
         self.ws_bytes = _abi.snn_workspace_size(self.params)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self.ws_ptr = (base + 255) & ~255
         self.net = _abi.snn_network_dev(
             row_ptr=self.t_row_ptr.data_ptr(), n_local=self.t_n_local.data_ptr(),
+            delay_off=self.t_delay_off.data_ptr(),
             tgt_delay=self.t_tgt_delay.data_ptr(), weight=self.t_weight.data_ptr(),
             vp_ptr=self.t_vp_ptr.data_ptr(), vp_part=self.t_vp_part.data_ptr(),
             vp_seg=self.t_vp_seg.data_ptr(), part_of_neuron=self.t_part.data_ptr(),
@@ -114,6 +120,12 @@ class Simulation:
     def sync(self):
         _abi.snn_sync(self.h)
 
+    def flush(self):
+        _abi.snn_flush(self.h)
+
+    def ring_events(self) -> int:
+        return _abi.snn_ring_events(self.h)
+
     @property
     def t(self) -> int:
         return _abi.snn_time(self.h)
@@ -131,18 +143,21 @@ class Simulation:
                                      counts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
         return ids[:n.value], counts
 
-    def read_routes(self, which: int):
-        """which 0 flat lists, 1 expanded lists (-> list of uint32 arrays per
-        partition), 2 node buckets (-> list of uint64 arrays per node)."""
+    def read_routes(self, which: int, sources_only: bool = False):
+        """which 0 flat lists, 1 expanded lists (per partition), 2 node buckets
+        (per node); uint64 elements (see include/snn.h), or just the source ids
+        (low 32 bits) with sources_only."""
         L = _abi.lib()
         nl = self.wl.n_nodes if which == 2 else self.wl.n_partitions
         sizes = np.zeros(nl, np.uint64)
         n = ctypes.c_uint64()
         _abi.check(L.snn_read_routes(self.h, which, sizes.ctypes.data_as(ctypes.c_void_p), None, 0,
                                      ctypes.byref(n)))
-        ent = np.zeros(max(n.value, 1), np.uint64 if which == 2 else np.uint32)
+        ent = np.zeros(max(n.value, 1), np.uint64)
         _abi.check(L.snn_read_routes(self.h, which, sizes.ctypes.data_as(ctypes.c_void_p),
                                      ent.ctypes.data_as(ctypes.c_void_p), ent.size, ctypes.byref(n)))
+        if sources_only:
+            ent = (ent & np.uint64(0xFFFFFFFF)).astype(np.uint32)
         offs = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
         return [ent[offs[i]:offs[i + 1]].copy() for i in range(nl)]
 
@@ -153,7 +168,10 @@ class Simulation:
         return out
 
     def state(self) -> dict:
-        """u, ref and the ring (D x N) as host arrays, after the stream drains."""
+        """u, ref and the ring (D x N) as host arrays.  Pending binned events
+        are first moved into the ring (snn_flush), so the ring holds all input
+        scheduled for the coming steps."""
+        self.flush()
         self.sync()
         D, N = self.wl.max_delay + 1, self.wl.n_neurons
         ring = self.ring.view(D, self.ring_stride)[:, :N].cpu().numpy()

@@ -98,3 +98,21 @@ def test_empty_steps():
     ids, counts = sim.read_spikes(0, 20)
     assert len(ids) == 0 and np.all(counts == 0)
     assert all(len(x) == 0 for x in sim.read_routes(1))
+
+
+@pytest.mark.parametrize("bin_cap,stage_cap", [(0, 0), (2, 1)])
+def test_dense_ring_fallback_is_exact(bin_cap, stage_cap):
+    """With no (or tiny) bin and staging capacity every event takes the dense
+    ring path; the result is the same as with the bins."""
+    wl = synth.get_workload("tiny_active")
+    a = Simulation(wl, log_steps=150)
+    b = Simulation(wl, log_steps=150, bin_cap=bin_cap, stage_cap=stage_cap)
+    a.run(150, _abi.SNN_ROUTE_TWO_LEVEL, use_graph=False)
+    b.run(150, _abi.SNN_ROUTE_TWO_LEVEL, use_graph=False)
+    assert b.ring_events() > 0
+    sa, sb = a.state(), b.state()
+    for k in ("u", "ref", "ring"):
+        assert np.array_equal(sa[k], sb[k]), k
+    ia, _ = a.read_spikes(0, 150)
+    ib, _ = b.read_spikes(0, 150)
+    assert np.array_equal(ia, ib)

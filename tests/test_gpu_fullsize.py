@@ -76,7 +76,9 @@ def test_paper_share_full_size_sampled():
     print(f"[gpu] {len(sample)} sampled neurons exact ({spiking} of them fired)", flush=True)
 
     # 4. routes of the last step (properties that hold at any size)
-    flat, xrecv, buckets = sim.read_routes(0), sim.read_routes(1), sim.read_routes(2)
+    flat = sim.read_routes(0, sources_only=True)
+    xrecv = sim.read_routes(1, sources_only=True)
+    buckets = sim.read_routes(2)
     for p in range(wl.n_partitions):
         assert np.array_equal(np.sort(flat[p]), np.sort(xrecv[p])), f"partition {p}"
     fired = ids[offs[T - 1]:offs[T]]

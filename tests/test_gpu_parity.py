@@ -38,13 +38,23 @@ def _same_state(sim, orc, where):
 
 
 def _same_routes(sim, orc, wl, where):
-    flat_g, x_g, b_g = sim.read_routes(0), sim.read_routes(1), sim.read_routes(2)
+    flat_e, x_e, b_g = sim.read_routes(0), sim.read_routes(1), sim.read_routes(2)
     flat_o, x_o, b_o = orc.recv(0), orc.recv(1), orc.buckets()
+    lo32 = np.uint64(0xFFFFFFFF)
+    host = sim.host
     for p in range(wl.n_partitions):
-        assert np.array_equal(np.sort(flat_g[p]), np.sort(flat_o[p])), f"flat {p} at {where}"
-        assert np.array_equal(np.sort(x_g[p]), np.sort(x_o[p])), f"expanded {p} at {where}"
+        fg = (flat_e[p] & lo32).astype(np.uint32)
+        xg = (x_e[p] & lo32).astype(np.uint32)
+        assert np.array_equal(np.sort(fg), np.sort(flat_o[p])), f"flat {p} at {where}"
+        assert np.array_equal(np.sort(xg), np.sort(x_o[p])), f"expanded {p} at {where}"
+        # the routing-table index each entry carries names partition p
+        for ent in (flat_e[p], x_e[p]):
+            if len(ent) and host is not None:
+                s = (ent & lo32).astype(np.int64)
+                j = host.vp_ptr[s] + (ent >> np.uint64(32)).astype(np.int64)
+                assert np.all(j < host.vp_ptr[s + 1]) and np.all(host.vp_part[j] == p)
     for n in range(wl.n_nodes):
-        # device messages carry an implementation index above bit 40
+        # device messages carry the first destination's list index above bit 40
         g = np.sort(b_g[n] & np.uint64((1 << 40) - 1))
         assert np.array_equal(g, np.sort(b_o[n])), f"bucket {n} at {where}"
 
