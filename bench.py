@@ -40,27 +40,6 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def phase_times(sim, steps, mode, torch):
-    """Average duration (ms) of the update, route and deliver phases, each
-    bracketed by HIP events on the simulation stream (eager launches)."""
-    s = sim.stream
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-    for i in range(steps):
-        ev[i][0].record(s)
-        sim.step()
-        ev[i][1].record(s)
-        sim.route(mode)
-        ev[i][2].record(s)
-        sim.deliver()
-        ev[i][3].record(s)
-    s.synchronize()
-    tot = [0.0, 0.0, 0.0]
-    for i in range(steps):
-        for k in range(3):
-            tot[k] += ev[i][k].elapsed_time(ev[i][k + 1])
-    return [x / steps for x in tot]
-
-
 def cpu_baseline(wl_full, seconds_budget=20.0):
     """The oracle (single-threaded C, FP64 + binary32 trajectories) on the same
     structure at 1/100 of the neurons (same in-degree, partitions, rate)."""
@@ -157,24 +136,38 @@ def main():
     log(f"timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), "
         f"{spikes / args.steps:.0f} spikes/step, {events / args.steps:,.0f} events/step")
 
-    # per-phase breakdown, eager launches bracketed by events on the stream
-    ph = phase_times(sim, args.phase_steps, mode, torch)
+    # per-kernel durations: eager steps, every kernel bracketed by HIP events
+    # on the simulation stream (the stream all kernels are launched on)
+    kt = sim.kernel_times(args.phase_steps, mode)
     pc = sim.read_counters(args.warmup + args.steps, args.phase_steps).astype(np.float64)
-    log(f"phases (ms/step): update {ph[0]:.4f}  route {ph[1]:.4f}  deliver {ph[2]:.4f}")
+    log("kernels (ms): " + "  ".join(f"{k} {v:.4f}" for k, v in kt.items() if v > 0))
     N = wl.n_neurons
     bw = 2 if wl.weight_type == "bf16" else 4
-    ph_events = (pc[:, 1].sum() + pc[:, 2].sum()) / args.phase_steps
-    # algorithmic bytes per launch:
-    #   update: ring slot read + clear (8), u read + write (8), ref read + write (2)
-    #   deliver: CSR target+delay (4) and weight (bw) per delivered synapse
-    bytes_update = 18.0 * N
-    bytes_deliver = ph_events * (4 + bw)
-    cand = {
-        "update": (bytes_update, ph[0]),
-        "deliver": (bytes_deliver, ph[2]),
+    per = pc.mean(axis=0)
+    spk, e_loc, e_rem, m2 = per[0], per[1], per[2], per[3] + per[4]
+    pairs = per[5] if mode == SNN_ROUTE_FLAT else per[6]   # (source, destination partition)
+    # algorithmic HBM bytes per launch, per kernel (what the method must move):
+    #   update      18 B per neuron: input slot read + clear 8, u read + write 8,
+    #               refractory count read + write 2
+    #   route       2 B per destination-list entry read, 8 B per message written
+    #               (flat: 2 B read + 4 B per entry written)
+    #   expand      8 B per message read, 4 B per receive entry written
+    #   recv_stage  4 B per receive entry read + 4 B segment index, and (4 + b_w) B
+    #               per remote synapse (target/delay + weight)
+    #   deliver     (4 + b_w) B per own-partition synapse
+    alg = {
+        "update": 18.0 * N,
+        "route_two_level": 2.0 * pairs + 8.0 * m2,
+        "expand": 8.0 * m2 + 4.0 * pairs,
+        "route_flat": 6.0 * pairs,
+        "recv_stage": 8.0 * pairs + (4 + bw) * e_rem,
+        "deliver": (4 + bw) * e_loc,
     }
-    dom = max(cand, key=lambda k: cand[k][1])
-    b, t_ms = cand[dom]
+    kernels = {k: {"ms": kt[k], "alg_bytes": alg[k],
+                   "gbs": alg[k] / (kt[k] * 1e-3) / 1e9 if kt[k] > 0 else None}
+               for k in kt if kt[k] > 0}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    b, t_ms = kernels[dom]["alg_bytes"], kernels[dom]["ms"]
     achieved = b / (t_ms * 1e-3) / 1e9
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
@@ -184,7 +177,8 @@ def main():
         ent = tj.get(wl.name, {}).get(dom)
         if ent and ent.get("kernel_hash") == kernel_source_hash():
             traffic = ent.get("bytes_per_launch")
-    step_bytes = bytes_update + (events / args.steps) * (4 + bw)
+    # whole step (survey's per-step algorithmic bytes, ring RMW excluded)
+    step_bytes = sum(v["alg_bytes"] for v in kernels.values())
     out = {
         "metric": "synaptic events/s + routed spike msgs/s per GPU; % of HBM peak BW",
         "value": events / sec,
@@ -210,10 +204,11 @@ def main():
                           "two_level_l2": cnt[:, 4].sum() / args.steps,
                           "flat": flat / args.steps},
         "hbm_frac_step": step_bytes / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
-        "phase_ms": {"update": ph[0], "route": ph[1], "deliver": ph[2]},
+        "kernels": kernels,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": b, "avg_launch_ms": t_ms},
+                     "algorithmic_bytes_per_launch": b, "avg_launch_ms": t_ms,
+                     "timing": "HIP events on the launch stream, %d eager steps" % args.phase_steps},
     }
     sim.close()
     del sim

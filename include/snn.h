@@ -109,6 +109,17 @@ enum {
   SNN_NSTAT = 7
 };
 
+/* Kernel kinds of a step, in launch order (snn_kernel_times). */
+enum {
+  SNN_KERNEL_UPDATE = 0,           /* neuron update, threshold, compaction */
+  SNN_KERNEL_ROUTE_TWO_LEVEL = 1,  /* per-node messages with partition masks */
+  SNN_KERNEL_EXPAND = 2,           /* mask expansion into receive lists */
+  SNN_KERNEL_ROUTE_FLAT = 3,       /* one entry per destination partition */
+  SNN_KERNEL_RECV_STAGE = 4,       /* receive side: synapses per entry, by delay */
+  SNN_KERNEL_DELIVER = 5,          /* binning of local and received synapses */
+  SNN_NKERNEL = 6
+};
+
 /* Largest supported sizes. */
 #define SNN_MAX_GPUS_PER_NODE 8u
 #define SNN_MAX_DELAY 15u
@@ -210,8 +221,9 @@ snn_status snn_route(snn_handle h, int mode);
 snn_status snn_deliver(snn_handle h);
 
 /* n_steps full steps (step, route(mode), deliver).  use_graph != 0 captures
-   one step into a HIP graph once and replays it (all step-dependent values
-   live in device memory).  Order: as snn_step. */
+   HIP graphs of 16 steps and of one step once per mode and replays them
+   (16-step replays first, then single steps for the remainder; all
+   step-dependent values live in device memory).  Order: as snn_step. */
 snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph);
 
 /* Moves every pending binned synaptic event into the dense ring, so that the
@@ -225,6 +237,14 @@ snn_status snn_sync(snn_handle h);
 /* Events that took the dense-ring path so far (a bin or a staging queue was
    full).  Synchronises. */
 snn_status snn_ring_events(snn_handle h, uint64_t* n);
+
+/* Measurement aid: runs n_steps ordinary whole steps (route mode `mode`) as
+   separate launches, each kernel bracketed by HIP events recorded on the
+   handle's stream, and writes the average duration in milliseconds of each
+   kernel kind to avg_ms[SNN_NKERNEL] (0 for kinds the mode does not launch).
+   The steps advance the simulation like snn_run.  Synchronises.  Order: as
+   snn_step. */
+snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg_ms);
 
 /* Steps completed so far (host-side count of enqueued steps). */
 uint64_t snn_time(snn_handle h);

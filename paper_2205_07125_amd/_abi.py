@@ -26,10 +26,13 @@ SNN_FORCED_RASTER = 1
 STAT_NAMES = ["spikes", "local_events", "remote_events", "msg_l1", "msg_l2", "flat_msgs",
               "recv_entries"]
 SNN_NSTAT = len(STAT_NAMES)
+KERNEL_NAMES = ["update", "route_two_level", "expand", "route_flat", "recv_stage", "deliver"]
+SNN_NKERNEL = len(KERNEL_NAMES)
 
 EXPORTED = [
     "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route",
-    "snn_deliver", "snn_run", "snn_flush", "snn_sync", "snn_time", "snn_ring_events",
+    "snn_deliver", "snn_run", "snn_kernel_times", "snn_flush", "snn_sync", "snn_time",
+    "snn_ring_events",
     "snn_read_spikes", "snn_read_routes",
     "snn_read_counters", "snn_destroy", "snn_last_error",
     "snn_setup_create", "snn_setup_sizes", "snn_setup_fill_rows", "snn_setup_fill_routes",
@@ -84,6 +87,12 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python paper_2205_07125_amd/build.py` (or __graft_entry__.build())")
+        # One HIP runtime per process: torch (which owns the device memory and
+        # streams) ships its own libamdhip64 and asks for it under another
+        # name, so it is loaded first; the library's libamdhip64.so.7 then
+        # resolves to the same copy.  Loaded the other way round, the process
+        # would hold two runtimes and the second finds no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         I = ctypes.c_int
         sig = {
@@ -95,6 +104,7 @@ def lib() -> ctypes.CDLL:
             "snn_route": (I, [vp, I]),
             "snn_deliver": (I, [vp]),
             "snn_run": (I, [vp, u32, I, I]),
+            "snn_kernel_times": (I, [vp, u32, I, vp]),
             "snn_flush": (I, [vp]),
             "snn_sync": (I, [vp]),
             "snn_ring_events": (I, [vp, ctypes.POINTER(u64)]),
@@ -157,6 +167,13 @@ def snn_deliver(h):
 
 def snn_run(h, n_steps: int, mode: int, use_graph: bool):
     check(lib().snn_run(h, n_steps, mode, 1 if use_graph else 0))
+
+
+def snn_kernel_times(h, n_steps: int, mode: int):
+    """-> list of SNN_NKERNEL average kernel durations (ms)."""
+    out = (f32 * SNN_NKERNEL)()
+    check(lib().snn_kernel_times(h, n_steps, mode, out))
+    return [float(x) for x in out]
 
 
 def snn_flush(h):

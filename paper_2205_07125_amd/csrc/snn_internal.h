@@ -46,19 +46,34 @@ enum : uint32_t { STREAM_POISSON = 1u, STREAM_RASTER = 2u };
 // synaptic events are binned per (ring slot, tile).
 constexpr int TILE_SHIFT = 14;
 constexpr uint32_t TILE = 1u << TILE_SHIFT;         // 16384 neurons
-constexpr int UPDATE_THREADS = 1024;
-constexpr int UPDATE_NPT = TILE / UPDATE_THREADS;   // 16 neurons per thread
+constexpr int UPDATE_THREADS = 512;
+constexpr int UPDATE_NPT = TILE / UPDATE_THREADS;   // 32 neurons per thread
 constexpr int ROUTE_THREADS = 256;
 constexpr int DELIVER_THREADS = 512;
 constexpr uint32_t CNT_STRIDE = 16;                 // counters padded to 64 bytes
 constexpr uint32_t ROUTE_STAGE = 4096;              // staged messages / entries per round
-constexpr uint32_t ROUTE_BLOCKS = 128;              // two-level routing blocks
+constexpr uint32_t ROUTE_BLOCKS = 256;              // two-level routing blocks
 constexpr uint32_t ROUTE_MAX_NODES_LDS = 8192;      // more nodes: unstaged routing
-constexpr uint32_t EXPAND_BLOCKS = 4;               // expansion blocks per node
-constexpr uint32_t DELIVER_STAGE = 6144;            // staged events per round
+constexpr int EXPAND_THREADS = 512;                 // one expansion block per node
+constexpr uint32_t DELIVER_STAGE = 4096;            // staged events per window
 constexpr uint32_t DELIVER_BLOCKS = 32;             // deliver blocks per delay
 constexpr uint32_t STAGE_BLOCKS = 256;              // receive-side blocks (one queue each)
-constexpr uint32_t STAGE_PARTS = (SNN_MAX_PARTITIONS + STAGE_BLOCKS - 1) / STAGE_BLOCKS;
+constexpr uint32_t STAGE_PARTS = 256;               // partitions per receive-side block, at most
+static_assert(STAGE_PARTS * STAGE_BLOCKS >= SNN_MAX_PARTITIONS, "receive blocks must cover P");
+static_assert(STAGE_BLOCKS % DELIVER_BLOCKS == 0, "deliver blocks split the queues evenly");
+constexpr int RECV_THREADS = 512;
+constexpr uint32_t RECV_PER_THREAD = 4;                         // entries per thread per batch
+constexpr uint32_t RECV_BATCH = RECV_THREADS * RECV_PER_THREAD; // entries per batch
+static_assert(STAGE_PARTS <= RECV_THREADS, "one partition count per thread");
+
+// Poisson inversion lookup: entry b covers draws r in [b << POIS_LUT_SHIFT,
+// (b + 1) << POIS_LUT_SHIFT).  k = #{j : thr[j] <= r} is the entry itself
+// when no threshold lies inside that range (entry < 16); with exactly one,
+// thr[j] with j = entry - 16, it is j + (r >= thr[j]); POIS_LUT_SLOW marks
+// ranges holding several thresholds, where the kernel counts all 15.
+constexpr int POIS_LUT_SHIFT = 19;
+constexpr uint32_t POIS_LUT_SIZE = 1u << (32 - POIS_LUT_SHIFT);   // 8192 one-byte entries
+constexpr uint8_t POIS_LUT_SLOW = 255;
 
 // A binned synaptic event: target index inside its tile and weight.
 struct Event {
@@ -74,6 +89,7 @@ struct KParams {
   uint64_t ring_stride;
   float alpha, theta, u_reset, w_ext;
   uint32_t thr[15];
+  const uint8_t* pois_lut;   // [POIS_LUT_SIZE] (workspace)
   uint32_t seed_lo, seed_hi;
   uint32_t forced, raster_on_thr, raster_off_thr, raster_period, raster_on;
   uint32_t bf16;
@@ -117,11 +133,13 @@ struct KParams {
 };
 
 // Launchers (snn_kernels.hip); all enqueue on `s` and return the launch error.
+// With non-null marks, events marks[2k], marks[2k + 1] are recorded around
+// each launch of kernel kind k (SNN_KERNEL_*).
 uint32_t tiles_of(uint32_t n);
 hipError_t prepare_kernels(const KParams& p);   // dynamic-LDS limits, once per handle
-hipError_t launch_update(const KParams& p, hipStream_t s);
-hipError_t launch_route(const KParams& p, int mode, hipStream_t s);
-hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s);
+hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks = nullptr);
+hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr);
+hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr);
 hipError_t launch_flush(const KParams& p, hipStream_t s);
 
 }  // namespace snn

@@ -30,19 +30,21 @@ namespace snn {
 // helpers
 
 // Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
-// multiply-xor S-box with a Weyl-bumped key.
+// multiply-xor S-box with a Weyl-bumped key.  Each product is written as one
+// 32x32->64 multiply so that it maps to a single v_mad_u64_u32 (high and low
+// halves together) instead of separate mul_hi / mul_lo instructions.
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = static_cast<uint32_t>(p1);
     c2 = n2;
-    c3 = lo0;
+    c3 = static_cast<uint32_t>(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -80,10 +82,65 @@ __device__ __forceinline__ float load_weight(const KParams& p, uint64_t e) {
   return static_cast<const float*>(p.weight)[e];
 }
 
-// Adds a per-thread counter into a global u64 with one atomic per wave.
-__device__ __forceinline__ void add_stat(uint64_t* dst, uint64_t v) {
-  v = wave_sum64(v);
-  if ((threadIdx.x & 63) == 0 && v) atomicAdd(reinterpret_cast<unsigned long long*>(dst), v);
+// Adds the block's sum of two per-thread counters into two global u64s with
+// one atomic each per block (atomics on one address serialise, so a block
+// sums first).  Every thread of the block calls it; s_red holds 2 * waves.
+__device__ void add_stats(uint64_t* dst0, uint64_t v0, uint64_t* dst1, uint64_t v1,
+                          uint64_t* s_red) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v0 = wave_sum64(v0);
+  v1 = wave_sum64(v1);
+  __syncthreads();
+  if (lane == 0) {
+    s_red[2 * wave] = v0;
+    s_red[2 * wave + 1] = v1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t a = 0, b = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      a += s_red[2 * w];
+      b += s_red[2 * w + 1];
+    }
+    if (a && dst0) atomicAdd(reinterpret_cast<unsigned long long*>(dst0), a);
+    if (b && dst1) atomicAdd(reinterpret_cast<unsigned long long*>(dst1), b);
+  }
+}
+
+__device__ __forceinline__ void add_stat(uint64_t* dst, uint64_t v, uint64_t* s_red) {
+  add_stats(dst, v, nullptr, 0, s_red);
+}
+
+// Exclusive prefix sum of one value per thread over the block; *total gets
+// the block total.  s_wsum holds one word per wave.  Every thread calls it.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wsum, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  __syncthreads();
+  if (lane == 63) s_wsum[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (uint32_t w = 0; w < nw; ++w) {
+    const uint32_t x = s_wsum[w];
+    before += w < wave ? x : 0u;
+    tot += x;
+  }
+  *total = tot;
+  return before + incl - v;
+}
+
+// Largest k < n with pre[k] <= e, for a non-decreasing pre with pre[0] = 0:
+// the segment that holds element e of a concatenation whose segment starts
+// are pre.  TOP is a power of two with 2 * TOP >= n (the steps reach 2 * TOP - 1).
+template <uint32_t TOP>
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* pre, uint32_t n, uint32_t e) {
+  uint32_t k = 0;
+#pragma unroll
+  for (uint32_t step = TOP; step; step >>= 1) {
+    const uint32_t m = k + step;
+    if (m < n && pre[m] <= e) k = m;
+  }
+  return k;
 }
 
 // An event that does not fit its bin goes to the dense ring; the tile is
@@ -103,6 +160,14 @@ __device__ __forceinline__ uint64_t subbin(const KParams& p, uint32_t slot, uint
 
 // ---------------------------------------------------------------------------
 // update: arriving input, neuron update, threshold, ascending compaction
+
+// Sub-bins per (slot, tile) at most, and the top step of the power-of-two
+// search over them.
+constexpr uint32_t MAX_SUBBINS = SNN_MAX_DELAY * DELIVER_BLOCKS;
+constexpr uint32_t SUBBIN_SEARCH_TOP = 256;
+static_assert(2 * SUBBIN_SEARCH_TOP > MAX_SUBBINS, "search must reach every sub-bin");
+static_assert(MAX_SUBBINS <= UPDATE_THREADS, "one sub-bin count per thread");
+constexpr int GATHER_UNROLL = 4;
 
 // Look-back word: [63:34] step tag, [33:32] status, [31:0] count.
 constexpr uint32_t LB_AGG = 1u, LB_INCL = 2u;
@@ -161,17 +226,24 @@ __device__ uint32_t lookback_exclusive(uint64_t* lb, uint32_t b, uint32_t agg, u
   return excl;
 }
 
-// One block per tile.  Thread tid owns 16 neurons as 4 quads: quad q covers
-// tile neurons q*4*UPDATE_THREADS + 4*tid .. +3, so every load and store
-// instruction of a wave touches one contiguous 1 KiB span.  Ids are ordered
-// quad-major across the block, which the compaction follows.
+// One block per tile.  Thread tid owns UPDATE_NPT neurons as UPDATE_NPT / 4
+// quads: quad q covers tile neurons q*4*UPDATE_THREADS + 4*tid .. +3, so
+// every load and store instruction of a wave touches one contiguous 1 KiB
+// span.  Ids are ordered quad-major across the block, which the compaction
+// follows.
+static_assert(UPDATE_NPT % 4 == 0 && UPDATE_NPT <= 32, "fire bits of a thread fit 32 bits");
 __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   constexpr int NQ = UPDATE_NPT / 4;
   constexpr int NW = UPDATE_THREADS / 64;
   __shared__ float s_syn[TILE];
-  __shared__ uint32_t s_cnt[NQ][NW];
-  __shared__ uint32_t s_excl;
+  __shared__ uint32_t s_cnt[NQ][NW];    // spikes per (quad, wave)
+  __shared__ uint32_t s_qoff[NQ][NW];   // their offsets in the block's order
+  __shared__ uint32_t s_wsum[NW];
+  __shared__ uint32_t s_bpre[MAX_SUBBINS + 1];
+  __shared__ uint32_t s_excl, s_btot;
   __shared__ uint32_t s_dirty;
+  __shared__ uint4 s_lut4[POIS_LUT_SIZE / 16];   // Poisson inversion lookup (bytes)
+  __shared__ uint32_t s_thr[16];
 
   // Read once (uniform, so kept in scalar registers): the last block advances
   // the step state when the step is complete.
@@ -203,21 +275,86 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   }
   for (uint32_t i = tid; i < TILE; i += UPDATE_THREADS) s_syn[i] = 0.f;
   if (tid == 0) s_dirty = p.dirty[slot * p.n_tiles + tile];
+  for (uint32_t i = tid; i < POIS_LUT_SIZE / 16; i += UPDATE_THREADS)
+    s_lut4[i] = reinterpret_cast<const uint4*>(p.pois_lut)[i];
+  if (tid < 15) s_thr[tid] = p.thr[tid];
+  const uint8_t* s_lut = reinterpret_cast<const uint8_t*>(s_lut4);
+
+  // State of quad q of the thread's neurons (4 consecutive neurons).  The
+  // branch on a whole tile in range is uniform, so loads carry no divergent
+  // merge; past N a lane reads neuron N - 1 (never stored back, never fires).
+  const bool tile_full = blk0 + TILE <= p.N;
+  auto load_quad = [&](int q, float4& u4, uint32_t& r4) {
+    const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
+    if (tile_full) {
+      u4 = *reinterpret_cast<const float4*>(p.u + i0);
+      r4 = *reinterpret_cast<const uint32_t*>(p.ref + i0);
+    } else {
+      float v[4];
+      uint32_t r = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t ik = min(i0 + k, p.N - 1);
+        v[k] = p.u[ik];
+        r |= static_cast<uint32_t>(p.ref[ik]) << (8 * k);
+      }
+      u4 = make_float4(v[0], v[1], v[2], v[3]);
+      r4 = r;
+    }
+  };
+  // quad 0 is loaded now so that its loads overlap the gather
+  float4 u_next;
+  uint32_t r_next;
+  load_quad(0, u_next, r_next);
   __syncthreads();
 
   // Arriving input of step t: the sub-bins (slot, tile, d, w) written d steps
-  // ago by deliver block w; one wave per sub-bin.
+  // ago by deliver block w.  Their counts are read in one coalesced load and
+  // scanned; the events are then taken as one flat sequence (a power-of-two
+  // search over the scanned counts finds an event's sub-bin), GATHER_UNROLL
+  // loads in flight per thread.
   const uint32_t md = p.D - 1;
   const uint32_t n_sub = md * DELIVER_BLOCKS;
   const uint64_t sb0 = subbin(p, slot, tile, 1, 0);
-  for (uint32_t k = wave; k < n_sub; k += NW) {
-    const uint64_t sb = sb0 + k;
-    const uint32_t c = min(p.bin_cnt[sb], static_cast<uint32_t>(p.bin_cap));
-    const Event* ev = p.bins + sb * p.bin_cap;
-    for (uint32_t e = lane; e < c; e += 64) {
-      const Event x = ev[e];
-      atomicAdd(&s_syn[x.tgt], x.w);
+  {
+    const uint32_t c = tid < n_sub ? min(p.bin_cnt[sb0 + tid], static_cast<uint32_t>(p.bin_cap))
+                                   : 0u;
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w) before += s_wsum[w];
+    if (tid < n_sub) s_bpre[tid] = before + incl - c;
+    if (tid == n_sub - 1) s_bpre[n_sub] = before + incl;
+  }
+  __syncthreads();
+  const uint32_t n_arrive = s_bpre[n_sub];
+  for (uint32_t e0 = 0; e0 < n_arrive; e0 += GATHER_UNROLL * UPDATE_THREADS) {
+    // Past the end a lane re-reads the last event (always a valid address)
+    // and skips the add, so the loads carry no branch and issue together.
+    uint32_t e[GATHER_UNROLL], ec[GATHER_UNROLL], k[GATHER_UNROLL];
+#pragma unroll
+    for (int v = 0; v < GATHER_UNROLL; ++v) {
+      e[v] = e0 + v * UPDATE_THREADS + tid;
+      ec[v] = min(e[v], n_arrive - 1);
+      k[v] = 0;
     }
+    // largest k < n_sub with s_bpre[k] <= ec: the sub-bin holding event ec
+#pragma unroll
+    for (uint32_t step = SUBBIN_SEARCH_TOP; step; step >>= 1) {
+#pragma unroll
+      for (int v = 0; v < GATHER_UNROLL; ++v) {
+        const uint32_t m = k[v] + step;
+        if (m < n_sub && s_bpre[m] <= ec[v]) k[v] = m;
+      }
+    }
+    Event x[GATHER_UNROLL];
+#pragma unroll
+    for (int v = 0; v < GATHER_UNROLL; ++v)
+      x[v] = p.bins[(sb0 + k[v]) * p.bin_cap + (ec[v] - s_bpre[k[v]])];
+#pragma unroll
+    for (int v = 0; v < GATHER_UNROLL; ++v)
+      if (e[v] < n_arrive) atomicAdd(&s_syn[x[v].tgt], x[v].w);
   }
   __syncthreads();
   float* ring_slot = p.ring + static_cast<uint64_t>(slot) * p.ring_stride;
@@ -237,10 +374,14 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   if (p.forced) thr_raster = phase < p.raster_on ? p.raster_on_thr : p.raster_off_thr;
 
   uint32_t fire_bits = 0;   // bit 4q + k: neuron k of quad q fired
-  // Quads one at a time (not unrolled): keeps the kernel near 64 VGPRs so two
-  // 1024-thread blocks fit a CU and every tile of the network is resident.
+  // One quad per iteration, the next quad's loads issued before this quad's
+  // arithmetic (not unrolled: keeps the kernel within 128 VGPRs, two blocks
+  // per CU).
 #pragma unroll 1
   for (int q = 0; q < NQ; ++q) {
+    const float4 u4 = u_next;
+    const uint32_t r4 = r_next;
+    if (q + 1 < NQ) load_quad(q + 1, u_next, r_next);
     const uint32_t l0 = q * (4 * UPDATE_THREADS) + 4 * tid;
     const uint32_t i0 = blk0 + l0;
     // Philox counter word 0 is i0 / 4: one call serves the quad's 4 neurons.
@@ -249,51 +390,45 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (p.forced) rnd2 = philox4x32_10(i0 >> 2, t32, STREAM_RASTER, 0u, p.seed_lo, p.seed_hi);
     const uint32_t r1[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
     const uint32_t r2[4] = {rnd2.x, rnd2.y, rnd2.z, rnd2.w};
-    float uu[4] = {0.f, 0.f, 0.f, 0.f};
-    uint32_t rf[4] = {0, 0, 0, 0};
-    const bool full = i0 + 4 <= p.N;
-    if (full) {
-      const float4 u4 = *reinterpret_cast<const float4*>(p.u + i0);
-      const uint32_t r4 = *reinterpret_cast<const uint32_t*>(p.ref + i0);
-      uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) rf[k] = (r4 >> (8 * k)) & 0xFFu;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (i0 + k < p.N) {
-          uu[k] = p.u[i0 + k];
-          rf[k] = p.ref[i0 + k];
-        }
-    }
     const float4 syn4 = *reinterpret_cast<const float4*>(&s_syn[l0]);
     const float syn[4] = {syn4.x, syn4.y, syn4.z, syn4.w};
+    float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+    uint32_t rf[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rf[k] = (r4 >> (8 * k)) & 0xFFu;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      uint32_t kk = 0;
+      // Poisson count k = #{j : thr[j] <= r} through the lookup; ranges
+      // holding several thresholds (far tail) count all of them.
+      const uint32_t r = r1[k];
+      const uint32_t e = s_lut[r >> POIS_LUT_SHIFT];
+      const uint32_t j = min(e - 16u, 14u);
+      uint32_t kk = e < 16u ? e : j + (r >= s_thr[j] ? 1u : 0u);
+      if (e == POIS_LUT_SLOW) {
+        kk = 0;
 #pragma unroll
-      for (int j = 0; j < 15; ++j) kk += p.thr[j] <= r1[k] ? 1u : 0u;
+        for (int jj = 0; jj < 15; ++jj) kk += p.thr[jj] <= r ? 1u : 0u;
+      }
       const float ext = __fmul_rn(static_cast<float>(kk), p.w_ext);
+      // integrate unless refractory (then the count drops and u stays):
+      // u = fl(fl(u * alpha) + fl(syn + ext)), selected without branches
       const bool integrating = rf[k] == 0;
-      if (!integrating) {
-        rf[k] -= 1;
-      } else {
-        const float I = __fadd_rn(syn[k], ext);
-        const float v = __fmul_rn(uu[k], p.alpha);
-        uu[k] = __fadd_rn(v, I);
-      }
-      bool s = p.forced ? (r2[k] < thr_raster) : (integrating && uu[k] >= p.theta);
+      const float u_int = __fadd_rn(__fmul_rn(uu[k], p.alpha), __fadd_rn(syn[k], ext));
+      const float un = integrating ? u_int : uu[k];
+      const uint32_t rn = integrating ? 0u : rf[k] - 1u;
+      bool s = p.forced ? (r2[k] < thr_raster) : (integrating && un >= p.theta);
       s = s && (i0 + k < p.N);
-      if (s) {
-        uu[k] = p.u_reset;
-        rf[k] = p.n_ref;
-      }
+      uu[k] = s ? p.u_reset : un;
+      rf[k] = s ? p.n_ref : rn;
       fire_bits |= static_cast<uint32_t>(s) << (4 * q + k);
     }
-    if (full) {
+    uint32_t cnt_q = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cnt_q += __popcll(__ballot((fire_bits >> (4 * q + k)) & 1u));
+    if (lane == 0) s_cnt[q][wave] = cnt_q;
+    if (tile_full) {
       *reinterpret_cast<float4*>(p.u + i0) = make_float4(uu[0], uu[1], uu[2], uu[3]);
-      *reinterpret_cast<uint32_t*>(p.ref + i0) =
-          rf[0] | (rf[1] << 8) | (rf[2] << 16) | (rf[3] << 24);
+      *reinterpret_cast<uint32_t*>(p.ref + i0) = rf[0] | (rf[1] << 8) | (rf[2] << 16) | (rf[3] << 24);
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -306,65 +441,52 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
 
   // Compaction.  Within quad q, ids ascend with (wave, lane, k); across
   // quads, quad q of every wave precedes quad q + 1.  The rank of a fired id
-  // is: fired ids of earlier quads (whole block) + of earlier waves in this
-  // quad + of lower lanes in this wave and quad (4 ballots) + earlier k.
-  const uint64_t lt = (1ull << lane) - 1ull;
-  uint32_t lane_pre[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    uint32_t pre = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint64_t b = __ballot((fire_bits >> (4 * q + k)) & 1u);
-      pre += __popcll(b & lt);
-      tot += __popcll(b);
-    }
-    lane_pre[q] = pre;
-    if (lane == 0) s_cnt[q][wave] = tot;
-  }
+  // is: the offset of its (quad, wave) in that order (one wave scans the
+  // NQ x NW counts) + fired ids of lower lanes in the same (quad, wave)
+  // (4 ballots) + earlier k.  The block's total goes through the look-back.
+  static_assert(NQ * NW <= 64, "one lane per (quad, wave)");
   __syncthreads();
-  uint32_t block_tot = 0;
-  uint32_t quad_off[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    uint32_t before_wave = 0, quad_tot = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      before_wave += w < static_cast<int>(wave) ? s_cnt[q][w] : 0u;
-      quad_tot += s_cnt[q][w];
-    }
-    quad_off[q] = block_tot + before_wave + lane_pre[q];
-    block_tot += quad_tot;
-  }
   if (wave == 0) {
+    const uint32_t c = lane < NQ * NW ? s_cnt[lane / NW][lane % NW] : 0u;
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane < NQ * NW) s_qoff[lane / NW][lane % NW] = incl - c;
+    const uint32_t block_tot = __shfl(incl, 63, 64);
     const uint32_t excl = lookback_exclusive(p.lookback, blockIdx.x, block_tot, tag);
-    if (lane == 0) s_excl = excl;
+    if (lane == 0) {
+      s_excl = excl;
+      s_btot = block_tot;
+    }
   }
   __syncthreads();
-  if (fire_bits) {
+  const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll 1
+  for (int q = 0; q < NQ; ++q) {
+    const uint32_t qb = (fire_bits >> (4 * q)) & 0xFu;
+    if (__ballot(qb != 0) == 0) continue;
+    uint32_t pos = s_excl + s_qoff[q][wave];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      uint32_t pos = s_excl + quad_off[q];
-      const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
+    for (int k = 0; k < 4; ++k) pos += __popcll(__ballot((qb >> k) & 1u) & lt);
+    const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if ((fire_bits >> (4 * q + k)) & 1u) {
-          p.fired[pos] = i0 + k;
-          if (p.log_cap) {
-            uint64_t at = log_head + pos;
-            if (at >= p.log_cap) at %= p.log_cap;
-            p.log[at] = i0 + k;
-          }
-          ++pos;
+    for (int k = 0; k < 4; ++k)
+      if ((qb >> k) & 1u) {
+        p.fired[pos] = i0 + k;
+        // a step with more spikes than the log holds is flagged by the last
+        // block (ERR_LOG); its ids past the capacity are not logged
+        if (pos < p.log_cap) {
+          uint64_t at = log_head + pos;
+          if (at >= p.log_cap) at -= p.log_cap;
+          p.log[at] = i0 + k;
         }
-    }
+        ++pos;
+      }
   }
 
   // The last block holds the step total once its look-back is done; every
   // other block has read t and log_total by then (they published first).
   if (blockIdx.x == gridDim.x - 1 && tid == 0) {
     DevState* w = p.st;
-    const uint32_t n = s_excl + block_tot;
+    const uint32_t n = s_excl + s_btot;
     const uint64_t log_base = w->log_total;
     w->n_fired = n;
     p.stats[static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_SPIKES] = n;
@@ -407,36 +529,49 @@ __device__ __forceinline__ void bucket_put(const KParams& p, uint32_t node, uint
 }
 
 // Two-level: block b takes a contiguous chunk of the fired sources and works
-// in rounds of SB sources (a source emits at most n_nodes messages).  Within
-// a round one wave per source finds the runs of equal node in its ascending
-// destination list; the first lane of each run ORs the run into a mask and
-// stages the message in LDS with its rank among the block's messages to that
-// node.  One atomic per (round, node) then reserves the node's bucket space.
-// Dynamic LDS: 2 * n_nodes counters + ROUTE_STAGE staged messages.
+// in rounds of SB sources (a source emits at most n_nodes messages).  The
+// chunk's per-source data (id, destination-list bounds, own node) is loaded
+// first, one source per thread, so that a wave's sources need only their
+// destination lists.  Within a round one wave per source finds the runs of
+// equal node in its ascending destination list; the first lane of each run
+// ORs the run into a mask and stages the message in LDS with its rank among
+// the block's messages to that node.  One atomic per (round, node) then
+// reserves the node's bucket space.
+// Dynamic LDS: ROUTE_STAGE staged messages + 2 * n_nodes counters.
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   uint64_t* s_msg = lds_u64;                                              // [ROUTE_STAGE]
   uint32_t* s_nr = reinterpret_cast<uint32_t*>(s_msg + ROUTE_STAGE);      // node | rank << 16
   uint32_t* l_cnt = s_nr + ROUTE_STAGE;                                   // [n_nodes]
   uint32_t* l_base = l_cnt + p.n_nodes;                                   // [n_nodes]
-  __shared__ uint32_t l_total;
   constexpr uint32_t NW = ROUTE_THREADS / 64;
+  __shared__ uint32_t l_total;
+  __shared__ uint32_t s_src[ROUTE_THREADS], s_own[ROUTE_THREADS];
+  __shared__ int64_t s_j0[ROUTE_THREADS], s_j1[ROUTE_THREADS];
+  __shared__ uint64_t s_red[2 * NW];
   const uint32_t nF = p.st->n_fired;
   const uint32_t row = p.st->cur_row;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t chunk = (nF + gridDim.x - 1) / gridDim.x;
   const uint32_t lo = min(blockIdx.x * chunk, nF), hi = min(lo + chunk, nF);
-  const uint32_t SB = max(1u, ROUTE_STAGE / p.n_nodes);
+  const uint32_t SB = max(1u, min(ROUTE_STAGE / p.n_nodes, static_cast<uint32_t>(ROUTE_THREADS)));
   uint64_t l1 = 0, l2 = 0;
   for (uint32_t r0 = lo; r0 < hi; r0 += SB) {
     const uint32_t r1 = min(r0 + SB, hi);
     for (uint32_t i = tid; i < p.n_nodes; i += ROUTE_THREADS) l_cnt[i] = 0;
     if (tid == 0) l_total = 0;
+    if (tid < r1 - r0) {
+      const uint32_t s = p.fired[r0 + tid];
+      s_src[tid] = s;
+      s_own[tid] = static_cast<uint32_t>(p.part[s]) / p.G;
+      s_j0[tid] = p.vp_ptr[s];
+      s_j1[tid] = p.vp_ptr[s + 1];
+    }
     __syncthreads();
-    for (uint32_t i = r0 + wave; i < r1; i += NW) {
-      const uint32_t s = p.fired[i];
-      const uint32_t own_node = static_cast<uint32_t>(p.part[s]) / p.G;
-      const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
+    for (uint32_t i = wave; i < r1 - r0; i += NW) {
+      const uint32_t s = s_src[i];
+      const uint32_t own_node = s_own[i];
+      const int64_t j0 = s_j0[i], j1 = s_j1[i];
       for (int64_t jb = j0; jb < j1; jb += 64) {
         const int64_t j = jb + lane;
         if (j >= j1) continue;
@@ -469,8 +604,8 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
     }
     __syncthreads();
   }
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_MSG_L1, l1);
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_MSG_L2, l2);
+  uint64_t* st = p.stats + static_cast<uint64_t>(row) * SNN_NSTAT;
+  add_stats(st + SNN_STAT_MSG_L1, l1, st + SNN_STAT_MSG_L2, l2, s_red);
 }
 
 // Two-level routing without LDS staging, for node counts whose counters do
@@ -496,36 +631,41 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level_direct(KParam
       if (node == own_node) ++l1; else ++l2;
     }
   }
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_MSG_L1, l1);
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_MSG_L2, l2);
+  __shared__ uint64_t s_red[2 * (ROUTE_THREADS / 64)];
+  uint64_t* st = p.stats + static_cast<uint64_t>(row) * SNN_NSTAT;
+  add_stats(st + SNN_STAT_MSG_L1, l1, st + SNN_STAT_MSG_L2, l2, s_red);
 }
 
-// Expansion at destination node n (grid x = chunks of the bucket, y = node):
-// every set bit b of a message's mask appends (source, index of partition
-// G*n + b in the source's destination list) to that partition's receive list.
-// A block only touches the node's G partitions, so entries are staged in LDS
-// and each round reserves with G atomics.
-__global__ __launch_bounds__(ROUTE_THREADS) void k_expand(KParams p) {
-  __shared__ uint64_t s_ent[ROUTE_STAGE];
-  __shared__ uint16_t s_br[ROUTE_STAGE];       // b | rank << 3 (rank < ROUTE_STAGE)
-  __shared__ uint32_t l_cnt[SNN_MAX_GPUS_PER_NODE], l_base[SNN_MAX_GPUS_PER_NODE];
+// Expansion at destination node n (one block per node): every set bit b of a
+// message's mask appends (source, index of partition G*n + b in the source's
+// destination list) to that partition's receive list.  The block owns the
+// node's G partitions, so list positions come from LDS counters (no global
+// atomics) and the counts are stored at the end.  Rounds take one message per
+// thread, staged in LDS so that each partition's entries are written as runs.
+__global__ __launch_bounds__(EXPAND_THREADS) void k_expand(KParams p) {
+  constexpr uint32_t NW = EXPAND_THREADS / 64;
+  __shared__ uint64_t s_ent[EXPAND_THREADS * SNN_MAX_GPUS_PER_NODE];
+  __shared__ uint16_t s_br[EXPAND_THREADS * SNN_MAX_GPUS_PER_NODE];   // b | rank << 3
+  __shared__ uint32_t l_cnt[SNN_MAX_GPUS_PER_NODE], l_run[SNN_MAX_GPUS_PER_NODE];
+  __shared__ uint64_t l_off[SNN_MAX_GPUS_PER_NODE + 1];
   __shared__ uint32_t l_total;
-  const uint32_t n = blockIdx.y;
+  __shared__ uint64_t s_red[2 * NW];
+  const uint32_t n = blockIdx.x;
   const uint32_t tid = threadIdx.x;
   const uint32_t row = p.st->cur_row;
   const uint64_t off = p.bucket_off[n];
   const uint64_t cap = p.bucket_off[n + 1] - off;
   const uint64_t cnt = min(static_cast<uint64_t>(p.bucket_cnt[n * CNT_STRIDE]), cap);
-  const uint64_t per = (cnt + gridDim.x - 1) / gridDim.x;
-  const uint64_t lo = min(static_cast<uint64_t>(blockIdx.x) * per, cnt), hi = min(lo + per, cnt);
-  const uint32_t MB = ROUTE_STAGE / p.G;      // a message yields at most G entries
+  const uint32_t gn = min(p.G, p.P - p.G * n);             // partitions of this node
+  if (tid < SNN_MAX_GPUS_PER_NODE) l_run[tid] = 0;
+  if (tid <= gn) l_off[tid] = p.recv_off[p.G * n + tid];
   uint64_t entries = 0;
-  for (uint64_t m0 = lo; m0 < hi; m0 += MB) {
-    const uint64_t m1 = min(m0 + MB, hi);
+  for (uint64_t m0 = 0; m0 < cnt; m0 += EXPAND_THREADS) {
     if (tid < SNN_MAX_GPUS_PER_NODE) l_cnt[tid] = 0;
     if (tid == 0) l_total = 0;
     __syncthreads();
-    for (uint64_t m = m0 + tid; m < m1; m += ROUTE_THREADS) {
+    const uint64_t m = m0 + tid;
+    if (m < cnt) {
       const uint64_t msg = p.bucket[off + m];
       const uint64_t s = msg & 0xFFFFFFFFull;
       uint32_t mask = static_cast<uint32_t>(msg >> 32) & 0xFFu;
@@ -533,7 +673,7 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_expand(KParams p) {
       while (mask) {
         const uint32_t b = __ffs(mask) - 1;
         mask &= mask - 1;
-        if (b >= p.G || p.G * n + b >= p.P) {
+        if (b >= gn) {
           atomicOr(&p.st->error, ERR_ROUTE);
           continue;
         }
@@ -546,20 +686,18 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_expand(KParams p) {
       }
     }
     __syncthreads();
-    if (tid < p.G && l_cnt[tid])
-      l_base[tid] = atomicAdd(p.recv_cnt + (p.G * n + tid) * CNT_STRIDE, l_cnt[tid]);
-    __syncthreads();
-    for (uint32_t k = tid; k < l_total; k += ROUTE_THREADS) {
+    for (uint32_t k = tid; k < l_total; k += EXPAND_THREADS) {
       const uint32_t b = s_br[k] & 7u;
-      const uint32_t part = p.G * n + b;
-      const uint64_t pos = l_base[b] + (s_br[k] >> 3);
-      const uint64_t roff = p.recv_off[part];
-      if (roff + pos < p.recv_off[part + 1]) p.recv[roff + pos] = s_ent[k];
+      const uint64_t pos = l_off[b] + l_run[b] + (s_br[k] >> 3);
+      if (pos < l_off[b + 1]) p.recv[pos] = s_ent[k];
       else atomicOr(&p.st->error, ERR_RECV);
     }
     __syncthreads();
+    if (tid < SNN_MAX_GPUS_PER_NODE) l_run[tid] += l_cnt[tid];
   }
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_RECV_ENTRIES, entries);
+  __syncthreads();
+  if (tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
+  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_RECV_ENTRIES, entries, s_red);
 }
 
 // Flat (direct peer-to-peer) routing: one wave per fired source, one receive
@@ -584,7 +722,8 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
       ++flat;
     }
   }
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_FLAT_MSGS, flat);
+  __shared__ uint64_t s_red[2 * (ROUTE_THREADS / 64)];
+  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_FLAT_MSGS, flat, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,104 +731,134 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
 
 // Block b of STAGE_BLOCKS owns a contiguous range of partitions and their
 // receive lists.  For every entry (s, j): the receiving partition's synapses
-// of source s are the row segment of s's j-th destination; each synapse is
-// staged in LDS by delay and written to the block's own queue for that delay
-// (no global atomics: the queue belongs to the block).  Rounds take one entry
-// per thread; events beyond the LDS stage go straight to the queue.
-__global__ __launch_bounds__(DELIVER_THREADS) void k_recv_stage(KParams p, int use_flat) {
-  __shared__ Event s_ev[DELIVER_STAGE];
-  __shared__ uint32_t s_dr[DELIVER_STAGE];     // (d - 1) | rank << 4
-  __shared__ uint32_t s_pref[STAGE_PARTS + 1];
-  __shared__ uint32_t l_cnt[SNN_MAX_DELAY], l_run[SNN_MAX_DELAY];
-  __shared__ uint32_t l_total;
+// of source s are the row segment of s's j-th destination; each synapse goes
+// to the block's own queue for its delay (positions from per-delay LDS
+// counters; no global atomics: the queues belong to the block).
+// Entries are taken in batches of RECV_BATCH, RECV_PER_THREAD per thread, so
+// that their three dependent lookups (entry; source row and destination-list
+// bounds; segment) are in flight together; the segments are then concatenated
+// by a block scan and their synapses loaded as one flat sequence.
+__global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_flat) {
+  constexpr uint32_t NW = RECV_THREADS / 64;
+  constexpr uint32_t R = RECV_PER_THREAD;
+  __shared__ uint32_t s_ppre[RECV_THREADS];     // entry starts of the block's partitions
+  __shared__ uint64_t s_roff[RECV_THREADS];     // list offsets of the block's partitions
+  __shared__ uint64_t s_seg[RECV_BATCH];        // first synapse of each entry's segment
+  __shared__ uint32_t s_epre[RECV_BATCH];       // segment starts in the concatenation
+  __shared__ uint32_t s_wsum[NW];
+  __shared__ uint64_t s_red[2 * NW];
+  __shared__ uint32_t l_pos[SNN_MAX_DELAY];
   const uint32_t tid = threadIdx.x, b = blockIdx.x;
   const uint32_t md = p.D - 1;
   const uint32_t slot0 = p.st->cur_slot;
   const uint32_t row = p.st->cur_row;
   const uint32_t ppb = (p.P + STAGE_BLOCKS - 1) / STAGE_BLOCKS;
   const uint32_t q0 = min(b * ppb, p.P), q1 = min(q0 + ppb, p.P);
+  const uint32_t nq = q1 - q0;
   const uint64_t* lists = use_flat ? p.flat : p.recv;
   const uint32_t* cnts = use_flat ? p.flat_cnt : p.recv_cnt;
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (uint32_t q = q0; q < q1; ++q) {
-      s_pref[q - q0] = acc;
-      const uint64_t cap = p.recv_off[q + 1] - p.recv_off[q];
-      acc += static_cast<uint32_t>(min(static_cast<uint64_t>(cnts[q * CNT_STRIDE]), cap));
-    }
-    s_pref[q1 - q0] = acc;
+  if (tid < SNN_MAX_DELAY) l_pos[tid] = 0;
+  uint32_t c = 0;
+  if (tid < nq) {
+    const uint64_t o = p.recv_off[q0 + tid], o1 = p.recv_off[q0 + tid + 1];
+    s_roff[tid] = o;
+    c = static_cast<uint32_t>(min(static_cast<uint64_t>(cnts[(q0 + tid) * CNT_STRIDE]), o1 - o));
   }
-  if (tid < SNN_MAX_DELAY) l_run[tid] = 0;
+  uint32_t n_ent;
+  s_ppre[tid] = block_excl_scan(c, s_wsum, &n_ent);
   __syncthreads();
-  const uint32_t n_ent = s_pref[q1 - q0];
   Event* queue = p.stage + static_cast<uint64_t>(b) * p.stage_cap;  // + (d-1)*STAGE_BLOCKS*cap
   const uint64_t qstride = static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap;
   uint64_t events = 0;
-  for (uint32_t e0 = 0; e0 < n_ent; e0 += DELIVER_THREADS) {
-    if (tid < SNN_MAX_DELAY) l_cnt[tid] = 0;
-    if (tid == 0) l_total = 0;
+  for (uint32_t b0 = 0; b0 < n_ent; b0 += RECV_BATCH) {
+    const uint32_t nb = min(n_ent - b0, RECV_BATCH);
+    // entries tid * R + v of the batch; past the end a lane repeats the last
+    // entry (valid addresses) and contributes no synapses
+    uint64_t ent[R];
+    uint32_t part[R];
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const uint32_t e = b0 + min(tid * R + v, nb - 1);
+      const uint32_t k = owner_of<STAGE_PARTS / 2>(s_ppre, nq, e);
+      part[v] = q0 + k;
+      ent[v] = lists[s_roff[k] + (e - s_ppre[k])];
+    }
+    int64_t jb[R], je[R], r0[R], r1[R];
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const uint32_t s = static_cast<uint32_t>(ent[v]);
+      const uint32_t sc = s < p.N ? s : 0u;
+      jb[v] = p.vp_ptr[sc];
+      je[v] = p.vp_ptr[sc + 1];
+      r0[v] = p.row_ptr[sc];
+      r1[v] = p.row_ptr[sc + 1];
+    }
+    uint32_t len[R];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const bool in = tid * R + v < nb;
+      const uint32_t s = static_cast<uint32_t>(ent[v]);
+      const int64_t j = jb[v] + static_cast<int64_t>(ent[v] >> 32);
+      bool ok = s < p.N && j < je[v];
+      const int64_t jc = ok ? j : 0;           // entries exist, so pair 0 does
+      const int64_t jn = jc + 1 < je[v] ? jc + 1 : jc;
+      const uint32_t vp = p.vp_part[jc];
+      const uint32_t sg = p.vp_seg[jc], sg1 = p.vp_seg[jn];
+      ok = ok && vp == part[v];
+      if (in && !ok) atomicOr(&p.st->error, ERR_ROUTE);
+      const uint64_t a = static_cast<uint64_t>(r0[v]) + sg;
+      const uint64_t z = jc + 1 < je[v] ? static_cast<uint64_t>(r0[v]) + sg1
+                                        : static_cast<uint64_t>(r1[v]);
+      s_seg[tid * R + v] = a;
+      len[v] = in && ok ? static_cast<uint32_t>(z - a) : 0u;
+      tsum += len[v];
+    }
+    uint32_t T;
+    uint32_t run = block_excl_scan(tsum, s_wsum, &T);
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      s_epre[tid * R + v] = run;
+      run += len[v];
+    }
     __syncthreads();
-    const uint32_t e = e0 + tid;
-    if (e < n_ent) {
-      uint32_t lo = 0, hi = q1 - q0;          // partition of entry e: s_pref[lo] <= e < s_pref[lo+1]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_pref[mid] <= e) lo = mid; else hi = mid;
+    events += tid == 0 ? T : 0u;
+    for (uint32_t e0 = 0; e0 < T; e0 += GATHER_UNROLL * RECV_THREADS) {
+      uint32_t td[GATHER_UNROLL];
+      float wt[GATHER_UNROLL];
+#pragma unroll
+      for (int v = 0; v < GATHER_UNROLL; ++v) {
+        const uint32_t e = min(e0 + v * RECV_THREADS + tid, T - 1);
+        const uint32_t k = owner_of<RECV_BATCH / 2>(s_epre, nb, e);
+        const uint64_t x = s_seg[k] + (e - s_epre[k]);
+        td[v] = p.tgt_delay[x];
+        wt[v] = load_weight(p, x);
       }
-      const uint32_t q = q0 + lo;
-      const uint64_t ent = lists[p.recv_off[q] + (e - s_pref[lo])];
-      const uint32_t s = static_cast<uint32_t>(ent);
-      const int64_t jb = s < p.N ? p.vp_ptr[s] : 0, je = s < p.N ? p.vp_ptr[s + 1] : 0;
-      const int64_t j = jb + static_cast<int64_t>(ent >> 32);
-      if (s >= p.N || j >= je || p.vp_part[j] != q) {
-        atomicOr(&p.st->error, ERR_ROUTE);
-      } else {
-        const uint64_t r0 = static_cast<uint64_t>(p.row_ptr[s]);
-        const uint64_t a = r0 + p.vp_seg[j];
-        const uint64_t z = j + 1 < je ? r0 + p.vp_seg[j + 1] : static_cast<uint64_t>(p.row_ptr[s + 1]);
-        events += z - a;
-        for (uint64_t x = a; x < z; ++x) {
-          const uint32_t td = p.tgt_delay[x];
-          const uint32_t d1 = (td >> 27) - 1;
-          if (d1 >= md) {                      // delay outside [1, max_delay]
-            atomicOr(&p.st->error, ERR_ROUTE);
-            continue;
-          }
-          const Event ev{td & 0x07FFFFFFu, load_weight(p, x)};
-          const uint32_t k = atomicAdd(&l_total, 1u);
-          if (k < DELIVER_STAGE) {
-            const uint32_t rk = atomicAdd(&l_cnt[d1], 1u);
-            s_ev[k] = ev;
-            s_dr[k] = d1 | (rk << 4);
-          } else {
-            uint32_t slot = slot0 + d1 + 1;
-            if (slot >= p.D) slot -= p.D;
-            ring_fallback(p, slot, ev.tgt, ev.w);
-          }
+#pragma unroll
+      for (int v = 0; v < GATHER_UNROLL; ++v) {
+        if (e0 + v * RECV_THREADS + tid >= T) continue;
+        const uint32_t d1 = (td[v] >> 27) - 1;
+        if (d1 >= md) {                        // delay outside [1, max_delay]
+          atomicOr(&p.st->error, ERR_ROUTE);
+          continue;
+        }
+        const Event ev{td[v] & 0x07FFFFFFu, wt[v]};
+        const uint32_t pos = atomicAdd(&l_pos[d1], 1u);
+        if (pos < p.stage_cap) {
+          queue[d1 * qstride + pos] = ev;
+        } else {
+          uint32_t slot = slot0 + d1 + 1;
+          if (slot >= p.D) slot -= p.D;
+          ring_fallback(p, slot, ev.tgt, ev.w);
         }
       }
     }
     __syncthreads();
-    const uint32_t staged = min(l_total, DELIVER_STAGE);
-    for (uint32_t k = tid; k < staged; k += DELIVER_THREADS) {
-      const uint32_t d1 = s_dr[k] & 15u;
-      const uint64_t pos = static_cast<uint64_t>(l_run[d1]) + (s_dr[k] >> 4);
-      if (pos < p.stage_cap) {
-        queue[d1 * qstride + pos] = s_ev[k];
-      } else {
-        uint32_t slot = slot0 + d1 + 1;
-        if (slot >= p.D) slot -= p.D;
-        ring_fallback(p, slot, s_ev[k].tgt, s_ev[k].w);
-      }
-    }
-    __syncthreads();
-    if (tid < md) l_run[tid] += l_cnt[tid];
-    __syncthreads();
   }
   if (tid < md)
     p.stage_cnt[tid * STAGE_BLOCKS + b] =
-        static_cast<uint32_t>(min(static_cast<uint64_t>(l_run[tid]), p.stage_cap));
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_REMOTE_EVENTS, events);
+        static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
+  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_REMOTE_EVENTS, events, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,8 +870,11 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_recv_stage(KParams p, int u
 // so the block counting-sorts them by tile in LDS and writes each tile's run
 // into sub-bin (slot, tile, d, w).  That sub-bin is written by this block
 // only, once per ring cycle, and read by the tile's update D - d steps later:
-// positions and counts need no atomics.  Rounds are sized by a wave scan of
-// the sources' run lengths so that they fit the LDS stage.
+// positions and counts need no atomics.
+// The runs are taken as one flat sequence: one thread per source loads the
+// run's start and length, a block scan concatenates them, and the events are
+// loaded in windows of DELIVER_STAGE with GATHER_UNROLL loads in flight per
+// thread (the owner of an event is found by a power-of-two search).
 // Dynamic LDS: DELIVER_STAGE events + tile/rank words + 2 * n_tiles counters.
 __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   extern __shared__ uint64_t lds_u64[];
@@ -710,9 +882,13 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   uint32_t* s_tr = reinterpret_cast<uint32_t*>(s_ev + DELIVER_STAGE);     // tile | rank << 16
   uint32_t* l_cnt = s_tr + DELIVER_STAGE;                                 // [n_tiles]
   uint32_t* l_run = l_cnt + p.n_tiles;                                    // [n_tiles]
-  __shared__ uint32_t l_total, s_m0, s_mn;
   constexpr uint32_t NW = DELIVER_THREADS / 64;
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr uint32_t QPB = STAGE_BLOCKS / DELIVER_BLOCKS;                 // queues per block
+  __shared__ uint64_t s_base[DELIVER_THREADS];   // first event of each segment
+  __shared__ uint32_t s_pre[DELIVER_THREADS];    // segment starts in the concatenation
+  __shared__ uint32_t s_wsum[NW];
+  __shared__ uint64_t s_red[2 * NW];
+  const uint32_t tid = threadIdx.x;
   const uint32_t w = blockIdx.x, d = blockIdx.y + 1;
 
   const uint32_t nF = p.st->n_fired;
@@ -720,26 +896,23 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   if (slot >= p.D) slot -= p.D;
   const uint32_t row = p.st->cur_row;
   const uint32_t D = p.D;
-  for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS) l_run[i] = 0;
+  for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS) {
+    l_run[i] = 0;
+    l_cnt[i] = 0;
+  }
   uint64_t events = 0;
 
-  // stage one event; events beyond the LDS stage go to the ring
-  auto stage = [&](uint32_t tgt, float wt) {
+  // event (global target, weight) into LDS slot k
+  auto put = [&](uint32_t k, uint32_t tgt, float wt) {
     const uint32_t tile = tgt >> TILE_SHIFT;
-    const uint32_t k = atomicAdd(&l_total, 1u);
-    if (k < DELIVER_STAGE) {
-      const uint32_t rk = atomicAdd(&l_cnt[tile], 1u);
-      s_ev[k] = Event{tgt & (TILE - 1), wt};
-      s_tr[k] = tile | (rk << 16);
-    } else {
-      ring_fallback(p, slot, tgt, wt);
-    }
+    const uint32_t rk = atomicAdd(&l_cnt[tile], 1u);
+    s_ev[k] = Event{tgt & (TILE - 1), wt};
+    s_tr[k] = tile | (rk << 16);
   };
-  // write the staged round into the sub-bins and advance the running counts
-  auto flush = [&]() {
+  // write the n staged events into the sub-bins and advance the running counts
+  auto flush = [&](uint32_t n) {
     __syncthreads();
-    const uint32_t staged = min(l_total, DELIVER_STAGE);
-    for (uint32_t k = tid; k < staged; k += DELIVER_THREADS) {
+    for (uint32_t k = tid; k < n; k += DELIVER_THREADS) {
       const uint32_t tile = s_tr[k] & 0xFFFFu;
       const uint64_t pos = static_cast<uint64_t>(l_run[tile]) + (s_tr[k] >> 16);
       if (pos < p.bin_cap) {
@@ -753,64 +926,86 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
       l_run[i] += l_cnt[i];
       l_cnt[i] = 0;
     }
-    if (tid == 0) l_total = 0;
     __syncthreads();
   };
 
-  for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS) l_cnt[i] = 0;
-  if (tid == 0) l_total = 0;
-  __syncthreads();
-
-  // local synapses of the fired sources assigned to this block
+  // local synapses of the fired sources assigned to this block, in batches
+  // of one source per thread
   const uint32_t M = nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
-  uint32_t m_next = 0;
-  while (m_next < M) {
-    if (wave == 0) {
-      const uint32_t m = m_next + lane;
-      uint32_t len = 0;
-      if (m < M) {
-        const uint32_t s = p.fired[w + m * DELIVER_BLOCKS];
-        len = p.delay_off[static_cast<uint64_t>(s) * D + d] -
-              p.delay_off[static_cast<uint64_t>(s) * D + d - 1];
-      }
-      const uint32_t incl = wave_incl_scan(len);
-      const uint32_t fit = __popcll(__ballot(m < M && incl <= DELIVER_STAGE));
-      if (lane == 0) {
-        s_m0 = m_next;
-        s_mn = max(fit, 1u);
-      }
+  for (uint32_t m0 = 0; m0 < M; m0 += DELIVER_THREADS) {
+    const uint32_t nsrc = min(M - m0, static_cast<uint32_t>(DELIVER_THREADS));
+    uint32_t len = 0;
+    if (tid < nsrc) {
+      const uint32_t s = p.fired[w + (m0 + tid) * DELIVER_BLOCKS];
+      const uint64_t o = static_cast<uint64_t>(s) * D;
+      const uint32_t a = p.delay_off[o + d - 1], z = p.delay_off[o + d];
+      s_base[tid] = static_cast<uint64_t>(p.row_ptr[s]) + a;
+      len = z - a;
     }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(len, s_wsum, &tot);
+    s_pre[tid] = ex;
     __syncthreads();
-    const uint32_t m0 = s_m0, mn = s_mn;
-    for (uint32_t k = wave; k < mn; k += NW) {
-      const uint32_t s = p.fired[w + (m0 + k) * DELIVER_BLOCKS];
-      const uint64_t r0 = static_cast<uint64_t>(p.row_ptr[s]);
-      const uint32_t a = p.delay_off[static_cast<uint64_t>(s) * D + d - 1];
-      const uint32_t z = p.delay_off[static_cast<uint64_t>(s) * D + d];
-      for (uint32_t x = a + lane; x < z; x += 64)
-        stage(p.tgt_delay[r0 + x] & 0x07FFFFFFu, load_weight(p, r0 + x));
-      if (lane == 0) events += z - a;
+    events += tid == 0 ? tot : 0u;
+    for (uint32_t e0 = 0; e0 < tot; e0 += DELIVER_STAGE) {
+      const uint32_t n_win = min(tot - e0, DELIVER_STAGE);
+      for (uint32_t i0 = 0; i0 < n_win; i0 += GATHER_UNROLL * DELIVER_THREADS) {
+        uint32_t td[GATHER_UNROLL];
+        float wt[GATHER_UNROLL];
+#pragma unroll
+        for (int v = 0; v < GATHER_UNROLL; ++v) {
+          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_win - 1);
+          const uint32_t k = owner_of<DELIVER_THREADS / 2>(s_pre, nsrc, e);
+          const uint64_t x = s_base[k] + (e - s_pre[k]);
+          td[v] = p.tgt_delay[x];
+          wt[v] = load_weight(p, x);
+        }
+#pragma unroll
+        for (int v = 0; v < GATHER_UNROLL; ++v) {
+          const uint32_t le = i0 + v * DELIVER_THREADS + tid;
+          if (le < n_win) put(le, td[v] & 0x07FFFFFFu, wt[v]);
+        }
+      }
+      flush(n_win);
     }
-    flush();
-    m_next = m0 + mn;
   }
 
-  // remote synapses staged by the receive side for this delay
-  for (uint32_t q = w; q < STAGE_BLOCKS; q += DELIVER_BLOCKS) {
-    const uint32_t c = p.stage_cnt[(d - 1) * STAGE_BLOCKS + q];
-    const Event* src = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + q) * p.stage_cap;
-    for (uint32_t e0 = 0; e0 < c; e0 += DELIVER_STAGE) {
-      const uint32_t e1 = min(e0 + DELIVER_STAGE, c);
-      for (uint32_t e = e0 + tid; e < e1; e += DELIVER_THREADS) stage(src[e].tgt, src[e].w);
-      flush();
+  // remote synapses staged by the receive side for this delay: queues
+  // w + k * DELIVER_BLOCKS, k < QPB, concatenated the same way
+  {
+    uint32_t c = 0;
+    if (tid < QPB) c = p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS];
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(c, s_wsum, &tot);
+    if (tid < QPB) s_pre[tid] = ex;
+    __syncthreads();
+    const Event* q0 = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + w) * p.stage_cap;
+    for (uint32_t e0 = 0; e0 < tot; e0 += DELIVER_STAGE) {
+      const uint32_t n_win = min(tot - e0, DELIVER_STAGE);
+      for (uint32_t i0 = 0; i0 < n_win; i0 += GATHER_UNROLL * DELIVER_THREADS) {
+        Event x[GATHER_UNROLL];
+#pragma unroll
+        for (int v = 0; v < GATHER_UNROLL; ++v) {
+          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_win - 1);
+          const uint32_t k = owner_of<QPB / 2>(s_pre, QPB, e);
+          x[v] = q0[static_cast<uint64_t>(k) * DELIVER_BLOCKS * p.stage_cap + (e - s_pre[k])];
+        }
+#pragma unroll
+        for (int v = 0; v < GATHER_UNROLL; ++v) {
+          const uint32_t le = i0 + v * DELIVER_THREADS + tid;
+          if (le < n_win) put(le, x[v].tgt, x[v].w);
+        }
+      }
+      flush(n_win);
     }
   }
+  __syncthreads();
 
   // publish this block's counts for slot `slot`, every tile (zeros included)
   for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS)
     p.bin_cnt[subbin(p, slot, i, d, w)] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_run[i]), p.bin_cap));
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_LOCAL_EVENTS, events);
+  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_LOCAL_EVENTS, events, s_red);
 }
 
 // Moves every pending binned event into the dense ring (for read-back) and
@@ -848,8 +1043,17 @@ __global__ __launch_bounds__(256) void k_flush(KParams p) {
 
 uint32_t tiles_of(uint32_t n) { return (n + TILE - 1) / TILE; }
 
-hipError_t launch_update(const KParams& p, hipStream_t s) {
+// Optional timing marks: when marks is non-null, events marks[2k] and
+// marks[2k + 1] are recorded on the stream around each launch of kernel kind
+// k (SNN_KERNEL_*).
+static inline void mark(hipEvent_t* marks, int kind, int end, hipStream_t s) {
+  if (marks) (void)hipEventRecord(marks[2 * kind + end], s);
+}
+
+hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks) {
+  mark(marks, SNN_KERNEL_UPDATE, 0, s);
   hipLaunchKernelGGL(k_update, dim3(p.n_tiles), dim3(UPDATE_THREADS), 0, s, p);
+  mark(marks, SNN_KERNEL_UPDATE, 1, s);
   return hipGetLastError();
 }
 
@@ -857,17 +1061,24 @@ size_t route_lds_bytes(const KParams& p) {
   return ROUTE_STAGE * (sizeof(uint64_t) + sizeof(uint32_t)) + 2ull * p.n_nodes * sizeof(uint32_t);
 }
 
-hipError_t launch_route(const KParams& p, int mode, hipStream_t s) {
+hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks) {
   if (mode == SNN_ROUTE_TWO_LEVEL || mode == SNN_ROUTE_BOTH) {
+    mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 0, s);
     if (p.n_nodes <= ROUTE_MAX_NODES_LDS)
       hipLaunchKernelGGL(k_route_two_level, dim3(ROUTE_BLOCKS), dim3(ROUTE_THREADS),
                          route_lds_bytes(p), s, p);
     else
       hipLaunchKernelGGL(k_route_two_level_direct, dim3(1024), dim3(ROUTE_THREADS), 0, s, p);
-    hipLaunchKernelGGL(k_expand, dim3(EXPAND_BLOCKS, p.n_nodes), dim3(ROUTE_THREADS), 0, s, p);
+    mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 1, s);
+    mark(marks, SNN_KERNEL_EXPAND, 0, s);
+    hipLaunchKernelGGL(k_expand, dim3(p.n_nodes), dim3(EXPAND_THREADS), 0, s, p);
+    mark(marks, SNN_KERNEL_EXPAND, 1, s);
   }
-  if (mode == SNN_ROUTE_FLAT || mode == SNN_ROUTE_BOTH)
+  if (mode == SNN_ROUTE_FLAT || mode == SNN_ROUTE_BOTH) {
+    mark(marks, SNN_KERNEL_ROUTE_FLAT, 0, s);
     hipLaunchKernelGGL(k_route_flat, dim3(1024), dim3(ROUTE_THREADS), 0, s, p);
+    mark(marks, SNN_KERNEL_ROUTE_FLAT, 1, s);
+  }
   return hipGetLastError();
 }
 
@@ -875,11 +1086,15 @@ size_t deliver_lds_bytes(const KParams& p) {
   return DELIVER_STAGE * (sizeof(Event) + sizeof(uint32_t)) + 2ull * p.n_tiles * sizeof(uint32_t);
 }
 
-hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_recv_stage, dim3(STAGE_BLOCKS), dim3(DELIVER_THREADS), 0, s, p,
+hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks) {
+  mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
+  hipLaunchKernelGGL(k_recv_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p,
                      mode == SNN_ROUTE_FLAT ? 1 : 0);
+  mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
+  mark(marks, SNN_KERNEL_DELIVER, 0, s);
   hipLaunchKernelGGL(k_deliver, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
                      deliver_lds_bytes(p), s, p);
+  mark(marks, SNN_KERNEL_DELIVER, 1, s);
   return hipGetLastError();
 }
 

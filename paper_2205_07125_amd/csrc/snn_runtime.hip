@@ -51,7 +51,7 @@ uint32_t n_nodes_of(const snn_params* p) {
 // Byte offsets of the workspace regions.
 struct Layout {
   uint64_t st, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat, stage_cnt,
-      stage, bin_cnt, dirty, bins, stats, log_off, log, total;
+      stage, bin_cnt, dirty, bins, stats, pois_lut, log_off, log, total;
 };
 
 Layout layout(const snn_params* p) {
@@ -73,6 +73,7 @@ Layout layout(const snn_params* p) {
   L.bin_cnt = take(sizeof(uint32_t) * D * tiles * md * DELIVER_BLOCKS);
   L.dirty = take(sizeof(uint32_t) * D * tiles);
   L.stats = take(sizeof(uint64_t) * SNN_NSTAT * uint64_t(p->log_steps));
+  L.pois_lut = take(POIS_LUT_SIZE);
   L.log_off = take(sizeof(uint64_t) * uint64_t(p->log_steps));
   // large buffers last: the region before them is zeroed at create
   L.bucket = take(sizeof(uint64_t) * p->bucket_total);
@@ -83,6 +84,23 @@ Layout layout(const snn_params* p) {
   L.log = take(sizeof(uint32_t) * p->log_cap);
   L.total = o;
   return L;
+}
+
+// Poisson inversion lookup (layout in snn_internal.h): for the draws of entry
+// b, [lo, hi], k = #{j : thr[j] <= r} is fixed when no threshold lies in
+// (lo, hi]; one threshold there is resolved by one comparison in the kernel.
+void build_pois_lut(const uint32_t* thr, std::vector<uint8_t>& lut) {
+  lut.assign(POIS_LUT_SIZE, 0);
+  for (uint32_t b = 0; b < POIS_LUT_SIZE; ++b) {
+    const uint64_t lo = uint64_t(b) << POIS_LUT_SHIFT;
+    const uint64_t hi = lo + (uint64_t(1) << POIS_LUT_SHIFT) - 1;
+    uint32_t k_lo = 0, k_hi = 0;
+    for (int j = 0; j < 15; ++j) {
+      k_lo += thr[j] <= lo ? 1u : 0u;
+      k_hi += thr[j] <= hi ? 1u : 0u;
+    }
+    lut[b] = k_hi == k_lo ? uint8_t(k_lo) : k_hi == k_lo + 1 ? uint8_t(16 + k_lo) : POIS_LUT_SLOW;
+  }
 }
 
 snn_status check_params(const snn_params* p) {
@@ -122,8 +140,13 @@ struct snn_ctx {
   int route_mode;     // mode of the step in flight
   uint64_t t_host;    // steps enqueued
   uint64_t routed_t;  // step whose routes are in the buffers (+1), 0 = none
-  hipGraphExec_t graph[3];
+  hipGraphExec_t graph[3][2];   // per route mode: one step, GRAPH_STEPS steps
+  std::vector<uint8_t> pois_lut;  // host copy of the lookup uploaded at create
 };
+
+// Steps captured in the long graph: replaying several steps per launch spreads
+// the graph launch cost (several microseconds) over them.
+constexpr uint32_t GRAPH_STEPS = 16;
 
 extern "C" {
 
@@ -224,11 +247,16 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.dirty = reinterpret_cast<uint32_t*>(ws + L.dirty);
   k.bins = reinterpret_cast<Event*>(ws + L.bins);
   k.stats = reinterpret_cast<uint64_t*>(ws + L.stats);
+  k.pois_lut = reinterpret_cast<const uint8_t*>(ws + L.pois_lut);
   k.log_off = reinterpret_cast<uint64_t*>(ws + L.log_off);
   k.log = reinterpret_cast<uint32_t*>(ws + L.log);
   // Everything before the large buffers starts at zero: state, look-back
   // words, counters (bin counts are read before their first write).
   hipError_t e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
+  build_pois_lut(params->poisson_thr, c->pois_lut);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.pois_lut, c->pois_lut.data(), POIS_LUT_SIZE, hipMemcpyHostToDevice,
+                       c->stream);
   if (e == hipSuccess) e = prepare_kernels(k);
   if (e != hipSuccess) {
     delete c;
@@ -267,6 +295,34 @@ snn_status snn_deliver(snn_handle h) {
   return SNN_OK;
 }
 
+// Captures (once) a graph of one step (which = 0) or GRAPH_STEPS steps
+// (which = 1) in route mode `mode`.
+static snn_status ensure_graph(snn_handle h, int mode, int which) {
+  if (h->graph[mode][which]) return SNN_OK;
+  const uint32_t steps = which ? GRAPH_STEPS : 1u;
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (uint32_t i = 0; i < steps && e == hipSuccess; ++i) {
+    e = launch_update(h->kp, h->stream);
+    if (e == hipSuccess) e = launch_route(h->kp, mode, h->stream);
+    if (e == hipSuccess) e = launch_deliver(h->kp, mode, h->stream);
+  }
+  hipError_t ec = hipStreamEndCapture(h->stream, &g);
+  if (e != hipSuccess || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(SNN_ERR_HIP, "graph capture failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : ec));
+  }
+  hipError_t ei = hipGraphInstantiate(&h->graph[mode][which], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    h->graph[mode][which] = nullptr;
+    return fail(SNN_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  return SNN_OK;
+}
+
 snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
   if (mode < SNN_ROUTE_TWO_LEVEL || mode > SNN_ROUTE_BOTH)
@@ -280,31 +336,79 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
       HIP_TRY(launch_deliver(h->kp, mode, h->stream));
     }
   } else {
-    if (!h->graph[mode]) {
-      hipGraph_t g = nullptr;
-      HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e1 = launch_update(h->kp, h->stream);
-      hipError_t e2 = e1 == hipSuccess ? launch_route(h->kp, mode, h->stream) : e1;
-      hipError_t e3 = e2 == hipSuccess ? launch_deliver(h->kp, mode, h->stream) : e2;
-      hipError_t ec = hipStreamEndCapture(h->stream, &g);
-      if (e3 != hipSuccess || ec != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(SNN_ERR_HIP, "graph capture failed: %s",
-                    hipGetErrorString(e3 != hipSuccess ? e3 : ec));
-      }
-      hipError_t ei = hipGraphInstantiate(&h->graph[mode], g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (ei != hipSuccess) {
-        h->graph[mode] = nullptr;
-        return fail(SNN_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
-      }
+    const uint32_t n_long = n_steps / GRAPH_STEPS, n_short = n_steps % GRAPH_STEPS;
+    if (n_long) {
+      snn_status st = ensure_graph(h, mode, 1);
+      if (st != SNN_OK) return st;
+      for (uint32_t i = 0; i < n_long; ++i) HIP_TRY(hipGraphLaunch(h->graph[mode][1], h->stream));
     }
-    for (uint32_t i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(h->graph[mode], h->stream));
+    if (n_short) {
+      snn_status st = ensure_graph(h, mode, 0);
+      if (st != SNN_OK) return st;
+      for (uint32_t i = 0; i < n_short; ++i) HIP_TRY(hipGraphLaunch(h->graph[mode][0], h->stream));
+    }
   }
   h->route_mode = mode;
   h->t_host += n_steps;
   h->routed_t = h->t_host;
   return SNN_OK;
+}
+
+static snn_status sync_and_check(snn_handle h, DevState* out);
+
+snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg_ms) {
+  if (!h || !avg_ms) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  if (mode < SNN_ROUTE_TWO_LEVEL || mode > SNN_ROUTE_BOTH)
+    return fail(SNN_ERR_INVALID_ARG, "route mode %d", mode);
+  if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_kernel_times called in the middle of a step");
+  hipEvent_t marks[2 * SNN_NKERNEL] = {};
+  double total[SNN_NKERNEL] = {};
+  bool used[SNN_NKERNEL] = {};
+  snn_status st = SNN_OK;
+  for (auto& e : marks) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      st = fail(SNN_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(r));
+      break;
+    }
+  }
+  for (uint32_t i = 0; i < n_steps && st == SNN_OK; ++i) {
+    // the launchers record only the marks of the kinds they launch; a kind
+    // counts as launched when its end mark completed after its start mark
+    hipError_t r = launch_update(h->kp, h->stream, marks);
+    if (r == hipSuccess) r = launch_route(h->kp, mode, h->stream, marks);
+    if (r == hipSuccess) r = launch_deliver(h->kp, mode, h->stream, marks);
+    if (r == hipSuccess) r = hipStreamSynchronize(h->stream);
+    if (r != hipSuccess) {
+      st = fail(SNN_ERR_HIP, "timed step: %s", hipGetErrorString(r));
+      break;
+    }
+    h->t_host += 1;
+    h->route_mode = mode;
+    h->routed_t = h->t_host;
+    for (int k = 0; k < SNN_NKERNEL; ++k) {
+      const bool launched = k == SNN_KERNEL_UPDATE || k == SNN_KERNEL_RECV_STAGE ||
+                            k == SNN_KERNEL_DELIVER ||
+                            ((k == SNN_KERNEL_ROUTE_TWO_LEVEL || k == SNN_KERNEL_EXPAND) &&
+                             mode != SNN_ROUTE_FLAT) ||
+                            (k == SNN_KERNEL_ROUTE_FLAT && mode != SNN_ROUTE_TWO_LEVEL);
+      if (!launched) continue;
+      float ms = 0.f;
+      r = hipEventElapsedTime(&ms, marks[2 * k], marks[2 * k + 1]);
+      if (r != hipSuccess) {
+        st = fail(SNN_ERR_HIP, "hipEventElapsedTime: %s", hipGetErrorString(r));
+        break;
+      }
+      total[k] += ms;
+      used[k] = true;
+    }
+  }
+  for (auto& e : marks)
+    if (e) (void)hipEventDestroy(e);
+  if (st != SNN_OK) return st;
+  for (int k = 0; k < SNN_NKERNEL; ++k)
+    avg_ms[k] = used[k] && n_steps ? static_cast<float>(total[k] / n_steps) : 0.f;
+  return sync_and_check(h, nullptr);
 }
 
 snn_status snn_flush(snn_handle h) {
@@ -314,7 +418,7 @@ snn_status snn_flush(snn_handle h) {
   return SNN_OK;
 }
 
-static snn_status sync_and_check(snn_handle h, DevState* out = nullptr) {
+static snn_status sync_and_check(snn_handle h, DevState* out) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   DevState st;
   HIP_TRY(hipMemcpy(&st, h->kp.st, sizeof(st), hipMemcpyDeviceToHost));
@@ -329,7 +433,7 @@ static snn_status sync_and_check(snn_handle h, DevState* out = nullptr) {
 
 snn_status snn_sync(snn_handle h) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
-  return sync_and_check(h);
+  return sync_and_check(h, nullptr);
 }
 
 uint64_t snn_time(snn_handle h) { return h ? h->t_host : 0; }
@@ -350,7 +454,7 @@ snn_status snn_read_counters(snn_handle h, uint64_t first_step, uint32_t n_steps
                 (unsigned long long)first_step, (unsigned long long)(first_step + n_steps),
                 (unsigned long long)L, (unsigned long long)h->t_host);
   if (n_steps > L) return fail(SNN_ERR_INVALID_ARG, "n_steps exceeds log_steps");
-  snn_status s = sync_and_check(h);
+  snn_status s = sync_and_check(h, nullptr);
   if (s != SNN_OK && s != SNN_ERR_CAPACITY) return s;
   std::vector<uint64_t> all(SNN_NSTAT * L);
   HIP_TRY(hipMemcpy(all.data(), h->kp.stats, all.size() * 8, hipMemcpyDeviceToHost));
@@ -416,7 +520,7 @@ snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entri
   const int mode = h->route_mode;
   if ((which == 0 && mode == SNN_ROUTE_TWO_LEVEL) || (which != 0 && mode == SNN_ROUTE_FLAT))
     return fail(SNN_ERR_BAD_STATE, "the last step was not routed in a mode that fills these buffers");
-  snn_status s = sync_and_check(h);
+  snn_status s = sync_and_check(h, nullptr);
   if (s != SNN_OK) return s;
   const uint32_t nl = which == 2 ? h->kp.n_nodes : h->kp.P;
   std::vector<uint32_t> cnt(uint64_t(nl) * CNT_STRIDE);
@@ -453,8 +557,9 @@ snn_status snn_destroy(snn_handle h) {
   snn_status s = SNN_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) s = fail(SNN_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-  for (auto& g : h->graph)
-    if (g) (void)hipGraphExecDestroy(g);
+  for (auto& gm : h->graph)
+    for (auto& g : gm)
+      if (g) (void)hipGraphExecDestroy(g);
   delete h;
   return s;
 }

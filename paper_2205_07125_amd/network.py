@@ -5,6 +5,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import sys
 import time
 
 import numpy as np
@@ -94,7 +95,7 @@ class HostNetwork:
             N = wl.n_neurons
             if verbose:
                 print(f"[setup] {wl.name}: counted {nnz:,} synapses in {time.time() - t0:.1f}s",
-                      flush=True)
+                      file=sys.stderr, flush=True)
             self.row_ptr = np.empty(N + 1, np.int64)
             self.n_local = np.empty(N, np.uint32)
             self.delay_off = np.empty(N * (wl.max_delay + 1), np.uint16)
@@ -108,7 +109,7 @@ class HostNetwork:
             pairs, self.bucket_total, self.recv_total = (s.value for s in sizes[1:])
             if verbose:
                 print(f"[setup] rows placed and sorted in {time.time() - t1:.1f}s; "
-                      f"{pairs:,} destination pairs", flush=True)
+                      f"{pairs:,} destination pairs", file=sys.stderr, flush=True)
             n_nodes = wl.n_nodes
             self.vp_ptr = np.empty(N + 1, np.int64)
             self.vp_part = np.empty(max(pairs, 1), np.uint16)

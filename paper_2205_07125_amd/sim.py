@@ -120,6 +120,12 @@ class Simulation:
     def sync(self):
         _abi.snn_sync(self.h)
 
+    def kernel_times(self, n_steps: int, mode=_abi.SNN_ROUTE_TWO_LEVEL) -> dict:
+        """Runs n_steps steps with every kernel bracketed by HIP events on the
+        simulation stream; -> {kernel name: average ms} (snn_kernel_times)."""
+        ms = _abi.snn_kernel_times(self.h, n_steps, mode)
+        return dict(zip(_abi.KERNEL_NAMES, ms))
+
     def flush(self):
         _abi.snn_flush(self.h)
 

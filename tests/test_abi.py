@@ -103,3 +103,27 @@ def test_null_handle_calls():
     assert L.snn_destroy(None) == _abi.SNN_OK
     n = ctypes.c_uint64()
     assert L.snn_read_spikes(None, 0, 1, None, 0, None, ctypes.byref(n)) == _abi.SNN_ERR_INVALID_ARG
+    out = (ctypes.c_float * _abi.SNN_NKERNEL)()
+    assert L.snn_kernel_times(None, 1, 0, out) == _abi.SNN_ERR_INVALID_ARG
+
+
+def test_counter_and_kernel_enums_match_binding():
+    """The binding's counter and kernel-kind names follow the header's enum order."""
+    src = open(os.path.join(ROOT, "include", "snn.h")).read()
+    stats = dict((m[0], int(m[1])) for m in re.findall(r"SNN_STAT_([A-Z0-9_]+) = (\d+)", src))
+    assert [k.lower() for k, _ in sorted(stats.items(), key=lambda kv: kv[1])] == _abi.STAT_NAMES
+    kinds = dict((m[0], int(m[1])) for m in re.findall(r"SNN_KERNEL_([A-Z0-9_]+) = (\d+)", src))
+    assert [k.lower() for k, _ in sorted(kinds.items(), key=lambda kv: kv[1])] == _abi.KERNEL_NAMES
+    assert int(re.search(r"SNN_NKERNEL = (\d+)", src).group(1)) == _abi.SNN_NKERNEL
+    assert int(re.search(r"SNN_NSTAT = (\d+)", src).group(1)) == _abi.SNN_NSTAT
+
+
+def test_one_hip_runtime_in_process():
+    """Loading the library leaves exactly one libamdhip64 mapped (torch's):
+    two runtimes in one process find no device."""
+    code = ("from paper_2205_07125_amd import _abi; _abi.lib(); "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([os.sys.executable, "-c", code], cwd=ROOT, capture_output=True,
+                         text=True, check=True).stdout
+    assert out.strip() == "1"
