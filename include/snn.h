@@ -149,13 +149,21 @@ typedef struct {
   uint64_t recv_total;        /* total per-partition receive-list capacity (entries) */
   uint32_t log_steps;         /* steps kept for snn_read_spikes / snn_read_counters (>= 1);
                                  older steps are overwritten */
-  uint32_t reserved0;
+  float input_bound;          /* largest synaptic input a neuron can get in one step (mV):
+                                 max over neurons of the sum of |w| over its incoming
+                                 synapses (snn_setup_input_bound computes it); > 0.  The
+                                 input of a step is summed exactly in fixed point with
+                                 F = floor(log2(2^30 / input_bound)) fractional bits
+                                 (8 <= F <= 30 required) after rounding each weight to
+                                 a multiple of 2^-F, then rounded once to binary32;
+                                 sums of weights that are multiples of 2^-F (the dyadic
+                                 weights of the parity tests) are exact */
   uint64_t log_cap;           /* spike-log capacity in neuron ids */
   uint64_t bin_cap;           /* events per delivery bin: one bin per (ring slot, tile of
-                                 16384 neurons, delay, delivery block of 32 per delay);
+                                 neurons, delay, delivery block), see snn_bin_geometry;
                                  events beyond it take the (slower) dense-ring path */
-  uint64_t stage_cap;         /* remote events per (delay, receive-side block of 256) and
-                                 step; beyond it, the dense-ring path */
+  uint64_t stage_cap;         /* remote events per (delay, receive-side block) and step,
+                                 see snn_bin_geometry; beyond it, the dense-ring path */
 } snn_params;
 
 /* Network arrays in device memory.  nnz = row_ptr[n_neurons]; pairs =
@@ -245,6 +253,13 @@ snn_status snn_ring_events(snn_handle h, uint64_t* n);
    The steps advance the simulation like snn_run.  Synchronises.  Order: as
    snn_step. */
 snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg_ms);
+
+/* Geometry of the binned delivery, for sizing snn_params.bin_cap and
+   stage_cap: *tile_neurons neurons share a bin; each (step slot, tile, delay)
+   has *deliver_blocks sub-bins (one per writing block), each of bin_cap
+   events; each delay has *stage_blocks receive queues of stage_cap events.
+   Any pointer may be NULL. */
+void snn_bin_geometry(uint32_t* tile_neurons, uint32_t* deliver_blocks, uint32_t* stage_blocks);
 
 /* Steps completed so far (host-side count of enqueued steps). */
 uint64_t snn_time(snn_handle h);

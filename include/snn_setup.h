@@ -19,6 +19,7 @@
  *   snn_setup_create(...)               count out-degrees -> nnz
  *   snn_setup_fill_rows(...)            row_ptr, n_local, tgt_delay, weight
  *   snn_setup_sizes(...)                pairs, bucket_total, recv_total
+ *   snn_setup_input_bound(...)          snn_params.input_bound
  *   snn_setup_fill_routes(...)          vp_ptr, vp_part, vp_seg, part_of_neuron,
  *                                       bucket_off, recv_off
  *   snn_setup_destroy(...)
@@ -75,6 +76,12 @@ snn_status snn_setup_sizes(snn_setup_handle h, uint64_t* nnz, uint64_t* pairs,
    uint16 per weight_type). */
 snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n_local,
                                uint16_t* delay_off, uint32_t* tgt_delay, void* weight);
+
+/* Largest synaptic input a neuron can receive in one step: the maximum over
+   neurons of the sum of |w| (as stored, i.e. after BF16 rounding) over the
+   neuron's incoming synapses; the value for snn_params.input_bound, rounded
+   up to a float.  Known after snn_setup_fill_rows (SNN_ERR_BAD_STATE before). */
+snn_status snn_setup_input_bound(snn_setup_handle h, float* bound);
 
 /* Destination-partition lists and capacity bounds: vp_ptr[N+1], vp_part[pairs],
    vp_seg[pairs], part_of_neuron[N], bucket_off[n_nodes+1] (bucket of node n:

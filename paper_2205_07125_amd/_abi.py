@@ -32,11 +32,12 @@ SNN_NKERNEL = len(KERNEL_NAMES)
 EXPORTED = [
     "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route",
     "snn_deliver", "snn_run", "snn_kernel_times", "snn_flush", "snn_sync", "snn_time",
+    "snn_bin_geometry",
     "snn_ring_events",
     "snn_read_spikes", "snn_read_routes",
     "snn_read_counters", "snn_destroy", "snn_last_error",
     "snn_setup_create", "snn_setup_sizes", "snn_setup_fill_rows", "snn_setup_fill_routes",
-    "snn_setup_destroy",
+    "snn_setup_input_bound", "snn_setup_destroy",
 ]
 
 u32, u64, i32, f32, f64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
@@ -51,7 +52,7 @@ class snn_params(ctypes.Structure):
         ("seed", u64), ("weight_type", u32), ("flags", u32),
         ("raster_thr_on", u32), ("raster_thr_off", u32), ("raster_period", u32), ("raster_on", u32),
         ("bucket_total", u64), ("recv_total", u64),
-        ("log_steps", u32), ("reserved0", u32), ("log_cap", u64),
+        ("log_steps", u32), ("input_bound", f32), ("log_cap", u64),
         ("bin_cap", u64), ("stage_cap", u64),
     ]
 
@@ -109,6 +110,7 @@ def lib() -> ctypes.CDLL:
             "snn_sync": (I, [vp]),
             "snn_ring_events": (I, [vp, ctypes.POINTER(u64)]),
             "snn_time": (u64, [vp]),
+            "snn_bin_geometry": (None, [ctypes.POINTER(u32)] * 3),
             "snn_read_spikes": (I, [vp, u64, u32, vp, u64, vp, ctypes.POINTER(u64)]),
             "snn_read_routes": (I, [vp, I, vp, vp, u64, ctypes.POINTER(u64)]),
             "snn_read_counters": (I, [vp, u64, u32, vp]),
@@ -118,6 +120,7 @@ def lib() -> ctypes.CDLL:
             "snn_setup_sizes": (I, [vp] + [ctypes.POINTER(u64)] * 4),
             "snn_setup_fill_rows": (I, [vp] * 6),
             "snn_setup_fill_routes": (I, [vp] * 7),
+            "snn_setup_input_bound": (I, [vp, ctypes.POINTER(f32)]),
             "snn_setup_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
@@ -188,6 +191,13 @@ def snn_ring_events(h) -> int:
     n = u64()
     check(lib().snn_ring_events(h, ctypes.byref(n)))
     return n.value
+
+
+def snn_bin_geometry():
+    """-> (tile_neurons, deliver_blocks, stage_blocks) of the binned delivery."""
+    a, b, c = u32(), u32(), u32()
+    lib().snn_bin_geometry(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
 
 
 def snn_time(h) -> int:

@@ -22,6 +22,8 @@
 // flagged.  The work is sparse gather/scatter: no dense contraction, no MFMA.
 // Compiled with -ffp-contract=off: the membrane update rounds after every
 // operation, exactly as specified.
+#include <algorithm>
+
 #include "snn_internal.h"
 
 namespace snn {
@@ -143,10 +145,19 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* pre, uint32_t n, ui
   return k;
 }
 
+// Weight in fixed point (multiples of 2^-F, rounded to nearest even; the
+// scaling by a power of two is exact) and back.
+__device__ __forceinline__ int32_t quantize_w(const KParams& p, float w) {
+  return __float2int_rn(w * p.wq_scale);
+}
+__device__ __forceinline__ float dequantize_w(const KParams& p, int32_t q) {
+  return static_cast<float>(static_cast<double>(q) * p.wq_inv);
+}
+
 // An event that does not fit its bin goes to the dense ring; the tile is
 // flagged so the update kernel reads that slice of the ring.
-__device__ void ring_fallback(const KParams& p, uint32_t slot, uint32_t tgt, float w) {
-  unsafeAtomicAdd(p.ring + slot * p.ring_stride + tgt, w);
+__device__ void ring_fallback(const KParams& p, uint32_t slot, uint32_t tgt, int32_t wq) {
+  unsafeAtomicAdd(p.ring + slot * p.ring_stride + tgt, dequantize_w(p, wq));
   p.dirty[slot * p.n_tiles + (tgt >> TILE_SHIFT)] = 1u;
   atomicAdd(reinterpret_cast<unsigned long long*>(&p.st->ring_events), 1ull);
 }
@@ -167,7 +178,9 @@ constexpr uint32_t MAX_SUBBINS = SNN_MAX_DELAY * DELIVER_BLOCKS;
 constexpr uint32_t SUBBIN_SEARCH_TOP = 256;
 static_assert(2 * SUBBIN_SEARCH_TOP > MAX_SUBBINS, "search must reach every sub-bin");
 static_assert(MAX_SUBBINS <= UPDATE_THREADS, "one sub-bin count per thread");
-constexpr int GATHER_UNROLL = 4;
+constexpr int GATHER_UNROLL = 4;          // loads in flight per thread (deliver, receive)
+constexpr int ARRIVE_UNROLL = 8;          // loads in flight per thread (update's gather)
+constexpr int ROUTE_UNROLL = 8;           // destination-list loads in flight per thread
 
 // Look-back word: [63:34] step tag, [33:32] status, [31:0] count.
 constexpr uint32_t LB_AGG = 1u, LB_INCL = 2u;
@@ -235,7 +248,7 @@ static_assert(UPDATE_NPT % 4 == 0 && UPDATE_NPT <= 32, "fire bits of a thread fi
 __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   constexpr int NQ = UPDATE_NPT / 4;
   constexpr int NW = UPDATE_THREADS / 64;
-  __shared__ float s_syn[TILE];
+  __shared__ int32_t s_acc[TILE];     // arriving input, fixed point (units of 2^-F)
   __shared__ uint32_t s_cnt[NQ][NW];    // spikes per (quad, wave)
   __shared__ uint32_t s_qoff[NQ][NW];   // their offsets in the block's order
   __shared__ uint32_t s_wsum[NW];
@@ -273,7 +286,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     }
     if (tid >= 1 && tid < SNN_NSTAT) p.stats[static_cast<uint64_t>(row) * SNN_NSTAT + tid] = 0;
   }
-  for (uint32_t i = tid; i < TILE; i += UPDATE_THREADS) s_syn[i] = 0.f;
+  for (uint32_t i = tid; i < TILE; i += UPDATE_THREADS) s_acc[i] = 0;
   if (tid == 0) s_dirty = p.dirty[slot * p.n_tiles + tile];
   for (uint32_t i = tid; i < POIS_LUT_SIZE / 16; i += UPDATE_THREADS)
     s_lut4[i] = reinterpret_cast<const uint4*>(p.pois_lut)[i];
@@ -311,7 +324,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   // Arriving input of step t: the sub-bins (slot, tile, d, w) written d steps
   // ago by deliver block w.  Their counts are read in one coalesced load and
   // scanned; the events are then taken as one flat sequence (a power-of-two
-  // search over the scanned counts finds an event's sub-bin), GATHER_UNROLL
+  // search over the scanned counts finds an event's sub-bin), ARRIVE_UNROLL
   // loads in flight per thread.
   const uint32_t md = p.D - 1;
   const uint32_t n_sub = md * DELIVER_BLOCKS;
@@ -329,12 +342,12 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   }
   __syncthreads();
   const uint32_t n_arrive = s_bpre[n_sub];
-  for (uint32_t e0 = 0; e0 < n_arrive; e0 += GATHER_UNROLL * UPDATE_THREADS) {
+  for (uint32_t e0 = 0; e0 < n_arrive; e0 += ARRIVE_UNROLL * UPDATE_THREADS) {
     // Past the end a lane re-reads the last event (always a valid address)
     // and skips the add, so the loads carry no branch and issue together.
-    uint32_t e[GATHER_UNROLL], ec[GATHER_UNROLL], k[GATHER_UNROLL];
+    uint32_t e[ARRIVE_UNROLL], ec[ARRIVE_UNROLL], k[ARRIVE_UNROLL];
 #pragma unroll
-    for (int v = 0; v < GATHER_UNROLL; ++v) {
+    for (int v = 0; v < ARRIVE_UNROLL; ++v) {
       e[v] = e0 + v * UPDATE_THREADS + tid;
       ec[v] = min(e[v], n_arrive - 1);
       k[v] = 0;
@@ -343,32 +356,25 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
 #pragma unroll
     for (uint32_t step = SUBBIN_SEARCH_TOP; step; step >>= 1) {
 #pragma unroll
-      for (int v = 0; v < GATHER_UNROLL; ++v) {
+      for (int v = 0; v < ARRIVE_UNROLL; ++v) {
         const uint32_t m = k[v] + step;
         if (m < n_sub && s_bpre[m] <= ec[v]) k[v] = m;
       }
     }
-    Event x[GATHER_UNROLL];
+    Event x[ARRIVE_UNROLL];
 #pragma unroll
-    for (int v = 0; v < GATHER_UNROLL; ++v)
+    for (int v = 0; v < ARRIVE_UNROLL; ++v)
       x[v] = p.bins[(sb0 + k[v]) * p.bin_cap + (ec[v] - s_bpre[k[v]])];
 #pragma unroll
-    for (int v = 0; v < GATHER_UNROLL; ++v)
-      if (e[v] < n_arrive) atomicAdd(&s_syn[x[v].tgt], x[v].w);
+    for (int v = 0; v < ARRIVE_UNROLL; ++v)
+      if (e[v] < n_arrive) atomicAdd(&s_acc[x[v].tgt], x[v].wq);
   }
   __syncthreads();
+  // events that did not fit their bins are in this tile's slice of the ring
+  // slot; a flagged tile reads (and clears) it with the neuron state
   float* ring_slot = p.ring + static_cast<uint64_t>(slot) * p.ring_stride;
-  if (s_dirty) {
-    // events that did not fit their bins: this tile's slice of the ring slot
-    for (uint32_t i = tid; i < TILE; i += UPDATE_THREADS) {
-      if (blk0 + i < p.N) {
-        s_syn[i] += ring_slot[blk0 + i];
-        ring_slot[blk0 + i] = 0.f;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) p.dirty[slot * p.n_tiles + tile] = 0u;
-  }
+  const bool dirty = s_dirty != 0;
+  if (dirty && tid == 0) p.dirty[slot * p.n_tiles + tile] = 0u;
 
   uint32_t thr_raster = 0;
   if (p.forced) thr_raster = phase < p.raster_on ? p.raster_on_thr : p.raster_off_thr;
@@ -390,8 +396,21 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (p.forced) rnd2 = philox4x32_10(i0 >> 2, t32, STREAM_RASTER, 0u, p.seed_lo, p.seed_hi);
     const uint32_t r1[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
     const uint32_t r2[4] = {rnd2.x, rnd2.y, rnd2.z, rnd2.w};
-    const float4 syn4 = *reinterpret_cast<const float4*>(&s_syn[l0]);
-    const float syn[4] = {syn4.x, syn4.y, syn4.z, syn4.w};
+    // arriving input: the exact fixed-point sum rounded once to binary32,
+    // plus the ring slice of a flagged tile
+    const int4 acc4 = *reinterpret_cast<const int4*>(&s_acc[l0]);
+    const int32_t acc[4] = {acc4.x, acc4.y, acc4.z, acc4.w};
+    float syn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) syn[k] = static_cast<float>(static_cast<double>(acc[k]) * p.wq_inv);
+    if (dirty) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (i0 + k < p.N) {
+          syn[k] = __fadd_rn(syn[k], ring_slot[i0 + k]);
+          ring_slot[i0 + k] = 0.f;
+        }
+    }
     float uu[4] = {u4.x, u4.y, u4.z, u4.w};
     uint32_t rf[4];
 #pragma unroll
@@ -528,81 +547,132 @@ __device__ __forceinline__ void bucket_put(const KParams& p, uint32_t node, uint
   else atomicOr(&p.st->error, ERR_BUCKET);
 }
 
-// Two-level: block b takes a contiguous chunk of the fired sources and works
-// in rounds of SB sources (a source emits at most n_nodes messages).  The
-// chunk's per-source data (id, destination-list bounds, own node) is loaded
-// first, one source per thread, so that a wave's sources need only their
-// destination lists.  Within a round one wave per source finds the runs of
-// equal node in its ascending destination list; the first lane of each run
-// ORs the run into a mask and stages the message in LDS with its rank among
-// the block's messages to that node.  One atomic per (round, node) then
-// reserves the node's bucket space.
-// Dynamic LDS: ROUTE_STAGE staged messages + 2 * n_nodes counters.
+// Two-level: block b takes a contiguous chunk of the fired sources.  Their
+// destination lists are taken as one flat sequence of (source, destination
+// partition) pairs: one thread per source loads the list bounds, a block scan
+// concatenates the lists, and windows of ROUTE_STAGE pairs are loaded into LDS
+// with ROUTE_UNROLL loads in flight per thread.  A pair that starts a run of
+// equal node in its source's (ascending) list ORs the run into the node's
+// mask, from LDS (from global memory past the window's end), and stages the
+// message with its rank among the window's messages to that node; one atomic
+// per (window, node) then reserves the node's bucket space.  A window has at
+// most as many messages as pairs, so the stage never overflows.
+// Dynamic LDS: ROUTE_STAGE messages, node/rank words, pairs and their source
+// index, + 2 * n_nodes counters.
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   uint64_t* s_msg = lds_u64;                                              // [ROUTE_STAGE]
   uint32_t* s_nr = reinterpret_cast<uint32_t*>(s_msg + ROUTE_STAGE);      // node | rank << 16
   uint32_t* l_cnt = s_nr + ROUTE_STAGE;                                   // [n_nodes]
   uint32_t* l_base = l_cnt + p.n_nodes;                                   // [n_nodes]
+  uint16_t* s_vp = reinterpret_cast<uint16_t*>(l_base + p.n_nodes);       // [ROUTE_STAGE]
+  uint16_t* s_k = s_vp + ROUTE_STAGE;                                     // [ROUTE_STAGE]
   constexpr uint32_t NW = ROUTE_THREADS / 64;
   __shared__ uint32_t l_total;
-  __shared__ uint32_t s_src[ROUTE_THREADS], s_own[ROUTE_THREADS];
-  __shared__ int64_t s_j0[ROUTE_THREADS], s_j1[ROUTE_THREADS];
+  __shared__ uint32_t s_src[ROUTE_THREADS], s_own[ROUTE_THREADS], s_pre[ROUTE_THREADS + 1];
+  __shared__ int64_t s_j0[ROUTE_THREADS];
+  __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
   const uint32_t nF = p.st->n_fired;
   const uint32_t row = p.st->cur_row;
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t G = p.G;
   const uint32_t chunk = (nF + gridDim.x - 1) / gridDim.x;
   const uint32_t lo = min(blockIdx.x * chunk, nF), hi = min(lo + chunk, nF);
-  const uint32_t SB = max(1u, min(ROUTE_STAGE / p.n_nodes, static_cast<uint32_t>(ROUTE_THREADS)));
   uint64_t l1 = 0, l2 = 0;
-  for (uint32_t r0 = lo; r0 < hi; r0 += SB) {
-    const uint32_t r1 = min(r0 + SB, hi);
-    for (uint32_t i = tid; i < p.n_nodes; i += ROUTE_THREADS) l_cnt[i] = 0;
-    if (tid == 0) l_total = 0;
-    if (tid < r1 - r0) {
+  for (uint32_t r0 = lo; r0 < hi; r0 += ROUTE_THREADS) {
+    const uint32_t nsrc = min(hi - r0, static_cast<uint32_t>(ROUTE_THREADS));
+    uint32_t len = 0;
+    if (tid < nsrc) {
       const uint32_t s = p.fired[r0 + tid];
+      const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
       s_src[tid] = s;
-      s_own[tid] = static_cast<uint32_t>(p.part[s]) / p.G;
-      s_j0[tid] = p.vp_ptr[s];
-      s_j1[tid] = p.vp_ptr[s + 1];
+      s_own[tid] = static_cast<uint32_t>(p.part[s]) / G;
+      s_j0[tid] = j0;
+      len = static_cast<uint32_t>(j1 - j0);
     }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(len, s_wsum, &tot);
+    s_pre[tid] = ex;
+    if (tid == 0) s_pre[nsrc] = tot;
     __syncthreads();
-    for (uint32_t i = wave; i < r1 - r0; i += NW) {
-      const uint32_t s = s_src[i];
-      const uint32_t own_node = s_own[i];
-      const int64_t j0 = s_j0[i], j1 = s_j1[i];
-      for (int64_t jb = j0; jb < j1; jb += 64) {
-        const int64_t j = jb + lane;
-        if (j >= j1) continue;
-        const uint32_t node = p.vp_part[j] / p.G;
-        if (j != j0 && p.vp_part[j - 1] / p.G == node) continue;
-        const uint64_t msg = (static_cast<uint64_t>(j - j0) << 40) |
-                             (static_cast<uint64_t>(node_mask(p, j, j1, node)) << 32) | s;
-        const uint32_t k = atomicAdd(&l_total, 1u);
-        if (k < ROUTE_STAGE) {
-          const uint32_t rk = atomicAdd(&l_cnt[node], 1u);
-          s_msg[k] = msg;
-          s_nr[k] = node | (rk << 16);
-        } else {
-          bucket_put(p, node, atomicAdd(p.bucket_cnt + node * CNT_STRIDE, 1u), msg);
+    for (uint32_t w0 = 0; w0 < tot; w0 += ROUTE_STAGE) {
+      const uint32_t nwin = min(tot - w0, ROUTE_STAGE);
+      for (uint32_t i = tid; i < p.n_nodes; i += ROUTE_THREADS) l_cnt[i] = 0;
+      if (tid == 0) l_total = 0;
+      // the window's pairs into LDS
+      for (uint32_t i0 = 0; i0 < nwin; i0 += ROUTE_UNROLL * ROUTE_THREADS) {
+        uint32_t vp[ROUTE_UNROLL], kk[ROUTE_UNROLL];
+#pragma unroll
+        for (int v = 0; v < ROUTE_UNROLL; ++v) {
+          const uint32_t e = w0 + min(i0 + v * ROUTE_THREADS + tid, nwin - 1);
+          kk[v] = owner_of<ROUTE_THREADS / 2>(s_pre, nsrc, e);
+          vp[v] = p.vp_part[s_j0[kk[v]] + (e - s_pre[kk[v]])];
         }
-        if (node == own_node) ++l1; else ++l2;
+#pragma unroll
+        for (int v = 0; v < ROUTE_UNROLL; ++v) {
+          const uint32_t i = i0 + v * ROUTE_THREADS + tid;
+          if (i < nwin) {
+            s_vp[i] = static_cast<uint16_t>(vp[v]);
+            s_k[i] = static_cast<uint16_t>(kk[v]);
+          }
+        }
       }
+      __syncthreads();
+      // one message per run of equal node
+      for (uint32_t i = tid; i < nwin; i += ROUTE_THREADS) {
+        const uint32_t k = s_k[i];
+        const uint32_t off = w0 + i - s_pre[k];             // position in the source's list
+        const uint32_t len_k = s_pre[k + 1] - s_pre[k];
+        const uint32_t node = s_vp[i] / G;
+        if (off > 0) {
+          const uint32_t prev = i > 0 ? s_vp[i - 1] : p.vp_part[s_j0[k] + off - 1];
+          if (prev / G == node) continue;
+        }
+        uint32_t mask = 0;
+        for (uint32_t x = off; x < len_k; ++x) {
+          const uint32_t at = i + (x - off);
+          const uint32_t v = at < nwin ? s_vp[at] : p.vp_part[s_j0[k] + x];
+          if (v / G != node) break;
+          mask |= 1u << (v - G * node);
+        }
+        const uint64_t msg = (static_cast<uint64_t>(off) << 40) |
+                             (static_cast<uint64_t>(mask) << 32) | s_src[k];
+        const uint32_t slot = atomicAdd(&l_total, 1u);
+        const uint32_t rk = atomicAdd(&l_cnt[node], 1u);
+        s_msg[slot] = msg;
+        s_nr[slot] = node | (rk << 16);
+        if (node == s_own[k]) ++l1; else ++l2;
+      }
+      __syncthreads();
+      for (uint32_t n = tid; n < p.n_nodes; n += ROUTE_THREADS) {
+        const uint32_t c = l_cnt[n];
+        if (c) l_base[n] = atomicAdd(p.bucket_cnt + n * CNT_STRIDE, c);
+      }
+      __syncthreads();
+      // bucket bounds of ROUTE_UNROLL messages loaded together (clamped
+      // indices keep the loads unconditional), then the stores
+      const uint32_t n_msg = l_total;
+      for (uint32_t k0 = tid; k0 < n_msg; k0 += ROUTE_UNROLL * ROUTE_THREADS) {
+        uint64_t o[ROUTE_UNROLL], o1[ROUTE_UNROLL];
+#pragma unroll
+        for (int v = 0; v < ROUTE_UNROLL; ++v) {
+          const uint32_t node = s_nr[min(k0 + v * ROUTE_THREADS, n_msg - 1)] & 0xFFFFu;
+          o[v] = p.bucket_off[node];
+          o1[v] = p.bucket_off[node + 1];
+        }
+#pragma unroll
+        for (int v = 0; v < ROUTE_UNROLL; ++v) {
+          const uint32_t k = k0 + v * ROUTE_THREADS;
+          if (k >= n_msg) continue;
+          const uint32_t nr = s_nr[k];
+          const uint64_t pos = o[v] + l_base[nr & 0xFFFFu] + (nr >> 16);
+          if (pos < o1[v]) p.bucket[pos] = s_msg[k];
+          else atomicOr(&p.st->error, ERR_BUCKET);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (uint32_t n = tid; n < p.n_nodes; n += ROUTE_THREADS) {
-      const uint32_t c = l_cnt[n];
-      if (c) l_base[n] = atomicAdd(p.bucket_cnt + n * CNT_STRIDE, c);
-    }
-    __syncthreads();
-    const uint32_t staged = min(l_total, ROUTE_STAGE);
-    for (uint32_t k = tid; k < staged; k += ROUTE_THREADS) {
-      const uint32_t nr = s_nr[k];
-      const uint32_t node = nr & 0xFFFFu;
-      bucket_put(p, node, l_base[node] + (nr >> 16), s_msg[k]);
-    }
-    __syncthreads();
   }
   uint64_t* st = p.stats + static_cast<uint64_t>(row) * SNN_NSTAT;
   add_stats(st + SNN_STAT_MSG_L1, l1, st + SNN_STAT_MSG_L2, l2, s_red);
@@ -842,14 +912,14 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
           atomicOr(&p.st->error, ERR_ROUTE);
           continue;
         }
-        const Event ev{td[v] & 0x07FFFFFFu, wt[v]};
+        const Event ev{td[v] & 0x07FFFFFFu, quantize_w(p, wt[v])};
         const uint32_t pos = atomicAdd(&l_pos[d1], 1u);
         if (pos < p.stage_cap) {
           queue[d1 * qstride + pos] = ev;
         } else {
           uint32_t slot = slot0 + d1 + 1;
           if (slot >= p.D) slot -= p.D;
-          ring_fallback(p, slot, ev.tgt, ev.w);
+          ring_fallback(p, slot, ev.tgt, ev.wq);
         }
       }
     }
@@ -875,13 +945,21 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
 // run's start and length, a block scan concatenates them, and the events are
 // loaded in windows of DELIVER_STAGE with GATHER_UNROLL loads in flight per
 // thread (the owner of an event is found by a power-of-two search).
-// Dynamic LDS: DELIVER_STAGE events + tile/rank words + 2 * n_tiles counters.
+// Each window is written out in tile order (a scan of the per-tile counts
+// and a permutation in LDS), so consecutive threads write consecutive
+// positions of one sub-bin.
+// Dynamic LDS: a window of dstage events + tile/rank words + permutation +
+// 3 * n_tiles counters (dstage <= DELIVER_STAGE, set by prepare_kernels to
+// what the device's LDS holds).
 __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   extern __shared__ uint64_t lds_u64[];
-  Event* s_ev = reinterpret_cast<Event*>(lds_u64);                        // [DELIVER_STAGE]
-  uint32_t* s_tr = reinterpret_cast<uint32_t*>(s_ev + DELIVER_STAGE);     // tile | rank << 16
-  uint32_t* l_cnt = s_tr + DELIVER_STAGE;                                 // [n_tiles]
+  const uint32_t S = p.dstage;                                            // window (events)
+  Event* s_ev = reinterpret_cast<Event*>(lds_u64);                        // [S]
+  uint32_t* s_tr = reinterpret_cast<uint32_t*>(s_ev + S);                 // tile | rank << 16
+  uint32_t* l_cnt = s_tr + S;                                             // [n_tiles]
   uint32_t* l_run = l_cnt + p.n_tiles;                                    // [n_tiles]
+  uint32_t* l_pre = l_run + p.n_tiles;                                    // [n_tiles]
+  uint16_t* s_perm = reinterpret_cast<uint16_t*>(l_pre + p.n_tiles);      // [S]
   constexpr uint32_t NW = DELIVER_THREADS / 64;
   constexpr uint32_t QPB = STAGE_BLOCKS / DELIVER_BLOCKS;                 // queues per block
   __shared__ uint64_t s_base[DELIVER_THREADS];   // first event of each segment
@@ -902,23 +980,44 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   }
   uint64_t events = 0;
 
-  // event (global target, weight) into LDS slot k
-  auto put = [&](uint32_t k, uint32_t tgt, float wt) {
+  // event (global target, quantized weight) into LDS slot k
+  auto put = [&](uint32_t k, uint32_t tgt, int32_t wq) {
     const uint32_t tile = tgt >> TILE_SHIFT;
     const uint32_t rk = atomicAdd(&l_cnt[tile], 1u);
-    s_ev[k] = Event{tgt & (TILE - 1), wt};
+    s_ev[k] = Event{tgt & (TILE - 1), wq};
     s_tr[k] = tile | (rk << 16);
   };
-  // write the n staged events into the sub-bins and advance the running counts
+  // write the n staged events into the sub-bins in tile order and advance
+  // the running counts
   auto flush = [&](uint32_t n) {
     __syncthreads();
+    {
+      // exclusive scan of the window's per-tile counts into l_pre
+      const uint32_t per = (p.n_tiles + DELIVER_THREADS - 1) / DELIVER_THREADS;
+      const uint32_t i0 = min(tid * per, p.n_tiles), i1 = min(i0 + per, p.n_tiles);
+      uint32_t sum = 0;
+      for (uint32_t i = i0; i < i1; ++i) sum += l_cnt[i];
+      uint32_t tot;
+      uint32_t ex = block_excl_scan(sum, s_wsum, &tot);
+      for (uint32_t i = i0; i < i1; ++i) {
+        l_pre[i] = ex;
+        ex += l_cnt[i];
+      }
+    }
+    __syncthreads();
     for (uint32_t k = tid; k < n; k += DELIVER_THREADS) {
+      const uint32_t tr = s_tr[k];
+      s_perm[l_pre[tr & 0xFFFFu] + (tr >> 16)] = static_cast<uint16_t>(k);
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < n; j += DELIVER_THREADS) {
+      const uint32_t k = s_perm[j];
       const uint32_t tile = s_tr[k] & 0xFFFFu;
-      const uint64_t pos = static_cast<uint64_t>(l_run[tile]) + (s_tr[k] >> 16);
+      const uint64_t pos = static_cast<uint64_t>(l_run[tile]) + (j - l_pre[tile]);
       if (pos < p.bin_cap) {
         p.bins[subbin(p, slot, tile, d, w) * p.bin_cap + pos] = s_ev[k];
       } else {
-        ring_fallback(p, slot, (tile << TILE_SHIFT) | s_ev[k].tgt, s_ev[k].w);
+        ring_fallback(p, slot, (tile << TILE_SHIFT) | s_ev[k].tgt, s_ev[k].wq);
       }
     }
     __syncthreads();
@@ -947,8 +1046,8 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
     s_pre[tid] = ex;
     __syncthreads();
     events += tid == 0 ? tot : 0u;
-    for (uint32_t e0 = 0; e0 < tot; e0 += DELIVER_STAGE) {
-      const uint32_t n_win = min(tot - e0, DELIVER_STAGE);
+    for (uint32_t e0 = 0; e0 < tot; e0 += S) {
+      const uint32_t n_win = min(tot - e0, S);
       for (uint32_t i0 = 0; i0 < n_win; i0 += GATHER_UNROLL * DELIVER_THREADS) {
         uint32_t td[GATHER_UNROLL];
         float wt[GATHER_UNROLL];
@@ -963,7 +1062,7 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
 #pragma unroll
         for (int v = 0; v < GATHER_UNROLL; ++v) {
           const uint32_t le = i0 + v * DELIVER_THREADS + tid;
-          if (le < n_win) put(le, td[v] & 0x07FFFFFFu, wt[v]);
+          if (le < n_win) put(le, td[v] & 0x07FFFFFFu, quantize_w(p, wt[v]));
         }
       }
       flush(n_win);
@@ -980,8 +1079,8 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
     if (tid < QPB) s_pre[tid] = ex;
     __syncthreads();
     const Event* q0 = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + w) * p.stage_cap;
-    for (uint32_t e0 = 0; e0 < tot; e0 += DELIVER_STAGE) {
-      const uint32_t n_win = min(tot - e0, DELIVER_STAGE);
+    for (uint32_t e0 = 0; e0 < tot; e0 += S) {
+      const uint32_t n_win = min(tot - e0, S);
       for (uint32_t i0 = 0; i0 < n_win; i0 += GATHER_UNROLL * DELIVER_THREADS) {
         Event x[GATHER_UNROLL];
 #pragma unroll
@@ -993,7 +1092,7 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
 #pragma unroll
         for (int v = 0; v < GATHER_UNROLL; ++v) {
           const uint32_t le = i0 + v * DELIVER_THREADS + tid;
-          if (le < n_win) put(le, x[v].tgt, x[v].w);
+          if (le < n_win) put(le, x[v].tgt, x[v].wq);
         }
       }
       flush(n_win);
@@ -1029,7 +1128,7 @@ __global__ __launch_bounds__(256) void k_flush(KParams p) {
       const Event* ev = p.bins + sb * p.bin_cap;
       for (uint32_t e = threadIdx.x; e < c; e += 256)
         unsafeAtomicAdd(p.ring + slot * p.ring_stride + (tile << TILE_SHIFT) + ev[e].tgt,
-                        ev[e].w);
+                        dequantize_w(p, ev[e].wq));
       if (c && threadIdx.x == 0) any = 1;
       __syncthreads();
       if (threadIdx.x == 0) p.bin_cnt[sb] = 0;
@@ -1058,7 +1157,8 @@ hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks) {
 }
 
 size_t route_lds_bytes(const KParams& p) {
-  return ROUTE_STAGE * (sizeof(uint64_t) + sizeof(uint32_t)) + 2ull * p.n_nodes * sizeof(uint32_t);
+  return ROUTE_STAGE * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(uint16_t)) +
+         2ull * p.n_nodes * sizeof(uint32_t);
 }
 
 hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks) {
@@ -1082,8 +1182,12 @@ hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* m
   return hipGetLastError();
 }
 
+// LDS bytes of one deliver event and of the per-tile counters.
+constexpr size_t DELIVER_EVENT_LDS = sizeof(Event) + sizeof(uint32_t) + sizeof(uint16_t);
+static_assert(DELIVER_STAGE <= 65536, "window ranks and permutation fit 16 bits");
+
 size_t deliver_lds_bytes(const KParams& p) {
-  return DELIVER_STAGE * (sizeof(Event) + sizeof(uint32_t)) + 2ull * p.n_tiles * sizeof(uint32_t);
+  return p.dstage * DELIVER_EVENT_LDS + 3ull * p.n_tiles * sizeof(uint32_t);
 }
 
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks) {
@@ -1098,10 +1202,22 @@ hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t*
   return hipGetLastError();
 }
 
-hipError_t prepare_kernels(const KParams& p) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_route_two_level),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     static_cast<int>(route_lds_bytes(p)));
+hipError_t prepare_kernels(KParams& p) {
+  // deliver window: DELIVER_STAGE events, less where many tiles leave less LDS
+  int dev = 0, lds_max = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  hipFuncAttributes fa{};
+  if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_deliver));
+  if (e != hipSuccess) return e;
+  const int64_t room = int64_t(lds_max) - int64_t(fa.sharedSizeBytes) -
+                       int64_t(3ull * p.n_tiles * sizeof(uint32_t));
+  const int64_t fit = room > 0 ? (room / int64_t(DELIVER_EVENT_LDS)) & ~int64_t(DELIVER_THREADS - 1) : 0;
+  p.dstage = static_cast<uint32_t>(std::min<int64_t>(DELIVER_STAGE, fit));
+  if (p.dstage < DELIVER_THREADS) return hipErrorInvalidConfiguration;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_route_two_level),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(route_lds_bytes(p)));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver),
                              hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -2,6 +2,7 @@
 // parameter validation, workspace carve-up, the step -> route -> deliver
 // state machine, HIP-graph replay of whole steps, and read-back.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -103,6 +104,15 @@ void build_pois_lut(const uint32_t* thr, std::vector<uint8_t>& lut) {
   }
 }
 
+// Fractional bits of the fixed-point input sums: the largest F <= 30 with
+// input_bound * 2^F <= 2^30, which leaves 2^30 of headroom in int32 for the
+// rounding of each weight to a multiple of 2^-F.
+int input_shift(float bound) {
+  int f = 30;
+  while (f > 0 && std::ldexp(double(bound), f) > std::ldexp(1.0, 30)) --f;
+  return f;
+}
+
 snn_status check_params(const snn_params* p) {
   if (!p) return fail(SNN_ERR_INVALID_ARG, "params is NULL");
   if (p->n_neurons == 0 || p->n_neurons > SNN_MAX_NEURONS)
@@ -126,6 +136,12 @@ snn_status check_params(const snn_params* p) {
   if (p->log_steps == 0) return fail(SNN_ERR_INVALID_ARG, "log_steps must be >= 1");
   if (p->bin_cap > 0xFFFFFFFFull || p->stage_cap > 0xFFFFFFFFull)
     return fail(SNN_ERR_INVALID_ARG, "bin_cap and stage_cap must fit 32 bits");
+  if (!(p->input_bound > 0.f) || !std::isfinite(p->input_bound))
+    return fail(SNN_ERR_INVALID_ARG, "input_bound must be a positive finite number");
+  const int f = input_shift(p->input_bound);
+  if (f < 8)
+    return fail(SNN_ERR_UNSUPPORTED, "input_bound %g mV leaves fewer than 8 fractional bits",
+                double(p->input_bound));
   return SNN_OK;
 }
 
@@ -216,6 +232,9 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.log_steps = params->log_steps;
   k.log_cap = params->log_cap;
   k.bin_cap = params->bin_cap;
+  const int wq_shift = input_shift(params->input_bound);
+  k.wq_scale = std::ldexp(1.0f, wq_shift);
+  k.wq_inv = std::ldexp(1.0, -wq_shift);
   k.stage_cap = params->stage_cap;
   k.row_ptr = net->row_ptr;
   k.n_local = net->n_local;
@@ -361,9 +380,12 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
   if (mode < SNN_ROUTE_TWO_LEVEL || mode > SNN_ROUTE_BOTH)
     return fail(SNN_ERR_INVALID_ARG, "route mode %d", mode);
   if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_kernel_times called in the middle of a step");
-  hipEvent_t marks[2 * SNN_NKERNEL] = {};
-  double total[SNN_NKERNEL] = {};
-  bool used[SNN_NKERNEL] = {};
+  // Every step gets its own events and nothing synchronises until the end:
+  // the launches queue up behind each other as in a normal run, so no start
+  // event fires on an idle queue ahead of its kernel.
+  const bool launched[SNN_NKERNEL] = {
+      true, mode != SNN_ROUTE_FLAT, mode != SNN_ROUTE_FLAT, mode != SNN_ROUTE_TWO_LEVEL, true, true};
+  std::vector<hipEvent_t> marks(size_t(2) * SNN_NKERNEL * n_steps, nullptr);
   snn_status st = SNN_OK;
   for (auto& e : marks) {
     hipError_t r = hipEventCreate(&e);
@@ -372,42 +394,35 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
       break;
     }
   }
+  double total[SNN_NKERNEL] = {};
   for (uint32_t i = 0; i < n_steps && st == SNN_OK; ++i) {
-    // the launchers record only the marks of the kinds they launch; a kind
-    // counts as launched when its end mark completed after its start mark
-    hipError_t r = launch_update(h->kp, h->stream, marks);
-    if (r == hipSuccess) r = launch_route(h->kp, mode, h->stream, marks);
-    if (r == hipSuccess) r = launch_deliver(h->kp, mode, h->stream, marks);
-    if (r == hipSuccess) r = hipStreamSynchronize(h->stream);
-    if (r != hipSuccess) {
-      st = fail(SNN_ERR_HIP, "timed step: %s", hipGetErrorString(r));
-      break;
-    }
+    hipEvent_t* m = marks.data() + size_t(2) * SNN_NKERNEL * i;
+    hipError_t r = launch_update(h->kp, h->stream, m);
+    if (r == hipSuccess) r = launch_route(h->kp, mode, h->stream, m);
+    if (r == hipSuccess) r = launch_deliver(h->kp, mode, h->stream, m);
+    if (r != hipSuccess) st = fail(SNN_ERR_HIP, "timed step: %s", hipGetErrorString(r));
     h->t_host += 1;
     h->route_mode = mode;
     h->routed_t = h->t_host;
-    for (int k = 0; k < SNN_NKERNEL; ++k) {
-      const bool launched = k == SNN_KERNEL_UPDATE || k == SNN_KERNEL_RECV_STAGE ||
-                            k == SNN_KERNEL_DELIVER ||
-                            ((k == SNN_KERNEL_ROUTE_TWO_LEVEL || k == SNN_KERNEL_EXPAND) &&
-                             mode != SNN_ROUTE_FLAT) ||
-                            (k == SNN_KERNEL_ROUTE_FLAT && mode != SNN_ROUTE_TWO_LEVEL);
-      if (!launched) continue;
-      float ms = 0.f;
-      r = hipEventElapsedTime(&ms, marks[2 * k], marks[2 * k + 1]);
-      if (r != hipSuccess) {
-        st = fail(SNN_ERR_HIP, "hipEventElapsedTime: %s", hipGetErrorString(r));
-        break;
-      }
-      total[k] += ms;
-      used[k] = true;
-    }
   }
+  if (st == SNN_OK) {
+    hipError_t r = hipStreamSynchronize(h->stream);
+    if (r != hipSuccess) st = fail(SNN_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(r));
+  }
+  for (uint32_t i = 0; i < n_steps && st == SNN_OK; ++i)
+    for (int k = 0; k < SNN_NKERNEL && st == SNN_OK; ++k) {
+      if (!launched[k]) continue;
+      const hipEvent_t* m = marks.data() + size_t(2) * SNN_NKERNEL * i;
+      float ms = 0.f;
+      hipError_t r = hipEventElapsedTime(&ms, m[2 * k], m[2 * k + 1]);
+      if (r != hipSuccess) st = fail(SNN_ERR_HIP, "hipEventElapsedTime: %s", hipGetErrorString(r));
+      total[k] += ms;
+    }
   for (auto& e : marks)
     if (e) (void)hipEventDestroy(e);
   if (st != SNN_OK) return st;
   for (int k = 0; k < SNN_NKERNEL; ++k)
-    avg_ms[k] = used[k] && n_steps ? static_cast<float>(total[k] / n_steps) : 0.f;
+    avg_ms[k] = launched[k] && n_steps ? static_cast<float>(total[k] / n_steps) : 0.f;
   return sync_and_check(h, nullptr);
 }
 
@@ -437,6 +452,12 @@ snn_status snn_sync(snn_handle h) {
 }
 
 uint64_t snn_time(snn_handle h) { return h ? h->t_host : 0; }
+
+void snn_bin_geometry(uint32_t* tile_neurons, uint32_t* deliver_blocks, uint32_t* stage_blocks) {
+  if (tile_neurons) *tile_neurons = TILE;
+  if (deliver_blocks) *deliver_blocks = DELIVER_BLOCKS;
+  if (stage_blocks) *stage_blocks = STAGE_BLOCKS;
+}
 
 snn_status snn_ring_events(snn_handle h, uint64_t* n) {
   if (!h || !n) return fail(SNN_ERR_INVALID_ARG, "NULL argument");

@@ -6,6 +6,7 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -84,6 +85,7 @@ struct snn_setup {
   std::vector<uint64_t> bucket_cap; // n_nodes
   std::vector<uint64_t> recv_cap;   // P
   uint64_t nnz = 0, pairs = 0, bucket_total = 0, recv_total = 0;
+  double input_bound = 0.0;         // max over targets of the sum of |w| of their inputs
   bool rows_done = false;
 };
 
@@ -163,6 +165,15 @@ snn_status snn_setup_sizes(snn_setup_handle h, uint64_t* nnz, uint64_t* pairs,
   return SNN_OK;
 }
 
+snn_status snn_setup_input_bound(snn_setup_handle h, float* bound) {
+  if (!h || !bound) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  if (!h->rows_done) return fail(SNN_ERR_BAD_STATE, "input bound needs snn_setup_fill_rows first");
+  float b = float(h->input_bound);
+  if (double(b) < h->input_bound) b = std::nextafter(b, INFINITY);
+  *bound = b;
+  return SNN_OK;
+}
+
 snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n_local,
                                uint16_t* delay_off, uint32_t* tgt_delay, void* weight) {
   if (!h || !row_ptr || !n_local || !delay_off || !tgt_delay || !weight)
@@ -186,11 +197,14 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
   uint16_t* wb = static_cast<uint16_t*>(weight);
   syn_gen* gen = h->gen;
 
-  // Pass 2: place every synapse in its source row (order fixed by the sort).
+  // Pass 2: place every synapse in its source row (order fixed by the sort),
+  // and bound each target's input in one step by the sum of its |w|.
   Progress prog("place", N, h->spec.verbose != 0);
-#pragma omp parallel for num_threads(h->threads) schedule(dynamic, 256)
+  double bound = 0.0;
+#pragma omp parallel for num_threads(h->threads) schedule(dynamic, 256) reduction(max : bound)
   for (int64_t t = 0; t < int64_t(N); ++t) {
     if ((t & 4095) == 0) prog.add(std::min<int64_t>(4096, int64_t(N) - t));
+    double in_abs = 0.0;
     for (uint32_t k = 0; k < K; ++k) {
       uint32_t src, d, vp;
       float w;
@@ -198,10 +212,21 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
       const uint64_t at = __atomic_fetch_add(cur + src, 1ull, __ATOMIC_RELAXED);
       tgt_delay[at] = (d << 27) | uint32_t(t);
       tag[at] = vp == syn_part_of(gen, src) ? 0 : uint16_t(vp + 1);
-      if (bf16) wb[at] = to_bf16(w);
-      else wf[at] = w;
+      if (bf16) {
+        const uint16_t b = to_bf16(w);
+        wb[at] = b;
+        uint32_t bits = uint32_t(b) << 16;
+        float wr;
+        std::memcpy(&wr, &bits, 4);
+        in_abs += std::fabs(double(wr));
+      } else {
+        wf[at] = w;
+        in_abs += std::fabs(double(w));
+      }
     }
+    bound = std::max(bound, in_abs);
   }
+  h->input_bound = bound;
 
   // Sort rows; count own-partition synapses, destination partitions, and the
   // per-node / per-partition capacity bounds.

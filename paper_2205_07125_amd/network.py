@@ -19,11 +19,6 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_P)
 
 
-TILE = 1 << 14            # neurons per tile (update block, delivery bin)
-DELIVER_BLOCKS = 32      # delivery blocks per delay
-STAGE_BLOCKS = 256       # receive-side blocks
-
-
 def default_caps(wl, host) -> tuple[int, int]:
     """Bin and staging capacities sized at four times the expected events per
     bin at the workload's highest rate (50 Hz assumed for LIF-driven spikes);
@@ -36,9 +31,10 @@ def default_caps(wl, host) -> tuple[int, int]:
     e_local = spikes * local
     e_remote = spikes * (outdeg - local)
     md = wl.max_delay
-    tiles = (wl.n_neurons + TILE - 1) // TILE
-    per_bin = (e_local + e_remote) / (md * DELIVER_BLOCKS * tiles)
-    per_queue = e_remote / (md * STAGE_BLOCKS)
+    tile, deliver_blocks, stage_blocks = _abi.snn_bin_geometry()
+    tiles = (wl.n_neurons + tile - 1) // tile
+    per_bin = (e_local + e_remote) / (md * deliver_blocks * tiles)
+    per_queue = e_remote / (md * stage_blocks)
     rnd = lambda x: int(-(-(4 * x + 64) // 32) * 32)
     return rnd(per_bin), rnd(per_queue)
 
@@ -107,6 +103,9 @@ class HostNetwork:
                                              _ptr(self.weight)))
             _abi.check(L.snn_setup_sizes(h, *[ctypes.byref(s) for s in sizes]))
             pairs, self.bucket_total, self.recv_total = (s.value for s in sizes[1:])
+            ib = ctypes.c_float()
+            _abi.check(L.snn_setup_input_bound(h, ctypes.byref(ib)))
+            self.input_bound = float(ib.value)
             if verbose:
                 print(f"[setup] rows placed and sorted in {time.time() - t1:.1f}s; "
                       f"{pairs:,} destination pairs", file=sys.stderr, flush=True)

@@ -79,7 +79,8 @@ class Simulation:
             raster_thr_on=dp["raster_thr_on"], raster_thr_off=dp["raster_thr_off"],
             raster_period=max(wl.period_steps, 1), raster_on=wl.on_steps,
             bucket_total=int(bucket_off[-1]), recv_total=int(recv_off[-1]),
-            log_steps=log_steps, log_cap=log_cap, bin_cap=bin_cap, stage_cap=stage_cap)
+            log_steps=log_steps, input_bound=host.input_bound, log_cap=log_cap, bin_cap=bin_cap,
+            stage_cap=stage_cap)
         self.ws_bytes = _abi.snn_workspace_size(self.params)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()

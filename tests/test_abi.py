@@ -43,7 +43,7 @@ def _params(**kw):
     p = _abi.snn_params(n_neurons=1000, n_partitions=8, gpus_per_node=4, max_delay=10,
                         alpha=0.995, theta=15.0, u_reset=0.0, w_ext=0.1, n_ref=20, seed=1,
                         raster_period=1, bucket_total=100, recv_total=100, log_steps=10,
-                        log_cap=1000)
+                        input_bound=100.0, log_cap=1000)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -62,12 +62,28 @@ def test_workspace_size_and_ring_stride():
     ("n_neurons", 0), ("n_neurons", (1 << 27) + 1), ("n_partitions", 0),
     ("n_partitions", 65536), ("gpus_per_node", 0), ("gpus_per_node", 9), ("max_delay", 0),
     ("max_delay", 16), ("n_ref", 256), ("weight_type", 2), ("flags", 2), ("log_steps", 0),
+    ("input_bound", 0.0), ("input_bound", -1.0), ("input_bound", float("nan")),
+    ("input_bound", float("inf")),
 ])
 def test_invalid_params_rejected(field, value):
     with pytest.raises(_abi.SNNError) as ei:
         _abi.snn_workspace_size(_params(**{field: value}))
     assert ei.value.status == _abi.SNN_ERR_INVALID_ARG
     assert _abi.snn_last_error()
+
+
+def test_input_bound_too_large_unsupported():
+    # more than 2^22 mV per step would leave fewer than 8 fractional bits
+    with pytest.raises(_abi.SNNError) as ei:
+        _abi.snn_workspace_size(_params(input_bound=float(1 << 23)))
+    assert ei.value.status == _abi.SNN_ERR_UNSUPPORTED
+    assert _abi.snn_workspace_size(_params(input_bound=float(1 << 21))) > 0
+
+
+def test_bin_geometry():
+    tile, deliver_blocks, stage_blocks = _abi.snn_bin_geometry()
+    assert tile > 0 and tile & (tile - 1) == 0
+    assert deliver_blocks > 0 and stage_blocks % deliver_blocks == 0
 
 
 def test_nonmonotone_poisson_table_rejected():

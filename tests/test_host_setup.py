@@ -63,6 +63,12 @@ def _check_network(wl, host):
     assert np.array_equal(a, b)
     # local segment = exactly the synapses whose destination is the own partition
     assert np.array_equal(local, vp_h == part[src_h])
+    # input bound: the largest sum of |w| (as stored) over a neuron's inputs,
+    # rounded up to a float
+    w_abs = np.abs(w_g.view(np.float32).astype(np.float64))
+    want = np.bincount(e["tgt"], weights=w_abs, minlength=N).max()
+    assert np.float32(host.input_bound) >= want
+    assert np.float32(host.input_bound) <= np.nextafter(np.float32(want), np.float32(np.inf))
     # exact capacity bounds: sources per destination partition / per node
     assert np.array_equal(np.diff(host.recv_off.astype(np.int64)), np.bincount(vp_part, minlength=P))
     node_pairs = np.unique(owner * (P // G + 1) + vp_part // G)
@@ -91,6 +97,7 @@ def test_setup_independent_of_threads():
     for k in ("row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_seg",
               "bucket_off", "recv_off"):
         assert np.array_equal(getattr(a, k), getattr(b, k)), k
+    assert a.input_bound == b.input_bound
 
 
 @pytest.mark.parametrize("name", ["tiny", "paper_share", "heavy"])
