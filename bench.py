@@ -66,6 +66,62 @@ def cpu_baseline(wl_full, seconds_budget=20.0):
                        f"ms/step {1e3 * dt / steps:.2f}")
 
 
+def calibrate_copy(nbytes: int, reps: int = 5):
+    """A plain device copy of nbytes (read nbytes, write nbytes), repeated:
+    the reference that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n * 4, "reps": reps}), flush=True)
+
+
+def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_bytes, workload, out):
+    """Per-kernel HBM traffic per launch from FETCH_SIZE / WRITE_SIZE runs
+    (KiB per dispatch), each scaled by copy_bytes / counter of the copy."""
+    import csv
+    import statistics
+
+    def per_kernel(d, counter):
+        rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        vals = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].split("::")[-1]
+            vals.setdefault(name, []).append(float(r["Counter_Value"]))
+        # drop the first third (warm-up steps), median of the rest
+        return {k: statistics.median(v[len(v) // 3:]) for k, v in vals.items()}
+
+    def copy_kib(d, counter):
+        v = per_kernel(d, counter)
+        k = max(v, key=lambda n: v[n])          # the copy is the largest dispatch
+        return v[k]
+    f_scale = cal_bytes / (copy_kib(cal_fetch_dir, "FETCH_SIZE") * 1024.0)
+    w_scale = cal_bytes / (copy_kib(cal_write_dir, "WRITE_SIZE") * 1024.0)
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    res = {}
+    for k in fetch:
+        if not k.startswith("k_"):
+            continue
+        fb, wb = fetch[k] * 1024.0 * f_scale, write.get(k, 0.0) * 1024.0 * w_scale
+        res[k[2:]] = {"fetch_kib": fetch[k], "write_kib": write.get(k, 0.0),
+                      "fetch_scale": f_scale, "write_scale": w_scale,
+                      "bytes_per_launch": fb + wb, "kernel_hash": kernel_source_hash()}
+    allres = {}
+    if os.path.exists(out):
+        with open(out) as fh:
+            allres = json.load(fh)
+    allres[workload] = res
+    with open(out, "w") as fh:
+        json.dump(allres, fh, indent=1, sort_keys=True)
+    print(json.dumps(allres[workload]), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,7 +134,20 @@ def main():
     ap.add_argument("--phase-steps", type=int, default=100)
     ap.add_argument("--neurons", type=int, default=0,
                     help="run the workload's structure at this many neurons (quick checks)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR",
+                                                       "CAL_WRITE_DIR", "CAL_BYTES"),
+                    help="write profiles/traffic.json from rocprofv3 --pmc output directories")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+    if args.pmc_summary:
+        fd, wd, cfd, cwd, cb = args.pmc_summary
+        pmc_summary(fd, wd, cfd, cwd, int(cb), args.workload,
+                    os.path.join(ROOT, "profiles", "traffic.json"))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs one GPU's share on one GPU; --gpus {args.gpus} is not supported "
@@ -173,10 +242,12 @@ def main():
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
         with open(tf) as fh:
-            tj = json.load(fh)
-        ent = tj.get(wl.name, {}).get(dom)
-        if ent and ent.get("kernel_hash") == kernel_source_hash():
-            traffic = ent.get("bytes_per_launch")
+            tj = json.load(fh).get(wl.name, {})
+        h = kernel_source_hash()
+        for k, v in kernels.items():
+            ent = tj.get(k)
+            v["traffic_bytes"] = ent["bytes_per_launch"] if ent and ent.get("kernel_hash") == h else None
+        traffic = kernels[dom].get("traffic_bytes")
     # whole step (survey's per-step algorithmic bytes, ring RMW excluded)
     step_bytes = sum(v["alg_bytes"] for v in kernels.values())
     out = {
