@@ -182,10 +182,18 @@ typedef struct {
   const uint16_t* vp_part;         /* [pairs] distinct, ascending, never s's own partition;
                                       this is the routing table TB of Sec. IV-B restricted
                                       to one source */
-  const uint32_t* vp_seg;          /* [pairs] first synapse (relative to row_ptr[s]) of the
-                                      row segment going to vp_part[j]; segments follow the
-                                      local part in vp order and end where the next begins
-                                      (the last at the row's end) */
+  const uint64_t* vp_rec;          /* [2 * pairs] receive record of pair j (source s, its
+                                      destination vp_part[j]), what the receiving partition
+                                      needs to find its synapses of s:
+                                        vp_rec[2j]   = start | (len << 40): the row segment
+                                                       [start, start + len) (absolute synapse
+                                                       indices, len >= 1) going to vp_part[j];
+                                                       segments follow the local part in vp
+                                                       order
+                                        vp_rec[2j+1] = tgt_delay | (weight bits << 32) of the
+                                                       segment's first synapse (a copy, so
+                                                       that one-synapse segments need no
+                                                       second lookup) */
   const int32_t* part_of_neuron;   /* [N] the neuron-GPU mapping PM of Sec. IV-A */
   const uint64_t* bucket_off;      /* [n_nodes+1] bucket of node n holds at most
                                       bucket_off[n+1] - bucket_off[n] messages */
@@ -275,13 +283,15 @@ snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps,
 
 /* Routing buffers of the last routed step, copied to host memory, as uint64
    elements.
-   which = 0: flat receive lists, per partition: bits 0..31 source id, bits
-              32..63 index of the partition in the source's destination list
-              (the routing-table index the receiver uses to find its synapses);
+   which = 0: flat receive lists, per partition: bits 0..26 source id, bits
+              27..63 pair index j of (source, partition) (vp_part[j] is the
+              partition; vp_rec[2j], vp_rec[2j+1] the record the receiver uses to
+              find its synapses);
    which = 1: expanded two-level receive lists, same format;
    which = 2: per-node send buckets: bits 0..31 source id, bits 32..39
               partition mask of the node, bits 40..63 index of the node's first
-              destination in the source's destination list.
+              destination in the source's destination list (on the device a
+              message also carries that destination's pair index, not copied).
    sizes[n_partitions or n_nodes] receives the counts; entries (may be NULL)
    receives the lists concatenated in partition / node order, at most cap
    entries.  Order inside a list is unspecified.  Synchronises. */

@@ -20,7 +20,7 @@
  *   snn_setup_fill_rows(...)            row_ptr, n_local, tgt_delay, weight
  *   snn_setup_sizes(...)                pairs, bucket_total, recv_total
  *   snn_setup_input_bound(...)          snn_params.input_bound
- *   snn_setup_fill_routes(...)          vp_ptr, vp_part, vp_seg, part_of_neuron,
+ *   snn_setup_fill_routes(...)          vp_ptr, vp_part, vp_rec, part_of_neuron,
  *                                       bucket_off, recv_off
  *   snn_setup_destroy(...)
  * All output pointers are caller-owned HOST arrays of the sizes stated.
@@ -83,13 +83,17 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
    up to a float.  Known after snn_setup_fill_rows (SNN_ERR_BAD_STATE before). */
 snn_status snn_setup_input_bound(snn_setup_handle h, float* bound);
 
-/* Destination-partition lists and capacity bounds: vp_ptr[N+1], vp_part[pairs],
-   vp_seg[pairs], part_of_neuron[N], bucket_off[n_nodes+1] (bucket of node n:
-   number of sources with a destination partition in n), recv_off[P+1] (list of
+/* Destination-partition lists, receive records and capacity bounds, from the
+   rows that snn_setup_fill_rows wrote (tgt_delay and weight are its output):
+   vp_ptr[N+1], vp_part[pairs], vp_rec[2 * pairs] (see snn_network_dev),
+   part_of_neuron[N], bucket_off[n_nodes+1] (bucket of node n: number of
+   sources with a destination partition in n), recv_off[P+1] (list of
    partition p: number of sources with destination p).  These bounds are exact
-   maxima per step, so routing can never overflow. */
-snn_status snn_setup_fill_routes(snn_setup_handle h, int64_t* vp_ptr, uint16_t* vp_part,
-                                 uint32_t* vp_seg, int32_t* part_of_neuron,
+   maxima per step, so routing can never overflow.  SNN_ERR_UNSUPPORTED if a
+   source has 2^24 or more synapses into one partition. */
+snn_status snn_setup_fill_routes(snn_setup_handle h, const uint32_t* tgt_delay,
+                                 const void* weight, int64_t* vp_ptr, uint16_t* vp_part,
+                                 uint64_t* vp_rec, int32_t* part_of_neuron,
                                  uint64_t* bucket_off, uint64_t* recv_off);
 
 void snn_setup_destroy(snn_setup_handle h);

@@ -23,6 +23,9 @@ SNN_W_FP32 = 0
 SNN_W_BF16 = 1
 SNN_FORCED_RASTER = 1
 
+# receive-list entries: source id in the low ENTRY_SRC_BITS bits, pair index above
+ENTRY_SRC_BITS = 27
+
 STAT_NAMES = ["spikes", "local_events", "remote_events", "msg_l1", "msg_l2", "flat_msgs",
               "recv_entries"]
 SNN_NSTAT = len(STAT_NAMES)
@@ -59,7 +62,7 @@ class snn_params(ctypes.Structure):
 
 class snn_network_dev(ctypes.Structure):
     _fields_ = [(n, vp) for n in (
-        "row_ptr", "n_local", "delay_off", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_seg",
+        "row_ptr", "n_local", "delay_off", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_rec",
         "part_of_neuron", "bucket_off", "recv_off", "u", "ref", "ring")]
 
 
@@ -119,7 +122,7 @@ def lib() -> ctypes.CDLL:
             "snn_setup_create": (I, [ctypes.POINTER(snn_setup_spec), vp, vp, ctypes.POINTER(vp)]),
             "snn_setup_sizes": (I, [vp] + [ctypes.POINTER(u64)] * 4),
             "snn_setup_fill_rows": (I, [vp] * 6),
-            "snn_setup_fill_routes": (I, [vp] * 7),
+            "snn_setup_fill_routes": (I, [vp] * 9),
             "snn_setup_input_bound": (I, [vp, ctypes.POINTER(f32)]),
             "snn_setup_destroy": (None, [vp]),
         }

@@ -75,6 +75,11 @@ constexpr int POIS_LUT_SHIFT = 19;
 constexpr uint32_t POIS_LUT_SIZE = 1u << (32 - POIS_LUT_SHIFT);   // 8192 one-byte entries
 constexpr uint8_t POIS_LUT_SLOW = 255;
 
+// Receive-list entries: source id in the low ENTRY_SRC_BITS bits (ids are
+// below 2^27), the (source, partition) pair index above.
+constexpr int ENTRY_SRC_BITS = 27;
+constexpr uint64_t ENTRY_SRC_MASK = (uint64_t(1) << ENTRY_SRC_BITS) - 1;
+
 // Synaptic input is summed in fixed point: each binned event carries its
 // weight rounded to a multiple of 2^-F (int32), the update adds them exactly
 // with 32-bit LDS integer atomics (about ten times faster than float ones on
@@ -116,10 +121,12 @@ struct KParams {
   const void* weight;
   const int64_t* vp_ptr;
   const uint16_t* vp_part;
-  const uint32_t* vp_seg;
+  const uint64_t* vp_rec;     // [2 * pairs] receive records (start | len << 40, first synapse)
   const int32_t* part;
   const uint64_t* bucket_off;
   const uint64_t* recv_off;
+  uint64_t n_pairs;           // vp_ptr[N]: destination pairs (bounds checks)
+  uint64_t nnz;               // row_ptr[N]: synapses (bounds checks)
   float* u;
   uint8_t* ref;
   float* ring;
@@ -128,7 +135,8 @@ struct KParams {
   uint64_t* lookback;   // [n_tiles] decoupled look-back words
   uint32_t* fired;      // [N] ascending fired ids of the step in flight
   uint32_t* bucket_cnt; // [n_nodes * CNT_STRIDE]
-  uint64_t* bucket;     // [bucket_total]
+  uint64_t* bucket;     // [2 * bucket_total] messages: source | mask << 32 | first
+                        // destination's list index << 40, then its pair index
   uint32_t* recv_cnt;   // [P * CNT_STRIDE] expanded lists
   uint64_t* recv;       // [recv_total]
   uint32_t* flat_cnt;   // [P * CNT_STRIDE]

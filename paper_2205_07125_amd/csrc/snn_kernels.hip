@@ -540,11 +540,19 @@ __device__ __forceinline__ uint32_t node_mask(const KParams& p, int64_t j, int64
   return mask;
 }
 
+// Message of node `node` at position pos of its bucket: word 0 = source |
+// mask << 32 | list index of the node's first destination << 40, word 1 =
+// that destination's pair index (the receive record the expansion hands on).
 __device__ __forceinline__ void bucket_put(const KParams& p, uint32_t node, uint32_t pos,
-                                           uint64_t msg) {
+                                           uint64_t msg, uint64_t pair) {
   const uint64_t off = p.bucket_off[node];
-  if (off + pos < p.bucket_off[node + 1]) p.bucket[off + pos] = msg;
-  else atomicOr(&p.st->error, ERR_BUCKET);
+  if (off + pos < p.bucket_off[node + 1]) {
+    uint64_t* m = p.bucket + 2 * (off + pos);
+    m[0] = msg;
+    m[1] = pair;
+  } else {
+    atomicOr(&p.st->error, ERR_BUCKET);
+  }
 }
 
 // Two-level: block b takes a contiguous chunk of the fired sources.  Their
@@ -558,7 +566,7 @@ __device__ __forceinline__ void bucket_put(const KParams& p, uint32_t node, uint
 // per (window, node) then reserves the node's bucket space.  A window has at
 // most as many messages as pairs, so the stage never overflows.
 // Dynamic LDS: ROUTE_STAGE messages, node/rank words, pairs and their source
-// index, + 2 * n_nodes counters.
+// index, each message's source index, + 2 * n_nodes counters.
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   uint64_t* s_msg = lds_u64;                                              // [ROUTE_STAGE]
@@ -567,6 +575,7 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
   uint32_t* l_base = l_cnt + p.n_nodes;                                   // [n_nodes]
   uint16_t* s_vp = reinterpret_cast<uint16_t*>(l_base + p.n_nodes);       // [ROUTE_STAGE]
   uint16_t* s_k = s_vp + ROUTE_STAGE;                                     // [ROUTE_STAGE]
+  uint16_t* s_mk = s_k + ROUTE_STAGE;                                     // source of message
   constexpr uint32_t NW = ROUTE_THREADS / 64;
   __shared__ uint32_t l_total;
   __shared__ uint32_t s_src[ROUTE_THREADS], s_own[ROUTE_THREADS], s_pre[ROUTE_THREADS + 1];
@@ -642,6 +651,7 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
         const uint32_t rk = atomicAdd(&l_cnt[node], 1u);
         s_msg[slot] = msg;
         s_nr[slot] = node | (rk << 16);
+        s_mk[slot] = static_cast<uint16_t>(k);
         if (node == s_own[k]) ++l1; else ++l2;
       }
       __syncthreads();
@@ -667,8 +677,13 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
           if (k >= n_msg) continue;
           const uint32_t nr = s_nr[k];
           const uint64_t pos = o[v] + l_base[nr & 0xFFFFu] + (nr >> 16);
-          if (pos < o1[v]) p.bucket[pos] = s_msg[k];
-          else atomicOr(&p.st->error, ERR_BUCKET);
+          if (pos < o1[v]) {
+            const uint64_t msg = s_msg[k];
+            p.bucket[2 * pos] = msg;
+            p.bucket[2 * pos + 1] = static_cast<uint64_t>(s_j0[s_mk[k]]) + (msg >> 40);
+          } else {
+            atomicOr(&p.st->error, ERR_BUCKET);
+          }
         }
       }
       __syncthreads();
@@ -697,7 +712,8 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level_direct(KParam
       if (j != j0 && p.vp_part[j - 1] / p.G == node) continue;
       const uint64_t msg = (static_cast<uint64_t>(j - j0) << 40) |
                            (static_cast<uint64_t>(node_mask(p, j, j1, node)) << 32) | s;
-      bucket_put(p, node, atomicAdd(p.bucket_cnt + node * CNT_STRIDE, 1u), msg);
+      bucket_put(p, node, atomicAdd(p.bucket_cnt + node * CNT_STRIDE, 1u), msg,
+                 static_cast<uint64_t>(j));
       if (node == own_node) ++l1; else ++l2;
     }
   }
@@ -707,8 +723,9 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level_direct(KParam
 }
 
 // Expansion at destination node n (one block per node): every set bit b of a
-// message's mask appends (source, index of partition G*n + b in the source's
-// destination list) to that partition's receive list.  The block owns the
+// message's mask appends (source, pair index of partition G*n + b) to that
+// partition's receive list; the node's destinations are consecutive in the
+// source's list, so the pair indices follow the message's first one.  The block owns the
 // node's G partitions, so list positions come from LDS counters (no global
 // atomics) and the counts are stored at the end.  Rounds take one message per
 // thread, staged in LDS so that each partition's entries are written as runs.
@@ -736,10 +753,10 @@ __global__ __launch_bounds__(EXPAND_THREADS) void k_expand(KParams p) {
     __syncthreads();
     const uint64_t m = m0 + tid;
     if (m < cnt) {
-      const uint64_t msg = p.bucket[off + m];
+      const uint64_t msg = p.bucket[2 * (off + m)];
+      uint64_t pair = p.bucket[2 * (off + m) + 1];
       const uint64_t s = msg & 0xFFFFFFFFull;
       uint32_t mask = static_cast<uint32_t>(msg >> 32) & 0xFFu;
-      uint64_t jrel = msg >> 40;
       while (mask) {
         const uint32_t b = __ffs(mask) - 1;
         mask &= mask - 1;
@@ -749,9 +766,9 @@ __global__ __launch_bounds__(EXPAND_THREADS) void k_expand(KParams p) {
         }
         const uint32_t k = atomicAdd(&l_total, 1u);
         const uint32_t rk = atomicAdd(&l_cnt[b], 1u);
-        s_ent[k] = s | (jrel << 32);
+        s_ent[k] = s | (pair << ENTRY_SRC_BITS);
         s_br[k] = static_cast<uint16_t>(b | (rk << 3));
-        ++jrel;
+        ++pair;
         ++entries;
       }
     }
@@ -771,7 +788,7 @@ __global__ __launch_bounds__(EXPAND_THREADS) void k_expand(KParams p) {
 }
 
 // Flat (direct peer-to-peer) routing: one wave per fired source, one receive
-// entry (source, index in its destination list) per destination partition.
+// entry (source, pair index) per destination partition.
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
   const uint32_t nF = p.st->n_fired;
   const uint32_t row = p.st->cur_row;
@@ -786,7 +803,7 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
       const uint32_t pos = atomicAdd(p.flat_cnt + v * CNT_STRIDE, 1u);
       const uint64_t off = p.recv_off[v];
       if (off + pos < p.recv_off[v + 1])
-        p.flat[off + pos] = static_cast<uint64_t>(s) | (static_cast<uint64_t>(j - j0) << 32);
+        p.flat[off + pos] = static_cast<uint64_t>(s) | (static_cast<uint64_t>(j) << ENTRY_SRC_BITS);
       else
         atomicOr(&p.st->error, ERR_FLAT);
       ++flat;
@@ -800,21 +817,22 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
 // receive side: stage remote synapses per delay
 
 // Block b of STAGE_BLOCKS owns a contiguous range of partitions and their
-// receive lists.  For every entry (s, j): the receiving partition's synapses
-// of source s are the row segment of s's j-th destination; each synapse goes
-// to the block's own queue for its delay (positions from per-delay LDS
-// counters; no global atomics: the queues belong to the block).
+// receive lists.  An entry (s, j) names the receive record of pair j: the row
+// segment of s going to this partition, with its first synapse inline.  Each
+// synapse goes to the block's own queue for its delay (positions from
+// per-delay LDS counters; no global atomics: the queues belong to the block).
 // Entries are taken in batches of RECV_BATCH, RECV_PER_THREAD per thread, so
-// that their three dependent lookups (entry; source row and destination-list
-// bounds; segment) are in flight together; the segments are then concatenated
-// by a block scan and their synapses loaded as one flat sequence.
+// that their two dependent loads (entry, record) are in flight together; the
+// first synapse of every segment comes from the record, and the rest of the
+// longer segments are concatenated by a block scan and loaded as one flat
+// sequence.
 __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_flat) {
   constexpr uint32_t NW = RECV_THREADS / 64;
   constexpr uint32_t R = RECV_PER_THREAD;
   __shared__ uint32_t s_ppre[RECV_THREADS];     // entry starts of the block's partitions
   __shared__ uint64_t s_roff[RECV_THREADS];     // list offsets of the block's partitions
-  __shared__ uint64_t s_seg[RECV_BATCH];        // first synapse of each entry's segment
-  __shared__ uint32_t s_epre[RECV_BATCH];       // segment starts in the concatenation
+  __shared__ uint64_t s_seg[RECV_BATCH];        // second synapse of each entry's segment
+  __shared__ uint32_t s_epre[RECV_BATCH];       // remaining synapses: starts in the concatenation
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
   __shared__ uint32_t l_pos[SNN_MAX_DELAY];
@@ -840,48 +858,62 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
   Event* queue = p.stage + static_cast<uint64_t>(b) * p.stage_cap;  // + (d-1)*STAGE_BLOCKS*cap
   const uint64_t qstride = static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap;
   uint64_t events = 0;
+
+  // one synapse (tgt_delay, weight) into the queue of its delay
+  auto emit = [&](uint32_t td, float w) {
+    const uint32_t d1 = (td >> 27) - 1;
+    if (d1 >= md) {                            // delay outside [1, max_delay]
+      atomicOr(&p.st->error, ERR_ROUTE);
+      return;
+    }
+    const Event ev{td & 0x07FFFFFFu, quantize_w(p, w)};
+    const uint32_t pos = atomicAdd(&l_pos[d1], 1u);
+    if (pos < p.stage_cap) {
+      queue[d1 * qstride + pos] = ev;
+    } else {
+      uint32_t slot = slot0 + d1 + 1;
+      if (slot >= p.D) slot -= p.D;
+      ring_fallback(p, slot, ev.tgt, ev.wq);
+    }
+  };
+
   for (uint32_t b0 = 0; b0 < n_ent; b0 += RECV_BATCH) {
     const uint32_t nb = min(n_ent - b0, RECV_BATCH);
     // entries tid * R + v of the batch; past the end a lane repeats the last
     // entry (valid addresses) and contributes no synapses
     uint64_t ent[R];
-    uint32_t part[R];
 #pragma unroll
     for (int v = 0; v < R; ++v) {
       const uint32_t e = b0 + min(tid * R + v, nb - 1);
       const uint32_t k = owner_of<STAGE_PARTS / 2>(s_ppre, nq, e);
-      part[v] = q0 + k;
       ent[v] = lists[s_roff[k] + (e - s_ppre[k])];
     }
-    int64_t jb[R], je[R], r0[R], r1[R];
+    uint64_t rec0[R], rec1[R];
 #pragma unroll
     for (int v = 0; v < R; ++v) {
-      const uint32_t s = static_cast<uint32_t>(ent[v]);
-      const uint32_t sc = s < p.N ? s : 0u;
-      jb[v] = p.vp_ptr[sc];
-      je[v] = p.vp_ptr[sc + 1];
-      r0[v] = p.row_ptr[sc];
-      r1[v] = p.row_ptr[sc + 1];
+      const uint64_t j = ent[v] >> ENTRY_SRC_BITS;
+      const uint64_t jc = j < p.n_pairs ? j : 0;   // entries exist, so pair 0 does
+      rec0[v] = p.vp_rec[2 * jc];
+      rec1[v] = p.vp_rec[2 * jc + 1];
     }
     uint32_t len[R];
     uint32_t tsum = 0;
 #pragma unroll
     for (int v = 0; v < R; ++v) {
       const bool in = tid * R + v < nb;
-      const uint32_t s = static_cast<uint32_t>(ent[v]);
-      const int64_t j = jb[v] + static_cast<int64_t>(ent[v] >> 32);
-      bool ok = s < p.N && j < je[v];
-      const int64_t jc = ok ? j : 0;           // entries exist, so pair 0 does
-      const int64_t jn = jc + 1 < je[v] ? jc + 1 : jc;
-      const uint32_t vp = p.vp_part[jc];
-      const uint32_t sg = p.vp_seg[jc], sg1 = p.vp_seg[jn];
-      ok = ok && vp == part[v];
+      const uint64_t start = rec0[v] & ((uint64_t(1) << 40) - 1);
+      const uint32_t seg_len = static_cast<uint32_t>(rec0[v] >> 40);
+      const bool ok = (ent[v] & ENTRY_SRC_MASK) < p.N && (ent[v] >> ENTRY_SRC_BITS) < p.n_pairs &&
+                      seg_len >= 1 && start + seg_len <= p.nnz;
       if (in && !ok) atomicOr(&p.st->error, ERR_ROUTE);
-      const uint64_t a = static_cast<uint64_t>(r0[v]) + sg;
-      const uint64_t z = jc + 1 < je[v] ? static_cast<uint64_t>(r0[v]) + sg1
-                                        : static_cast<uint64_t>(r1[v]);
-      s_seg[tid * R + v] = a;
-      len[v] = in && ok ? static_cast<uint32_t>(z - a) : 0u;
+      if (in && ok) {
+        const uint32_t wbits = static_cast<uint32_t>(rec1[v] >> 32);
+        emit(static_cast<uint32_t>(rec1[v]),
+             p.bf16 ? __uint_as_float(wbits << 16) : __uint_as_float(wbits));
+        events += seg_len;
+      }
+      s_seg[tid * R + v] = start + 1;
+      len[v] = in && ok ? seg_len - 1 : 0u;
       tsum += len[v];
     }
     uint32_t T;
@@ -892,7 +924,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
       run += len[v];
     }
     __syncthreads();
-    events += tid == 0 ? T : 0u;
+    // the remaining synapses of longer segments
     for (uint32_t e0 = 0; e0 < T; e0 += GATHER_UNROLL * RECV_THREADS) {
       uint32_t td[GATHER_UNROLL];
       float wt[GATHER_UNROLL];
@@ -905,23 +937,8 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
         wt[v] = load_weight(p, x);
       }
 #pragma unroll
-      for (int v = 0; v < GATHER_UNROLL; ++v) {
-        if (e0 + v * RECV_THREADS + tid >= T) continue;
-        const uint32_t d1 = (td[v] >> 27) - 1;
-        if (d1 >= md) {                        // delay outside [1, max_delay]
-          atomicOr(&p.st->error, ERR_ROUTE);
-          continue;
-        }
-        const Event ev{td[v] & 0x07FFFFFFu, quantize_w(p, wt[v])};
-        const uint32_t pos = atomicAdd(&l_pos[d1], 1u);
-        if (pos < p.stage_cap) {
-          queue[d1 * qstride + pos] = ev;
-        } else {
-          uint32_t slot = slot0 + d1 + 1;
-          if (slot >= p.D) slot -= p.D;
-          ring_fallback(p, slot, ev.tgt, ev.wq);
-        }
-      }
+      for (int v = 0; v < GATHER_UNROLL; ++v)
+        if (e0 + v * RECV_THREADS + tid < T) emit(td[v], wt[v]);
     }
     __syncthreads();
   }
@@ -1157,7 +1174,7 @@ hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks) {
 }
 
 size_t route_lds_bytes(const KParams& p) {
-  return ROUTE_STAGE * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(uint16_t)) +
+  return ROUTE_STAGE * (sizeof(uint64_t) + sizeof(uint32_t) + 3 * sizeof(uint16_t)) +
          2ull * p.n_nodes * sizeof(uint32_t);
 }
 

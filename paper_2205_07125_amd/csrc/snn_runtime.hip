@@ -77,7 +77,7 @@ Layout layout(const snn_params* p) {
   L.pois_lut = take(POIS_LUT_SIZE);
   L.log_off = take(sizeof(uint64_t) * uint64_t(p->log_steps));
   // large buffers last: the region before them is zeroed at create
-  L.bucket = take(sizeof(uint64_t) * p->bucket_total);
+  L.bucket = take(2 * sizeof(uint64_t) * p->bucket_total);
   L.recv = take(sizeof(uint64_t) * p->recv_total);
   L.flat = take(sizeof(uint64_t) * p->recv_total);
   L.stage = take(sizeof(Event) * md * STAGE_BLOCKS * p->stage_cap);
@@ -186,10 +186,10 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   if (s != SNN_OK) return s;
   if (!net) return fail(SNN_ERR_INVALID_ARG, "net is NULL");
   const void* req[] = {net->row_ptr, net->n_local, net->delay_off, net->tgt_delay, net->weight,
-                       net->vp_ptr, net->vp_part, net->vp_seg, net->part_of_neuron,
+                       net->vp_ptr, net->vp_part, net->vp_rec, net->part_of_neuron,
                        net->bucket_off, net->recv_off, net->u, net->ref, net->ring};
   const char* names[] = {"row_ptr", "n_local", "delay_off", "tgt_delay", "weight", "vp_ptr",
-                         "vp_part", "vp_seg", "part_of_neuron", "bucket_off", "recv_off", "u",
+                         "vp_part", "vp_rec", "part_of_neuron", "bucket_off", "recv_off", "u",
                          "ref", "ring"};
   for (int i = 0; i < 14; ++i)
     if (!req[i]) return fail(SNN_ERR_INVALID_ARG, "net->%s is NULL", names[i]);
@@ -243,7 +243,7 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.weight = net->weight;
   k.vp_ptr = net->vp_ptr;
   k.vp_part = net->vp_part;
-  k.vp_seg = net->vp_seg;
+  k.vp_rec = net->vp_rec;
   k.part = net->part_of_neuron;
   k.bucket_off = net->bucket_off;
   k.recv_off = net->recv_off;
@@ -271,7 +271,23 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.log = reinterpret_cast<uint32_t*>(ws + L.log);
   // Everything before the large buffers starts at zero: state, look-back
   // words, counters (bin counts are read before their first write).
-  hipError_t e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
+  // totals of the network arrays, for the kernels' bounds checks
+  int64_t tot[2] = {0, 0};
+  hipError_t e = hipMemcpy(&tot[0], net->vp_ptr + params->n_neurons, 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(&tot[1], net->row_ptr + params->n_neurons, 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(SNN_ERR_HIP, "create: reading vp_ptr[N], row_ptr[N]: %s", hipGetErrorString(e));
+  }
+  if (tot[0] < 0 || tot[1] < 0 || tot[1] >= (int64_t(1) << 40)) {
+    delete c;
+    return fail(SNN_ERR_INVALID_ARG, "vp_ptr[N] = %lld or row_ptr[N] = %lld out of range",
+                (long long)tot[0], (long long)tot[1]);
+  }
+  k.n_pairs = uint64_t(tot[0]);
+  k.nnz = uint64_t(tot[1]);
+  e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
   build_pois_lut(params->poisson_thr, c->pois_lut);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.pois_lut, c->pois_lut.data(), POIS_LUT_SIZE, hipMemcpyHostToDevice,
@@ -565,8 +581,12 @@ snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entri
   uint64_t at = 0;
   for (uint32_t i = 0; i < nl; ++i) {
     if (!sizes[i]) continue;
-    HIP_TRY(hipMemcpyAsync(static_cast<char*>(entries) + at * 8, base + off[i] * 8, sizes[i] * 8,
-                           hipMemcpyDeviceToHost, h->stream));
+    if (which == 2)   // first word of each two-word message
+      HIP_TRY(hipMemcpy2DAsync(static_cast<char*>(entries) + at * 8, 8, base + off[i] * 16, 16, 8,
+                               sizes[i], hipMemcpyDeviceToHost, h->stream));
+    else
+      HIP_TRY(hipMemcpyAsync(static_cast<char*>(entries) + at * 8, base + off[i] * 8, sizes[i] * 8,
+                             hipMemcpyDeviceToHost, h->stream));
     at += sizes[i];
   }
   HIP_TRY(hipStreamSynchronize(h->stream));

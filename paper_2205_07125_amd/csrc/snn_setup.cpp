@@ -305,31 +305,48 @@ snn_status snn_setup_fill_rows(snn_setup_handle h, int64_t* row_ptr, uint32_t* n
   return SNN_OK;
 }
 
-snn_status snn_setup_fill_routes(snn_setup_handle h, int64_t* vp_ptr, uint16_t* vp_part,
-                                 uint32_t* vp_seg, int32_t* part_of_neuron,
+snn_status snn_setup_fill_routes(snn_setup_handle h, const uint32_t* tgt_delay,
+                                 const void* weight, int64_t* vp_ptr, uint16_t* vp_part,
+                                 uint64_t* vp_rec, int32_t* part_of_neuron,
                                  uint64_t* bucket_off, uint64_t* recv_off) {
-  if (!h || !vp_ptr || !part_of_neuron || !bucket_off || !recv_off)
+  if (!h || !tgt_delay || !weight || !vp_ptr || !part_of_neuron || !bucket_off || !recv_off)
     return fail(SNN_ERR_INVALID_ARG, "NULL argument");
   if (!h->rows_done) return fail(SNN_ERR_BAD_STATE, "snn_setup_fill_rows has not run");
-  if (h->pairs && (!vp_part || !vp_seg)) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  if (h->pairs && (!vp_part || !vp_rec)) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
   const uint32_t N = h->N;
   vp_ptr[0] = 0;
   for (uint32_t s = 0; s < N; ++s) vp_ptr[s + 1] = vp_ptr[s] + h->n_vp[s];
   const uint16_t* tag = h->tag.data();
+  const bool bf16 = h->spec.weight_type == SNN_W_BF16;
+  const float* wf = static_cast<const float*>(weight);
+  const uint16_t* wb = static_cast<const uint16_t*>(weight);
+  int too_long = 0;
 #pragma omp parallel for num_threads(h->threads) schedule(dynamic, 256)
   for (int64_t s = 0; s < int64_t(N); ++s) {
     const uint64_t r0 = uint64_t(h->row_ptr[s]), r1 = uint64_t(h->row_ptr[s + 1]);
     int64_t j = vp_ptr[s];
     uint16_t last = 0;
-    for (uint64_t e = r0; e < r1; ++e) {
-      if (tag[e] != 0 && tag[e] != last) {
-        vp_part[j] = uint16_t(tag[e] - 1);
-        vp_seg[j] = uint32_t(e - r0);
+    uint64_t seg0 = 0;
+    for (uint64_t e = r0; e <= r1; ++e) {
+      const uint16_t tg = e < r1 ? tag[e] : 0;
+      if (last != 0 && tg != last) {
+        // close the segment of partition last - 1: [seg0, e)
+        const uint64_t len = e - seg0;
+        if (len >= (uint64_t(1) << 24)) __atomic_store_n(&too_long, 1, __ATOMIC_RELAXED);
+        uint32_t wbits;
+        if (bf16) wbits = wb[seg0];
+        else std::memcpy(&wbits, wf + seg0, 4);
+        vp_part[j] = uint16_t(last - 1);
+        vp_rec[2 * j] = seg0 | (len << 40);
+        vp_rec[2 * j + 1] = uint64_t(tgt_delay[seg0]) | (uint64_t(wbits) << 32);
         ++j;
-        last = tag[e];
       }
+      if (tg != 0 && tg != last) seg0 = e;
+      last = tg;
     }
   }
+  if (too_long)
+    return fail(SNN_ERR_UNSUPPORTED, "a source has 2^24 or more synapses into one partition");
   syn_part_map(h->gen, part_of_neuron);
   bucket_off[0] = 0;
   for (uint32_t n = 0; n < h->n_nodes; ++n) bucket_off[n + 1] = bucket_off[n] + h->bucket_cap[n];

@@ -112,12 +112,13 @@ class HostNetwork:
             n_nodes = wl.n_nodes
             self.vp_ptr = np.empty(N + 1, np.int64)
             self.vp_part = np.empty(max(pairs, 1), np.uint16)
-            self.vp_seg = np.empty(max(pairs, 1), np.uint32)
+            self.vp_rec = np.empty(2 * max(pairs, 1), np.uint64)
             self.part = np.empty(N, np.int32)
             self.bucket_off = np.empty(n_nodes + 1, np.uint64)
             self.recv_off = np.empty(wl.n_partitions + 1, np.uint64)
-            _abi.check(L.snn_setup_fill_routes(h, _ptr(self.vp_ptr), _ptr(self.vp_part),
-                                               _ptr(self.vp_seg), _ptr(self.part),
+            _abi.check(L.snn_setup_fill_routes(h, _ptr(self.tgt_delay), _ptr(self.weight),
+                                               _ptr(self.vp_ptr), _ptr(self.vp_part),
+                                               _ptr(self.vp_rec), _ptr(self.part),
                                                _ptr(self.bucket_off), _ptr(self.recv_off)))
         finally:
             L.snn_setup_destroy(h)
@@ -127,5 +128,5 @@ class HostNetwork:
     def host_bytes(self) -> int:
         return sum(a.nbytes for a in (self.row_ptr, self.n_local, self.delay_off, self.tgt_delay,
                                       self.weight,
-                                      self.vp_ptr, self.vp_part, self.vp_seg, self.part,
+                                      self.vp_ptr, self.vp_part, self.vp_rec, self.part,
                                       self.bucket_off, self.recv_off))

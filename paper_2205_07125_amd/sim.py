@@ -51,7 +51,7 @@ class Simulation:
         self.t_weight = d(host.weight)
         self.t_vp_ptr = d(host.vp_ptr)
         self.t_vp_part = d(host.vp_part)
-        self.t_vp_seg = d(host.vp_seg)
+        self.t_vp_rec = d(host.vp_rec)
         self.t_part = d(host.part)
         self.t_bucket_off = d(bucket_off)
         self.t_recv_off = d(recv_off)
@@ -90,7 +90,7 @@ class Simulation:
             delay_off=self.t_delay_off.data_ptr(),
             tgt_delay=self.t_tgt_delay.data_ptr(), weight=self.t_weight.data_ptr(),
             vp_ptr=self.t_vp_ptr.data_ptr(), vp_part=self.t_vp_part.data_ptr(),
-            vp_seg=self.t_vp_seg.data_ptr(), part_of_neuron=self.t_part.data_ptr(),
+            vp_rec=self.t_vp_rec.data_ptr(), part_of_neuron=self.t_part.data_ptr(),
             bucket_off=self.t_bucket_off.data_ptr(), recv_off=self.t_recv_off.data_ptr(),
             u=self.u.data_ptr(), ref=self.ref.data_ptr(), ring=self.ring.data_ptr())
         # A stream of our own at default priority: graphs cannot be captured
@@ -153,7 +153,7 @@ class Simulation:
     def read_routes(self, which: int, sources_only: bool = False):
         """which 0 flat lists, 1 expanded lists (per partition), 2 node buckets
         (per node); uint64 elements (see include/snn.h), or just the source ids
-        (low 32 bits) with sources_only."""
+        with sources_only."""
         L = _abi.lib()
         nl = self.wl.n_nodes if which == 2 else self.wl.n_partitions
         sizes = np.zeros(nl, np.uint64)
@@ -164,7 +164,8 @@ class Simulation:
         _abi.check(L.snn_read_routes(self.h, which, sizes.ctypes.data_as(ctypes.c_void_p),
                                      ent.ctypes.data_as(ctypes.c_void_p), ent.size, ctypes.byref(n)))
         if sources_only:
-            ent = (ent & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+            bits = _abi.ENTRY_SRC_BITS if which != 2 else 32
+            ent = (ent & np.uint64((1 << bits) - 1)).astype(np.uint32)
         offs = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
         return [ent[offs[i]:offs[i + 1]].copy() for i in range(nl)]
 

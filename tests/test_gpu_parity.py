@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import synth
+from paper_2205_07125_amd._abi import ENTRY_SRC_BITS
 
 pytestmark = pytest.mark.gpu
 
@@ -40,19 +41,20 @@ def _same_state(sim, orc, where):
 def _same_routes(sim, orc, wl, where):
     flat_e, x_e, b_g = sim.read_routes(0), sim.read_routes(1), sim.read_routes(2)
     flat_o, x_o, b_o = orc.recv(0), orc.recv(1), orc.buckets()
-    lo32 = np.uint64(0xFFFFFFFF)
+    src_mask = np.uint64((1 << ENTRY_SRC_BITS) - 1)
     host = sim.host
     for p in range(wl.n_partitions):
-        fg = (flat_e[p] & lo32).astype(np.uint32)
-        xg = (x_e[p] & lo32).astype(np.uint32)
+        fg = (flat_e[p] & src_mask).astype(np.uint32)
+        xg = (x_e[p] & src_mask).astype(np.uint32)
         assert np.array_equal(np.sort(fg), np.sort(flat_o[p])), f"flat {p} at {where}"
         assert np.array_equal(np.sort(xg), np.sort(x_o[p])), f"expanded {p} at {where}"
-        # the routing-table index each entry carries names partition p
+        # the pair index each entry carries belongs to its source and names p
         for ent in (flat_e[p], x_e[p]):
             if len(ent) and host is not None:
-                s = (ent & lo32).astype(np.int64)
-                j = host.vp_ptr[s] + (ent >> np.uint64(32)).astype(np.int64)
-                assert np.all(j < host.vp_ptr[s + 1]) and np.all(host.vp_part[j] == p)
+                s = (ent & src_mask).astype(np.int64)
+                j = (ent >> np.uint64(ENTRY_SRC_BITS)).astype(np.int64)
+                assert np.all(j >= host.vp_ptr[s]) and np.all(j < host.vp_ptr[s + 1])
+                assert np.all(host.vp_part[j] == p)
     for n in range(wl.n_nodes):
         # device messages carry the first destination's list index above bit 40
         g = np.sort(b_g[n] & np.uint64((1 << 40) - 1))

@@ -30,19 +30,30 @@ def _check_network(wl, host):
     pairs = int(vp_ptr[-1])
     assert host.pairs == pairs
     vp_part = host.vp_part[:pairs].astype(np.int64)
-    vp_seg = host.vp_seg[:pairs].astype(np.int64)
+    rec = host.vp_rec[:2 * pairs].reshape(-1, 2) if pairs else np.zeros((0, 2), np.uint64)
+    seg_start = (rec[:, 0] & np.uint64((1 << 40) - 1)).astype(np.int64)
+    seg_len = (rec[:, 0] >> np.uint64(40)).astype(np.int64)
     owner = np.repeat(np.arange(N), n_vp)
     first = np.zeros(pairs, bool)
     first[vp_ptr[:-1][n_vp > 0]] = True
     assert np.all(vp_part != part[owner])
     assert np.all(np.diff(vp_part)[~first[1:]] > 0)          # ascending within a source
-    assert np.all(vp_seg[first] == nl[owner[first]])          # segments follow the local part
-    seg_end = np.append(vp_seg[1:], 0)
-    last = np.append(~first[1:], False) == False               # noqa: E712
-    seg_end[last] = row_len[owner[last]]
-    seg_len = seg_end - vp_seg
+    # segments: right after the local part, contiguous, ending at the row's end
+    assert np.all(seg_start[first] == row_ptr[owner[first]] + nl[owner[first]])
+    assert np.all(seg_start[1:][~first[1:]] == (seg_start + seg_len)[:-1][~first[1:]])
+    last = np.append(first[1:], True)
+    assert np.all((seg_start + seg_len)[last] == row_ptr[owner[last] + 1])
     assert np.all(seg_len > 0)
     assert seg_len.sum() == (~local).sum()
+    # the record's copy of the segment's first synapse
+    if pairs:
+        assert np.array_equal((rec[:, 1] & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+                              host.tgt_delay[seg_start])
+        wbits = (rec[:, 1] >> np.uint64(32)).astype(np.uint32)
+        if wl.weight_type == "bf16":
+            assert np.array_equal(wbits, host.weight[seg_start].astype(np.uint32))
+        else:
+            assert np.array_equal(wbits, host.weight.view(np.uint32)[seg_start])
     vp_h = np.empty(nnz, np.int64)
     vp_h[local] = part[src_h[local]]
     vp_h[~local] = np.repeat(vp_part, seg_len)
@@ -94,7 +105,7 @@ def test_setup_independent_of_threads():
     wl = synth.get_workload("paper_share").scaled(4000, k_in=50)
     a = HostNetwork(wl, n_threads=1)
     b = HostNetwork(wl, n_threads=7)
-    for k in ("row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_seg",
+    for k in ("row_ptr", "n_local", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_rec",
               "bucket_off", "recv_off"):
         assert np.array_equal(getattr(a, k), getattr(b, k)), k
     assert a.input_bound == b.input_bound
