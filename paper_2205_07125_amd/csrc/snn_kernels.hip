@@ -162,11 +162,21 @@ __device__ void ring_fallback(const KParams& p, uint32_t slot, uint32_t tgt, int
   atomicAdd(reinterpret_cast<unsigned long long*>(&p.st->ring_events), 1ull);
 }
 
-// Sub-bin (slot, tile, delay d in 1..max_delay, deliver block w) of events.
+// Count index of sub-bin (slot, tile, delay d in 1..max_delay, deliver block
+// w): a tile's counts are adjacent (the update reads them in one load).
 __device__ __forceinline__ uint64_t subbin(const KParams& p, uint32_t slot, uint32_t tile,
                                            uint32_t d, uint32_t w) {
   const uint32_t md = p.D - 1;
   return ((static_cast<uint64_t>(slot) * p.n_tiles + tile) * md + (d - 1)) * DELIVER_BLOCKS + w;
+}
+
+// First event of sub-bin (slot, tile, dw = (d - 1) * DELIVER_BLOCKS + w): the
+// sub-bins one deliver block writes, (slot, d, w) over all tiles, are
+// adjacent, so its tile-ordered runs land close together.
+__device__ __forceinline__ uint64_t bin_data(const KParams& p, uint32_t slot, uint32_t tile,
+                                             uint32_t dw) {
+  const uint64_t per_slot = static_cast<uint64_t>(p.D - 1) * DELIVER_BLOCKS;
+  return ((slot * per_slot + dw) * p.n_tiles + tile) * p.bin_cap;
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +374,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     Event x[ARRIVE_UNROLL];
 #pragma unroll
     for (int v = 0; v < ARRIVE_UNROLL; ++v)
-      x[v] = p.bins[(sb0 + k[v]) * p.bin_cap + (ec[v] - s_bpre[k[v]])];
+      x[v] = p.bins[bin_data(p, slot, tile, k[v]) + (ec[v] - s_bpre[k[v]])];
 #pragma unroll
     for (int v = 0; v < ARRIVE_UNROLL; ++v)
       if (e[v] < n_arrive) atomicAdd(&s_acc[x[v].tgt], x[v].wq);
@@ -1032,7 +1042,7 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
       const uint32_t tile = s_tr[k] & 0xFFFFu;
       const uint64_t pos = static_cast<uint64_t>(l_run[tile]) + (j - l_pre[tile]);
       if (pos < p.bin_cap) {
-        p.bins[subbin(p, slot, tile, d, w) * p.bin_cap + pos] = s_ev[k];
+        p.bins[bin_data(p, slot, tile, (d - 1) * DELIVER_BLOCKS + w) + pos] = s_ev[k];
       } else {
         ring_fallback(p, slot, (tile << TILE_SHIFT) | s_ev[k].tgt, s_ev[k].wq);
       }
@@ -1142,7 +1152,7 @@ __global__ __launch_bounds__(256) void k_flush(KParams p) {
     for (uint32_t w = 0; w < DELIVER_BLOCKS; ++w) {
       const uint64_t sb = subbin(p, slot, tile, d, w);
       const uint32_t c = min(p.bin_cnt[sb], static_cast<uint32_t>(p.bin_cap));
-      const Event* ev = p.bins + sb * p.bin_cap;
+      const Event* ev = p.bins + bin_data(p, slot, tile, (d - 1) * DELIVER_BLOCKS + w);
       for (uint32_t e = threadIdx.x; e < c; e += 256)
         unsafeAtomicAdd(p.ring + slot * p.ring_stride + (tile << TILE_SHIFT) + ev[e].tgt,
                         dequantize_w(p, ev[e].wq));
