@@ -231,12 +231,21 @@ snn_status snn_step(snn_handle h);
    follow snn_step. */
 snn_status snn_route(snn_handle h, int mode);
 
+/* snn_step followed by snn_route(mode), in fewer launches: for the two-level
+   modes the update kernel routes each tile's fired neurons itself (Sec. IV-B
+   messages into the node buckets) while it waits for the spike-count prefix
+   of the tiles before it; with more than 1,024 nodes the two calls are made
+   as they are.  The buckets hold the same messages as after snn_route (their
+   order within a bucket may differ).  Order: as snn_step; snn_deliver
+   follows. */
+snn_status snn_step_route(snn_handle h, int mode);
+
 /* Delivers the current step's synaptic events (own partition and receive
    lists): each is scheduled for step t + d in its tile's bin (or the ring
    slot (t + d) mod D when the bin is full).  Order: must follow snn_route. */
 snn_status snn_deliver(snn_handle h);
 
-/* n_steps full steps (step, route(mode), deliver).  use_graph != 0 captures
+/* n_steps full steps (snn_step_route(mode), snn_deliver).  use_graph != 0 captures
    HIP graphs of 16 steps and of one step once per mode and replays them
    (16-step replays first, then single steps for the remainder; all
    step-dependent values live in device memory).  Order: as snn_step. */
@@ -254,10 +263,12 @@ snn_status snn_sync(snn_handle h);
    full).  Synchronises. */
 snn_status snn_ring_events(snn_handle h, uint64_t* n);
 
-/* Measurement aid: runs n_steps ordinary whole steps (route mode `mode`) as
-   separate launches, each kernel bracketed by HIP events recorded on the
-   handle's stream, and writes the average duration in milliseconds of each
-   kernel kind to avg_ms[SNN_NKERNEL] (0 for kinds the mode does not launch).
+/* Measurement aid: runs n_steps ordinary whole steps (route mode `mode`, as
+   snn_run launches them) as separate launches, each kernel bracketed by HIP
+   events recorded on the handle's stream, and writes the average duration in
+   milliseconds of each kernel kind to avg_ms[SNN_NKERNEL] (0 for kinds the
+   mode does not launch; two-level routing done inside the update kernel
+   counts as update).
    The steps advance the simulation like snn_run.  Synchronises.  Order: as
    snn_step. */
 snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg_ms);

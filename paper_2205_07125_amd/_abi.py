@@ -33,7 +33,7 @@ KERNEL_NAMES = ["update", "route_two_level", "expand", "route_flat", "recv_stage
 SNN_NKERNEL = len(KERNEL_NAMES)
 
 EXPORTED = [
-    "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route",
+    "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route", "snn_step_route",
     "snn_deliver", "snn_run", "snn_kernel_times", "snn_flush", "snn_sync", "snn_time",
     "snn_bin_geometry",
     "snn_ring_events",
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
             "snn_step": (I, [vp]),
             "snn_route": (I, [vp, I]),
+            "snn_step_route": (I, [vp, I]),
             "snn_deliver": (I, [vp]),
             "snn_run": (I, [vp, u32, I, I]),
             "snn_kernel_times": (I, [vp, u32, I, vp]),
@@ -165,6 +166,10 @@ def snn_step(h):
 
 def snn_route(h, mode: int):
     check(lib().snn_route(h, mode))
+
+
+def snn_step_route(h, mode: int):
+    check(lib().snn_step_route(h, mode))
 
 
 def snn_deliver(h):

@@ -35,7 +35,10 @@ struct DevState {
   uint32_t cur_slot;   // slot of the step in flight
   uint32_t cur_row;    // row of the step in flight
   uint64_t log_head;   // log_total mod log_cap
-  uint32_t pad[2];
+  uint32_t cur_par;    // parity (t mod 2) of the step in flight: its bucket counter set
+  uint32_t srow;       // t mod (log_steps + 1): counter row of step t
+  uint32_t cur_srow;   // counter row of the step in flight
+  uint32_t pad;
 };
 
 // Stream ids of the counter-based generator.
@@ -65,6 +68,17 @@ constexpr int RECV_THREADS = 512;
 constexpr uint32_t RECV_PER_THREAD = 4;                         // entries per thread per batch
 constexpr uint32_t RECV_BATCH = RECV_THREADS * RECV_PER_THREAD; // entries per batch
 static_assert(STAGE_PARTS <= RECV_THREADS, "one partition count per thread");
+
+// Per-step counters: each row (step mod (log_steps + 1); the spare row is the
+// next step's, cleared by the update kernel ahead of its use) holds STAT_LANES copies of
+// the SNN_NSTAT counters, one 128-byte line each.  A block adds into copy
+// (block index mod STAT_LANES), so the per-block atomics of a kernel spread
+// over STAT_LANES lines instead of queueing on one; the host sums the copies.
+// The spike count is written once, into copy 0.
+constexpr uint32_t STAT_LANES = 16;
+constexpr uint32_t STAT_LANE_WORDS = 16;
+constexpr uint32_t STAT_ROW_WORDS = STAT_LANES * STAT_LANE_WORDS;
+static_assert(SNN_NSTAT <= STAT_LANE_WORDS, "a copy of the counters fits its line");
 
 // Poisson inversion lookup: entry b covers draws r in [b << POIS_LUT_SHIFT,
 // (b + 1) << POIS_LUT_SHIFT).  k = #{j : thr[j] <= r} is the entry itself
@@ -98,6 +112,7 @@ struct Event {
 struct KParams {
   // model
   uint32_t N, P, G, D, n_nodes, n_tiles;
+  uint32_t g_magic;          // ceil(2^32 / G) for G >= 2: node of a partition by one multiply
   uint32_t n_ref;
   uint64_t ring_stride;
   float alpha, theta, u_reset, w_ext;
@@ -134,7 +149,7 @@ struct KParams {
   DevState* st;
   uint64_t* lookback;   // [n_tiles] decoupled look-back words
   uint32_t* fired;      // [N] ascending fired ids of the step in flight
-  uint32_t* bucket_cnt; // [n_nodes * CNT_STRIDE]
+  uint32_t* bucket_cnt; // [2][n_nodes * CNT_STRIDE] two sets, by step parity
   uint64_t* bucket;     // [2 * bucket_total] messages: source | mask << 32 | first
                         // destination's list index << 40, then its pair index
   uint32_t* recv_cnt;   // [P * CNT_STRIDE] expanded lists
@@ -146,7 +161,7 @@ struct KParams {
   uint32_t* bin_cnt;    // [D * n_tiles * CNT_STRIDE]
   uint32_t* dirty;      // [D * n_tiles] ring tile holds events
   Event* bins;          // [D][n_tiles][bin_cap]
-  uint64_t* stats;      // [log_steps][SNN_NSTAT]
+  uint64_t* stats;      // [log_steps + 1][STAT_LANES][STAT_LANE_WORDS]
   uint64_t* log_off;    // [log_steps] first log position of each step
   uint32_t* log;        // [log_cap] spike-log ring
 };
@@ -156,8 +171,14 @@ struct KParams {
 // each launch of kernel kind k (SNN_KERNEL_*).
 uint32_t tiles_of(uint32_t n);
 hipError_t prepare_kernels(KParams& p);   // LDS sizing (sets dstage), once per handle
-hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks = nullptr);
-hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr);
+// With route, the update kernel also routes the step two-level where the node
+// count allows (fused_route_ok); launch_route is then told so (routed) and
+// launches only what remains (expansion, flat lists).
+bool fused_route_ok(const KParams& p);
+hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks = nullptr,
+                         bool route = false);
+hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr,
+                        bool routed = false);
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr);
 hipError_t launch_flush(const KParams& p, hipStream_t s);
 

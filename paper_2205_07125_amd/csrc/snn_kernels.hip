@@ -113,6 +113,12 @@ __device__ __forceinline__ void add_stat(uint64_t* dst, uint64_t v, uint64_t* s_
   add_stats(dst, v, nullptr, 0, s_red);
 }
 
+// This block's copy of the counters of step row `row`.
+__device__ __forceinline__ uint64_t* stat_copy(const KParams& p, uint32_t row) {
+  const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
+  return p.stats + static_cast<uint64_t>(row) * STAT_ROW_WORDS + (b % STAT_LANES) * STAT_LANE_WORDS;
+}
+
 // Exclusive prefix sum of one value per thread over the block; *total gets
 // the block total.  s_wsum holds one word per wave.  Every thread calls it.
 __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wsum, uint32_t* total) {
@@ -179,18 +185,250 @@ __device__ __forceinline__ uint64_t bin_data(const KParams& p, uint32_t slot, ui
   return ((slot * per_slot + dw) * p.n_tiles + tile) * p.bin_cap;
 }
 
+// Sub-bins per (slot, tile) at most.
+constexpr uint32_t MAX_SUBBINS = SNN_MAX_DELAY * DELIVER_BLOCKS;
+static_assert(MAX_SUBBINS <= UPDATE_THREADS, "one sub-bin count per thread");
+constexpr int GATHER_UNROLL = 8;          // loads in flight per thread (deliver, receive)
+// The update reads its sub-bins in groups of ARRIVE_LANES lanes, one sub-bin
+// per group at a time (lane j takes event j), ARRIVE_UNROLL sub-bins per
+// group in flight.
+constexpr uint32_t ARRIVE_LANES = 32;
+constexpr uint32_t ARRIVE_GROUPS = UPDATE_THREADS / ARRIVE_LANES;
+constexpr int ARRIVE_UNROLL = 10;
+constexpr int ROUTE_UNROLL = 8;           // destination-list loads in flight per thread
+// Two-level routing inside the update kernel (one tile's fired neurons per
+// block): window of pairs, and the node count up to which its counters fit
+// the LDS the update leaves free.
+constexpr uint32_t FUSED_ROUTE_WINDOW = 1024;
+constexpr uint32_t FUSED_MAX_NODES = 1024;
+constexpr int FUSED_ROUTE_UNROLL = FUSED_ROUTE_WINDOW / UPDATE_THREADS;   // one load round per window
+
+// ---------------------------------------------------------------------------
+// route
+
+// Node of partition v (v < 2^16, G <= 8): v / G as one high multiply; with
+// M = ceil(2^32 / G) the product exceeds v / G by less than 2^-16, too little
+// to pass the next integer.
+__device__ __forceinline__ uint32_t node_of(const KParams& p, uint32_t v) {
+  return p.G == 1 ? v : __umulhi(v, p.g_magic);
+}
+
+// Message to node n for source s: bits 0..31 source, 32..39 mask of the
+// node's destination partitions, 40..63 index (in s's destination list) of
+// the node's first destination partition.
+__device__ __forceinline__ uint32_t node_mask(const KParams& p, int64_t j, int64_t j1,
+                                              uint32_t node) {
+  uint32_t mask = 0;
+  for (int64_t jj = j; jj < j1; ++jj) {
+    const uint32_t vv = p.vp_part[jj];
+    if (node_of(p, vv) != node) break;
+    mask |= 1u << (vv - p.G * node);
+  }
+  return mask;
+}
+
+// Message of node `node` at position pos of its bucket: word 0 = source |
+// mask << 32 | list index of the node's first destination << 40, word 1 =
+// that destination's pair index (the receive record the expansion hands on).
+__device__ __forceinline__ void bucket_put(const KParams& p, uint32_t node, uint32_t pos,
+                                           uint64_t msg, uint64_t pair) {
+  const uint64_t off = p.bucket_off[node];
+  if (off + pos < p.bucket_off[node + 1]) {
+    uint64_t* m = p.bucket + 2 * (off + pos);
+    m[0] = msg;
+    m[1] = pair;
+  } else {
+    atomicOr(&p.st->error, ERR_BUCKET);
+  }
+}
+
+// Bucket counters of the step with parity par (t mod 2).  Steps alternate
+// between two sets: the update kernel of step t clears the set of step t + 1
+// while step t's routing (possibly in the same kernel) counts into its own.
+__device__ __forceinline__ uint32_t* bucket_counts(const KParams& p, uint32_t par) {
+  return p.bucket_cnt + static_cast<uint64_t>(par) * p.n_nodes * CNT_STRIDE;
+}
+
+// LDS arrays of the two-level routing of a batch of at most NT sources of
+// one block, over windows of W (source, destination) pairs.
+struct RouteLds {
+  int64_t* j0;     // [NT] first pair index of each source
+  uint64_t* msg;   // [W] staged messages
+  uint32_t* pre;   // [NT + 1] list starts in the concatenation of the batch's lists
+  uint32_t* src;   // [NT] source ids of the batch
+  uint32_t* own;   // [NT] node of each source
+  uint32_t* nr;    // [W] node | rank among the window's messages to that node << 16
+  uint32_t* cnt;   // [n_nodes] messages of the window per node
+  uint32_t* base;  // [n_nodes] their reserved start in the node's bucket
+  uint16_t* nb;    // [W] node << 3 | bit of each pair's partition in the node
+  uint16_t* pk;    // [W] batch index of each pair's source
+  uint16_t* off;   // [W] position of each pair in its source's list
+  uint16_t* mk;    // [W] batch index of each message's source
+  uint32_t W;
+};
+
+__host__ __device__ constexpr size_t route_lds_bytes(uint32_t nt, uint32_t w, uint32_t n_nodes) {
+  return size_t(nt) * 8 + size_t(w) * 8 + (size_t(nt) + 2) * 4 + size_t(nt) * 8 + size_t(w) * 4 +
+         size_t(n_nodes) * 8 + size_t(w) * 8;
+}
+
+__device__ RouteLds route_lds(void* lds, uint32_t nt, uint32_t w, uint32_t n_nodes) {
+  RouteLds L;
+  char* c = static_cast<char*>(lds);
+  L.j0 = reinterpret_cast<int64_t*>(c);                  c += size_t(nt) * 8;
+  L.msg = reinterpret_cast<uint64_t*>(c);                c += size_t(w) * 8;
+  L.pre = reinterpret_cast<uint32_t*>(c);                c += (size_t(nt) + 2) * 4;
+  L.src = reinterpret_cast<uint32_t*>(c);                c += size_t(nt) * 4;
+  L.own = reinterpret_cast<uint32_t*>(c);                c += size_t(nt) * 4;
+  L.nr = reinterpret_cast<uint32_t*>(c);                 c += size_t(w) * 4;
+  L.cnt = reinterpret_cast<uint32_t*>(c);                c += size_t(n_nodes) * 4;
+  L.base = reinterpret_cast<uint32_t*>(c);               c += size_t(n_nodes) * 4;
+  L.nb = reinterpret_cast<uint16_t*>(c);                 c += size_t(w) * 2;
+  L.pk = reinterpret_cast<uint16_t*>(c);                 c += size_t(w) * 2;
+  L.off = reinterpret_cast<uint16_t*>(c);                c += size_t(w) * 2;
+  L.mk = reinterpret_cast<uint16_t*>(c);
+  L.W = w;
+  return L;
+}
+
+// Two-level routing (Sec. IV-B) of the n <= NT sources in L.src: one message
+// per (source, destination node) into the node buckets counted by bcnt.
+// The sources' destination lists are taken as one flat sequence of pairs: one
+// thread per source loads the list bounds, a block scan concatenates the
+// lists, and windows of W pairs are loaded into LDS, U loads in flight per
+// thread, each pair stored as its node and its partition's bit in
+// the node.  A pair that starts a run of equal node in its source's
+// (ascending) list ORs the run into the mask: the run has at most G pairs, so
+// the next SNN_MAX_GPUS_PER_NODE - 1 pairs are read at once from LDS (global
+// memory only for a run that continues past the window's end).  Messages are
+// staged in LDS with their rank among the window's messages to their node;
+// one atomic per (window, node) then reserves the node's bucket space.  A
+// window has at most as many messages as pairs, so the stage never
+// overflows.  Every thread of the block calls it; it ends with a barrier.
+template <uint32_t NT, int U>
+__device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uint32_t* bcnt,
+                            uint64_t& l1, uint64_t& l2) {
+  __shared__ uint32_t l_total, s_prev_node;
+  __shared__ uint32_t s_wsum[NT / 64];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t G = p.G;
+  uint32_t len = 0;
+  if (tid < n) {
+    const uint32_t s = L.src[tid];
+    const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
+    L.own[tid] = node_of(p, static_cast<uint32_t>(p.part[s]));
+    L.j0[tid] = j0;
+    len = static_cast<uint32_t>(j1 - j0);
+  }
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan(len, s_wsum, &tot);
+  L.pre[tid] = ex;
+  if (tid == 0) L.pre[n] = tot;
+  __syncthreads();
+  for (uint32_t w0 = 0; w0 < tot; w0 += L.W) {
+    const uint32_t nwin = min(tot - w0, L.W);
+    for (uint32_t i = tid; i < p.n_nodes; i += NT) L.cnt[i] = 0;
+    if (tid == 0) {
+      l_total = 0;
+      // node of the pair before the window, where the window starts inside a list
+      const uint32_t k0 = owner_of<NT / 2>(L.pre, n, w0);
+      const uint32_t off0 = w0 - L.pre[k0];
+      s_prev_node = off0 > 0 ? node_of(p, p.vp_part[L.j0[k0] + off0 - 1]) : 0xFFFFFFFFu;
+    }
+    // the window's pairs into LDS
+    for (uint32_t i0 = 0; i0 < nwin; i0 += U * NT) {
+      uint32_t vp[U], kk[U], o[U];
+#pragma unroll
+      for (int v = 0; v < U; ++v) {
+        const uint32_t e = w0 + min(i0 + v * NT + tid, nwin - 1);
+        kk[v] = owner_of<NT / 2>(L.pre, n, e);
+        o[v] = e - L.pre[kk[v]];
+        vp[v] = p.vp_part[L.j0[kk[v]] + o[v]];
+      }
+#pragma unroll
+      for (int v = 0; v < U; ++v) {
+        const uint32_t i = i0 + v * NT + tid;
+        if (i < nwin) {
+          const uint32_t node = node_of(p, vp[v]);
+          L.nb[i] = static_cast<uint16_t>((node << 3) | (vp[v] - G * node));
+          L.pk[i] = static_cast<uint16_t>(kk[v]);
+          L.off[i] = static_cast<uint16_t>(o[v]);
+        }
+      }
+    }
+    __syncthreads();
+    // one message per run of equal node
+    for (uint32_t i = tid; i < nwin; i += NT) {
+      const uint32_t k = L.pk[i], off = L.off[i], nbi = L.nb[i];
+      const uint32_t node = nbi >> 3;
+      if (off > 0 && (i > 0 ? static_cast<uint32_t>(L.nb[i - 1] >> 3) : s_prev_node) == node)
+        continue;
+      uint32_t mask = 1u << (nbi & 7u);
+      bool open = true, cut = false;
+#pragma unroll
+      for (uint32_t d = 1; d < SNN_MAX_GPUS_PER_NODE; ++d) {
+        const bool in = i + d < nwin;
+        cut = cut || (open && !in);
+        const uint32_t at = min(i + d, nwin - 1);
+        const uint32_t v = L.nb[at], kv = L.pk[at];
+        open = open && in && kv == k && (v >> 3) == node;
+        if (open) mask |= 1u << (v & 7u);
+      }
+      if (cut) {   // the run reaches the window's end: its rest from global memory
+        const uint32_t len_k = L.pre[k + 1] - L.pre[k];
+        for (uint32_t x = off + (nwin - i); x < len_k; ++x) {
+          const uint32_t v = p.vp_part[L.j0[k] + x];
+          if (node_of(p, v) != node) break;
+          mask |= 1u << (v - G * node);
+        }
+      }
+      const uint64_t msg = (static_cast<uint64_t>(off) << 40) |
+                           (static_cast<uint64_t>(mask) << 32) | L.src[k];
+      const uint32_t slot = atomicAdd(&l_total, 1u);
+      const uint32_t rk = atomicAdd(&L.cnt[node], 1u);
+      L.msg[slot] = msg;
+      L.nr[slot] = node | (rk << 16);
+      L.mk[slot] = static_cast<uint16_t>(k);
+      if (node == L.own[k]) ++l1; else ++l2;
+    }
+    __syncthreads();
+    for (uint32_t nn = tid; nn < p.n_nodes; nn += NT) {
+      const uint32_t c = L.cnt[nn];
+      if (c) L.base[nn] = atomicAdd(bcnt + nn * CNT_STRIDE, c);
+    }
+    __syncthreads();
+    // bucket bounds of U messages loaded together (clamped
+    // indices keep the loads unconditional), then the stores
+    const uint32_t n_msg = l_total;
+    for (uint32_t k0 = tid; k0 < n_msg; k0 += U * NT) {
+      uint64_t o[U], o1[U];
+#pragma unroll
+      for (int v = 0; v < U; ++v) {
+        const uint32_t node = L.nr[min(k0 + v * NT, n_msg - 1)] & 0xFFFFu;
+        o[v] = p.bucket_off[node];
+        o1[v] = p.bucket_off[node + 1];
+      }
+#pragma unroll
+      for (int v = 0; v < U; ++v) {
+        const uint32_t k = k0 + v * NT;
+        if (k >= n_msg) continue;
+        const uint32_t nr = L.nr[k];
+        const uint64_t pos = o[v] + L.base[nr & 0xFFFFu] + (nr >> 16);
+        if (pos < o1[v]) {
+          const uint64_t msg = L.msg[k];
+          p.bucket[2 * pos] = msg;
+          p.bucket[2 * pos + 1] = static_cast<uint64_t>(L.j0[L.mk[k]]) + (msg >> 40);
+        } else {
+          atomicOr(&p.st->error, ERR_BUCKET);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // update: arriving input, neuron update, threshold, ascending compaction
-
-// Sub-bins per (slot, tile) at most, and the top step of the power-of-two
-// search over them.
-constexpr uint32_t MAX_SUBBINS = SNN_MAX_DELAY * DELIVER_BLOCKS;
-constexpr uint32_t SUBBIN_SEARCH_TOP = 256;
-static_assert(2 * SUBBIN_SEARCH_TOP > MAX_SUBBINS, "search must reach every sub-bin");
-static_assert(MAX_SUBBINS <= UPDATE_THREADS, "one sub-bin count per thread");
-constexpr int GATHER_UNROLL = 4;          // loads in flight per thread (deliver, receive)
-constexpr int ARRIVE_UNROLL = 8;          // loads in flight per thread (update's gather)
-constexpr int ROUTE_UNROLL = 8;           // destination-list loads in flight per thread
 
 // Look-back word: [63:34] step tag, [33:32] status, [31:0] count.
 constexpr uint32_t LB_AGG = 1u, LB_INCL = 2u;
@@ -199,23 +437,24 @@ __device__ __forceinline__ uint64_t lb_pack(uint32_t tag, uint32_t status, uint3
   return (static_cast<uint64_t>(tag) << 34) | (static_cast<uint64_t>(status) << 32) | v;
 }
 
-// Wave 0 of block b: publishes the block's count, walks back over the
-// predecessors 64 at a time until an inclusive prefix closes the window, and
-// publishes the inclusive prefix.  Returns the exclusive prefix.
+// Decoupled look-back, run by wave 0 of block b in two parts so that a block
+// can do other work between them: lookback_publish makes the block's count
+// visible (block 0 publishes its inclusive prefix at once), lookback_resolve
+// walks back over the predecessors 64 at a time until an inclusive prefix
+// closes the window, publishes the block's inclusive prefix and returns the
+// exclusive one.
 // The 64-bit word carries tag, status and count together and nothing else
 // is read through it, so relaxed device-scope atomics suffice: acquire or
 // release would add an L2 invalidate or write-back to every poll.
-__device__ uint32_t lookback_exclusive(uint64_t* lb, uint32_t b, uint32_t agg, uint32_t tag) {
-  const int lane = threadIdx.x & 63;
-  if (b == 0) {
-    if (lane == 0)
-      __hip_atomic_store(lb, lb_pack(tag, LB_INCL, agg), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
-  }
-  if (lane == 0)
-    __hip_atomic_store(lb + b, lb_pack(tag, LB_AGG, agg), __ATOMIC_RELAXED,
+__device__ void lookback_publish(uint64_t* lb, uint32_t b, uint32_t agg, uint32_t tag) {
+  if ((threadIdx.x & 63) == 0)
+    __hip_atomic_store(lb + b, lb_pack(tag, b == 0 ? LB_INCL : LB_AGG, agg), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ uint32_t lookback_resolve(uint64_t* lb, uint32_t b, uint32_t agg, uint32_t tag) {
+  const int lane = threadIdx.x & 63;
+  if (b == 0) return 0;
   uint32_t excl = 0;
   int64_t j = static_cast<int64_t>(b) - 1;
   while (true) {
@@ -254,19 +493,31 @@ __device__ uint32_t lookback_exclusive(uint64_t* lb, uint32_t b, uint32_t agg, u
 // every load and store instruction of a wave touches one contiguous 1 KiB
 // span.  Ids are ordered quad-major across the block, which the compaction
 // follows.
+// With ROUTE, the block also routes its tile's fired neurons two-level
+// (route_batch) between publishing its spike count and resolving its prefix,
+// so the routing's latency overlaps the look-back and no separate routing
+// launch is needed; the LDS of the input sums and the Poisson lookup, free by
+// then, holds the routing's arrays.
 static_assert(UPDATE_NPT % 4 == 0 && UPDATE_NPT <= 32, "fire bits of a thread fit 32 bits");
+constexpr size_t UPDATE_BIG_LDS = TILE * sizeof(int32_t) + POIS_LUT_SIZE;
+static_assert(route_lds_bytes(UPDATE_THREADS, FUSED_ROUTE_WINDOW, FUSED_MAX_NODES) <= UPDATE_BIG_LDS,
+              "the fused routing's arrays fit the update's LDS");
+template <bool ROUTE>
 __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   constexpr int NQ = UPDATE_NPT / 4;
   constexpr int NW = UPDATE_THREADS / 64;
-  __shared__ int32_t s_acc[TILE];     // arriving input, fixed point (units of 2^-F)
+  // input sums (TILE int32, fixed point in units of 2^-F) and the Poisson
+  // inversion lookup (bytes); the routing's arrays afterwards
+  __shared__ uint4 s_big[UPDATE_BIG_LDS / 16];
+  int32_t* s_acc = reinterpret_cast<int32_t*>(s_big);
+  uint4* s_lut4 = s_big + TILE / 4;
   __shared__ uint32_t s_cnt[NQ][NW];    // spikes per (quad, wave)
   __shared__ uint32_t s_qoff[NQ][NW];   // their offsets in the block's order
-  __shared__ uint32_t s_wsum[NW];
-  __shared__ uint32_t s_bpre[MAX_SUBBINS + 1];
+  __shared__ uint32_t s_bcnt[MAX_SUBBINS];
   __shared__ uint32_t s_excl, s_btot;
   __shared__ uint32_t s_dirty;
-  __shared__ uint4 s_lut4[POIS_LUT_SIZE / 16];   // Poisson inversion lookup (bytes)
   __shared__ uint32_t s_thr[16];
+  __shared__ uint64_t s_red[2 * NW];
 
   // Read once (uniform, so kept in scalar registers): the last block advances
   // the step state when the step is complete.
@@ -278,6 +529,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   const uint32_t t32 = rd32(reinterpret_cast<const uint32_t*>(&st->t));   // low word
   const uint32_t slot = rd32(&st->slot);
   const uint32_t row = rd32(&st->row);
+  const uint32_t srow = rd32(&st->srow);
   const uint32_t phase = rd32(&st->phase);
   const uint32_t tag = rd32(&st->tag) + 1u;
   const uint64_t log_head =
@@ -287,14 +539,18 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   const uint32_t tile = blockIdx.x;
   const uint32_t blk0 = tile * TILE;
 
-  // Per-step counters of the routing kernels that follow.
+  // Per-step counters of the routing: the bucket counters of step t + 1 (this
+  // step's routing counts into the other set) and the receive-list counters.
   if (blockIdx.x == 0) {
-    for (uint32_t i = tid; i < p.n_nodes; i += UPDATE_THREADS) p.bucket_cnt[i * CNT_STRIDE] = 0;
+    uint32_t* next_bcnt = bucket_counts(p, (t32 + 1u) & 1u);
+    for (uint32_t i = tid; i < p.n_nodes; i += UPDATE_THREADS) next_bcnt[i * CNT_STRIDE] = 0;
     for (uint32_t i = tid; i < p.P; i += UPDATE_THREADS) {
       p.recv_cnt[i * CNT_STRIDE] = 0;
       p.flat_cnt[i * CNT_STRIDE] = 0;
     }
-    if (tid >= 1 && tid < SNN_NSTAT) p.stats[static_cast<uint64_t>(row) * SNN_NSTAT + tid] = 0;
+    // the counter row of step t + 1 (this step's was cleared by the step before)
+    const uint32_t next_srow = srow + 1 == p.log_steps + 1 ? 0u : srow + 1;
+    if (tid < STAT_ROW_WORDS) p.stats[static_cast<uint64_t>(next_srow) * STAT_ROW_WORDS + tid] = 0;
   }
   for (uint32_t i = tid; i < TILE; i += UPDATE_THREADS) s_acc[i] = 0;
   if (tid == 0) s_dirty = p.dirty[slot * p.n_tiles + tile];
@@ -332,54 +588,45 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   __syncthreads();
 
   // Arriving input of step t: the sub-bins (slot, tile, d, w) written d steps
-  // ago by deliver block w.  Their counts are read in one coalesced load and
-  // scanned; the events are then taken as one flat sequence (a power-of-two
-  // search over the scanned counts finds an event's sub-bin), ARRIVE_UNROLL
-  // loads in flight per thread.
+  // ago by deliver block w.  Their counts are read in one coalesced load;
+  // then each group of ARRIVE_LANES lanes takes whole sub-bins, so an event's
+  // address is its sub-bin's start plus the lane (no search over the counts).
+  // A lane without an event re-reads event 0 of the tile's first sub-bin (a
+  // valid address) and skips the add, so the loads carry no branch and issue
+  // together.  Events past ARRIVE_LANES in a sub-bin (rare) take a second loop.
   const uint32_t md = p.D - 1;
   const uint32_t n_sub = md * DELIVER_BLOCKS;
-  const uint64_t sb0 = subbin(p, slot, tile, 1, 0);
-  {
-    const uint32_t c = tid < n_sub ? min(p.bin_cnt[sb0 + tid], static_cast<uint32_t>(p.bin_cap))
-                                   : 0u;
-    const uint32_t incl = wave_incl_scan(c);
-    if (lane == 63) s_wsum[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t w = 0; w < wave; ++w) before += s_wsum[w];
-    if (tid < n_sub) s_bpre[tid] = before + incl - c;
-    if (tid == n_sub - 1) s_bpre[n_sub] = before + incl;
-  }
+  if (tid < n_sub)
+    s_bcnt[tid] = min(p.bin_cnt[subbin(p, slot, tile, 1, 0) + tid], static_cast<uint32_t>(p.bin_cap));
   __syncthreads();
-  const uint32_t n_arrive = s_bpre[n_sub];
-  for (uint32_t e0 = 0; e0 < n_arrive; e0 += ARRIVE_UNROLL * UPDATE_THREADS) {
-    // Past the end a lane re-reads the last event (always a valid address)
-    // and skips the add, so the loads carry no branch and issue together.
-    uint32_t e[ARRIVE_UNROLL], ec[ARRIVE_UNROLL], k[ARRIVE_UNROLL];
-#pragma unroll
-    for (int v = 0; v < ARRIVE_UNROLL; ++v) {
-      e[v] = e0 + v * UPDATE_THREADS + tid;
-      ec[v] = min(e[v], n_arrive - 1);
-      k[v] = 0;
-    }
-    // largest k < n_sub with s_bpre[k] <= ec: the sub-bin holding event ec
-#pragma unroll
-    for (uint32_t step = SUBBIN_SEARCH_TOP; step; step >>= 1) {
-#pragma unroll
-      for (int v = 0; v < ARRIVE_UNROLL; ++v) {
-        const uint32_t m = k[v] + step;
-        if (m < n_sub && s_bpre[m] <= ec[v]) k[v] = m;
-      }
-    }
+  // sub-bin dw of this tile starts at ev0 + dw * sub_stride
+  const Event* ev0 = p.bins + bin_data(p, slot, tile, 0);
+  const uint64_t sub_stride = static_cast<uint64_t>(p.n_tiles) * p.bin_cap;
+  const uint32_t grp = tid / ARRIVE_LANES, gl = tid % ARRIVE_LANES;
+  bool over = false;
+  for (uint32_t k0 = grp; k0 < n_sub; k0 += ARRIVE_GROUPS * ARRIVE_UNROLL) {
+    bool has[ARRIVE_UNROLL];
     Event x[ARRIVE_UNROLL];
 #pragma unroll
-    for (int v = 0; v < ARRIVE_UNROLL; ++v)
-      x[v] = p.bins[bin_data(p, slot, tile, k[v]) + (ec[v] - s_bpre[k[v]])];
+    for (int v = 0; v < ARRIVE_UNROLL; ++v) {
+      const uint32_t k = k0 + v * ARRIVE_GROUPS;
+      const uint32_t c = k < n_sub ? s_bcnt[k] : 0u;
+      has[v] = gl < c;
+      over |= c > ARRIVE_LANES;
+      x[v] = ev0[has[v] ? k * sub_stride + gl : 0];
+    }
 #pragma unroll
     for (int v = 0; v < ARRIVE_UNROLL; ++v)
-      if (e[v] < n_arrive) atomicAdd(&s_acc[x[v].tgt], x[v].wq);
+      if (has[v]) atomicAdd(&s_acc[x[v].tgt], x[v].wq);
   }
-  __syncthreads();
+  if (__syncthreads_or(over)) {
+    for (uint32_t k = grp; k < n_sub; k += ARRIVE_GROUPS)
+      for (uint32_t j = ARRIVE_LANES + gl; j < s_bcnt[k]; j += ARRIVE_LANES) {
+        const Event y = ev0[k * sub_stride + j];
+        atomicAdd(&s_acc[y.tgt], y.wq);
+      }
+    __syncthreads();
+  }
   // events that did not fit their bins are in this tile's slice of the ring
   // slot; a flagged tile reads (and clears) it with the neuron state
   float* ring_slot = p.ring + static_cast<uint64_t>(slot) * p.ring_stride;
@@ -406,13 +653,16 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (p.forced) rnd2 = philox4x32_10(i0 >> 2, t32, STREAM_RASTER, 0u, p.seed_lo, p.seed_hi);
     const uint32_t r1[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
     const uint32_t r2[4] = {rnd2.x, rnd2.y, rnd2.z, rnd2.w};
-    // arriving input: the exact fixed-point sum rounded once to binary32,
-    // plus the ring slice of a flagged tile
+    // arriving input: the exact fixed-point sum rounded once to binary32
+    // (rounding the integer and then scaling by the power of two 2^-F gives
+    // the same value: the scaling is exact), plus the ring slice of a
+    // flagged tile
     const int4 acc4 = *reinterpret_cast<const int4*>(&s_acc[l0]);
     const int32_t acc[4] = {acc4.x, acc4.y, acc4.z, acc4.w};
+    const float wq_inv = static_cast<float>(p.wq_inv);
     float syn[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) syn[k] = static_cast<float>(static_cast<double>(acc[k]) * p.wq_inv);
+    for (int k = 0; k < 4; ++k) syn[k] = __fmul_rn(static_cast<float>(acc[k]), wq_inv);
     if (dirty) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -470,9 +720,10 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
 
   // Compaction.  Within quad q, ids ascend with (wave, lane, k); across
   // quads, quad q of every wave precedes quad q + 1.  The rank of a fired id
-  // is: the offset of its (quad, wave) in that order (one wave scans the
-  // NQ x NW counts) + fired ids of lower lanes in the same (quad, wave)
-  // (4 ballots) + earlier k.  The block's total goes through the look-back.
+  // in the block is: the offset of its (quad, wave) in that order (one wave
+  // scans the NQ x NW counts) + fired ids of lower lanes in the same (quad,
+  // wave) (4 ballots) + earlier k.  The block's total goes through the
+  // look-back.
   static_assert(NQ * NW <= 64, "one lane per (quad, wave)");
   __syncthreads();
   if (wave == 0) {
@@ -480,36 +731,63 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     const uint32_t incl = wave_incl_scan(c);
     if (lane < NQ * NW) s_qoff[lane / NW][lane % NW] = incl - c;
     const uint32_t block_tot = __shfl(incl, 63, 64);
-    const uint32_t excl = lookback_exclusive(p.lookback, blockIdx.x, block_tot, tag);
-    if (lane == 0) {
-      s_excl = excl;
-      s_btot = block_tot;
-    }
+    lookback_publish(p.lookback, blockIdx.x, block_tot, tag);
+    if (lane == 0) s_btot = block_tot;
   }
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
+  // f(rank in the block, id) for every fired neuron of this thread
+  auto for_each_fired = [&](auto&& f) {
 #pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const uint32_t qb = (fire_bits >> (4 * q)) & 0xFu;
-    if (__ballot(qb != 0) == 0) continue;
-    uint32_t pos = s_excl + s_qoff[q][wave];
+    for (int q = 0; q < NQ; ++q) {
+      const uint32_t qb = (fire_bits >> (4 * q)) & 0xFu;
+      if (__ballot(qb != 0) == 0) continue;
+      uint32_t pos = s_qoff[q][wave];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pos += __popcll(__ballot((qb >> k) & 1u) & lt);
-    const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
+      for (int k = 0; k < 4; ++k) pos += __popcll(__ballot((qb >> k) & 1u) & lt);
+      const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if ((qb >> k) & 1u) {
-        p.fired[pos] = i0 + k;
-        // a step with more spikes than the log holds is flagged by the last
-        // block (ERR_LOG); its ids past the capacity are not logged
-        if (pos < p.log_cap) {
-          uint64_t at = log_head + pos;
-          if (at >= p.log_cap) at -= p.log_cap;
-          p.log[at] = i0 + k;
-        }
-        ++pos;
-      }
+      for (int k = 0; k < 4; ++k)
+        if ((qb >> k) & 1u) f(pos++, i0 + k);
+    }
+  };
+  const uint32_t btot = s_btot;
+
+  if constexpr (ROUTE) {
+    // the tile's fired neurons, UPDATE_THREADS at a time, routed into the
+    // bucket set of this step
+    const RouteLds L = route_lds(s_big, UPDATE_THREADS, FUSED_ROUTE_WINDOW, p.n_nodes);
+    uint32_t* bcnt = bucket_counts(p, t32 & 1u);
+    uint64_t l1 = 0, l2 = 0;
+    for (uint32_t b0 = 0; b0 < btot; b0 += UPDATE_THREADS) {
+      for_each_fired([&](uint32_t r, uint32_t id) {
+        if (r - b0 < UPDATE_THREADS) L.src[r - b0] = id;
+      });
+      __syncthreads();
+      route_batch<UPDATE_THREADS, FUSED_ROUTE_UNROLL>(
+          p, L, min(btot - b0, static_cast<uint32_t>(UPDATE_THREADS)), bcnt, l1, l2);
+    }
+    uint64_t* sc = stat_copy(p, srow);
+    add_stats(sc + SNN_STAT_MSG_L1, l1, sc + SNN_STAT_MSG_L2, l2, s_red);
   }
+
+  if (wave == 0) {
+    const uint32_t excl = lookback_resolve(p.lookback, blockIdx.x, btot, tag);
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  const uint32_t excl = s_excl;
+  for_each_fired([&](uint32_t r, uint32_t id) {
+    const uint32_t pos = excl + r;
+    p.fired[pos] = id;
+    // a step with more spikes than the log holds is flagged by the last
+    // block (ERR_LOG); its ids past the capacity are not logged
+    if (pos < p.log_cap) {
+      uint64_t at = log_head + pos;
+      if (at >= p.log_cap) at -= p.log_cap;
+      p.log[at] = id;
+    }
+  });
 
   // The last block holds the step total once its look-back is done; every
   // other block has read t and log_total by then (they published first).
@@ -518,13 +796,16 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     const uint32_t n = s_excl + s_btot;
     const uint64_t log_base = w->log_total;
     w->n_fired = n;
-    p.stats[static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_SPIKES] = n;
+    p.stats[static_cast<uint64_t>(srow) * STAT_ROW_WORDS + SNN_STAT_SPIKES] = n;
     p.log_off[row] = log_base;
     if (p.log_cap && n > p.log_cap) atomicOr(&w->error, ERR_LOG);
     w->log_total = log_base + n;
     if (p.log_cap) w->log_head = (w->log_head + n) % p.log_cap;
     w->cur_slot = slot;
     w->cur_row = row;
+    w->cur_par = t32 & 1u;
+    w->cur_srow = srow;
+    w->srow = srow + 1 == p.log_steps + 1 ? 0u : srow + 1;
     w->slot = slot + 1 == p.D ? 0u : slot + 1;
     w->row = row + 1 == p.log_steps ? 0u : row + 1;
     w->phase = phase + 1 == p.raster_period ? 0u : phase + 1;
@@ -533,173 +814,27 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// route
-
-// Message to node n for source s: bits 0..31 source, 32..39 mask of the
-// node's destination partitions, 40..63 index (in s's destination list) of
-// the node's first destination partition.
-__device__ __forceinline__ uint32_t node_mask(const KParams& p, int64_t j, int64_t j1,
-                                              uint32_t node) {
-  uint32_t mask = 0;
-  for (int64_t jj = j; jj < j1; ++jj) {
-    const uint32_t vv = p.vp_part[jj];
-    if (vv / p.G != node) break;
-    mask |= 1u << (vv - p.G * node);
-  }
-  return mask;
-}
-
-// Message of node `node` at position pos of its bucket: word 0 = source |
-// mask << 32 | list index of the node's first destination << 40, word 1 =
-// that destination's pair index (the receive record the expansion hands on).
-__device__ __forceinline__ void bucket_put(const KParams& p, uint32_t node, uint32_t pos,
-                                           uint64_t msg, uint64_t pair) {
-  const uint64_t off = p.bucket_off[node];
-  if (off + pos < p.bucket_off[node + 1]) {
-    uint64_t* m = p.bucket + 2 * (off + pos);
-    m[0] = msg;
-    m[1] = pair;
-  } else {
-    atomicOr(&p.st->error, ERR_BUCKET);
-  }
-}
-
-// Two-level: block b takes a contiguous chunk of the fired sources.  Their
-// destination lists are taken as one flat sequence of (source, destination
-// partition) pairs: one thread per source loads the list bounds, a block scan
-// concatenates the lists, and windows of ROUTE_STAGE pairs are loaded into LDS
-// with ROUTE_UNROLL loads in flight per thread.  A pair that starts a run of
-// equal node in its source's (ascending) list ORs the run into the node's
-// mask, from LDS (from global memory past the window's end), and stages the
-// message with its rank among the window's messages to that node; one atomic
-// per (window, node) then reserves the node's bucket space.  A window has at
-// most as many messages as pairs, so the stage never overflows.
-// Dynamic LDS: ROUTE_STAGE messages, node/rank words, pairs and their source
-// index, each message's source index, + 2 * n_nodes counters.
+// Two-level routing as a kernel of its own: block b routes a contiguous chunk
+// of the step's fired sources, ROUTE_THREADS at a time (route_batch).
+// Dynamic LDS: route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, n_nodes).
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
   extern __shared__ uint64_t lds_u64[];
-  uint64_t* s_msg = lds_u64;                                              // [ROUTE_STAGE]
-  uint32_t* s_nr = reinterpret_cast<uint32_t*>(s_msg + ROUTE_STAGE);      // node | rank << 16
-  uint32_t* l_cnt = s_nr + ROUTE_STAGE;                                   // [n_nodes]
-  uint32_t* l_base = l_cnt + p.n_nodes;                                   // [n_nodes]
-  uint16_t* s_vp = reinterpret_cast<uint16_t*>(l_base + p.n_nodes);       // [ROUTE_STAGE]
-  uint16_t* s_k = s_vp + ROUTE_STAGE;                                     // [ROUTE_STAGE]
-  uint16_t* s_mk = s_k + ROUTE_STAGE;                                     // source of message
-  constexpr uint32_t NW = ROUTE_THREADS / 64;
-  __shared__ uint32_t l_total;
-  __shared__ uint32_t s_src[ROUTE_THREADS], s_own[ROUTE_THREADS], s_pre[ROUTE_THREADS + 1];
-  __shared__ int64_t s_j0[ROUTE_THREADS];
-  __shared__ uint32_t s_wsum[NW];
-  __shared__ uint64_t s_red[2 * NW];
+  __shared__ uint64_t s_red[2 * (ROUTE_THREADS / 64)];
+  const RouteLds L = route_lds(lds_u64, ROUTE_THREADS, ROUTE_STAGE, p.n_nodes);
   const uint32_t nF = p.st->n_fired;
-  const uint32_t row = p.st->cur_row;
+  const uint32_t row = p.st->cur_srow;   // counter row
+  uint32_t* bcnt = bucket_counts(p, p.st->cur_par);
   const uint32_t tid = threadIdx.x;
-  const uint32_t G = p.G;
   const uint32_t chunk = (nF + gridDim.x - 1) / gridDim.x;
   const uint32_t lo = min(blockIdx.x * chunk, nF), hi = min(lo + chunk, nF);
   uint64_t l1 = 0, l2 = 0;
   for (uint32_t r0 = lo; r0 < hi; r0 += ROUTE_THREADS) {
-    const uint32_t nsrc = min(hi - r0, static_cast<uint32_t>(ROUTE_THREADS));
-    uint32_t len = 0;
-    if (tid < nsrc) {
-      const uint32_t s = p.fired[r0 + tid];
-      const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
-      s_src[tid] = s;
-      s_own[tid] = static_cast<uint32_t>(p.part[s]) / G;
-      s_j0[tid] = j0;
-      len = static_cast<uint32_t>(j1 - j0);
-    }
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(len, s_wsum, &tot);
-    s_pre[tid] = ex;
-    if (tid == 0) s_pre[nsrc] = tot;
+    const uint32_t n = min(hi - r0, static_cast<uint32_t>(ROUTE_THREADS));
+    if (tid < n) L.src[tid] = p.fired[r0 + tid];
     __syncthreads();
-    for (uint32_t w0 = 0; w0 < tot; w0 += ROUTE_STAGE) {
-      const uint32_t nwin = min(tot - w0, ROUTE_STAGE);
-      for (uint32_t i = tid; i < p.n_nodes; i += ROUTE_THREADS) l_cnt[i] = 0;
-      if (tid == 0) l_total = 0;
-      // the window's pairs into LDS
-      for (uint32_t i0 = 0; i0 < nwin; i0 += ROUTE_UNROLL * ROUTE_THREADS) {
-        uint32_t vp[ROUTE_UNROLL], kk[ROUTE_UNROLL];
-#pragma unroll
-        for (int v = 0; v < ROUTE_UNROLL; ++v) {
-          const uint32_t e = w0 + min(i0 + v * ROUTE_THREADS + tid, nwin - 1);
-          kk[v] = owner_of<ROUTE_THREADS / 2>(s_pre, nsrc, e);
-          vp[v] = p.vp_part[s_j0[kk[v]] + (e - s_pre[kk[v]])];
-        }
-#pragma unroll
-        for (int v = 0; v < ROUTE_UNROLL; ++v) {
-          const uint32_t i = i0 + v * ROUTE_THREADS + tid;
-          if (i < nwin) {
-            s_vp[i] = static_cast<uint16_t>(vp[v]);
-            s_k[i] = static_cast<uint16_t>(kk[v]);
-          }
-        }
-      }
-      __syncthreads();
-      // one message per run of equal node
-      for (uint32_t i = tid; i < nwin; i += ROUTE_THREADS) {
-        const uint32_t k = s_k[i];
-        const uint32_t off = w0 + i - s_pre[k];             // position in the source's list
-        const uint32_t len_k = s_pre[k + 1] - s_pre[k];
-        const uint32_t node = s_vp[i] / G;
-        if (off > 0) {
-          const uint32_t prev = i > 0 ? s_vp[i - 1] : p.vp_part[s_j0[k] + off - 1];
-          if (prev / G == node) continue;
-        }
-        uint32_t mask = 0;
-        for (uint32_t x = off; x < len_k; ++x) {
-          const uint32_t at = i + (x - off);
-          const uint32_t v = at < nwin ? s_vp[at] : p.vp_part[s_j0[k] + x];
-          if (v / G != node) break;
-          mask |= 1u << (v - G * node);
-        }
-        const uint64_t msg = (static_cast<uint64_t>(off) << 40) |
-                             (static_cast<uint64_t>(mask) << 32) | s_src[k];
-        const uint32_t slot = atomicAdd(&l_total, 1u);
-        const uint32_t rk = atomicAdd(&l_cnt[node], 1u);
-        s_msg[slot] = msg;
-        s_nr[slot] = node | (rk << 16);
-        s_mk[slot] = static_cast<uint16_t>(k);
-        if (node == s_own[k]) ++l1; else ++l2;
-      }
-      __syncthreads();
-      for (uint32_t n = tid; n < p.n_nodes; n += ROUTE_THREADS) {
-        const uint32_t c = l_cnt[n];
-        if (c) l_base[n] = atomicAdd(p.bucket_cnt + n * CNT_STRIDE, c);
-      }
-      __syncthreads();
-      // bucket bounds of ROUTE_UNROLL messages loaded together (clamped
-      // indices keep the loads unconditional), then the stores
-      const uint32_t n_msg = l_total;
-      for (uint32_t k0 = tid; k0 < n_msg; k0 += ROUTE_UNROLL * ROUTE_THREADS) {
-        uint64_t o[ROUTE_UNROLL], o1[ROUTE_UNROLL];
-#pragma unroll
-        for (int v = 0; v < ROUTE_UNROLL; ++v) {
-          const uint32_t node = s_nr[min(k0 + v * ROUTE_THREADS, n_msg - 1)] & 0xFFFFu;
-          o[v] = p.bucket_off[node];
-          o1[v] = p.bucket_off[node + 1];
-        }
-#pragma unroll
-        for (int v = 0; v < ROUTE_UNROLL; ++v) {
-          const uint32_t k = k0 + v * ROUTE_THREADS;
-          if (k >= n_msg) continue;
-          const uint32_t nr = s_nr[k];
-          const uint64_t pos = o[v] + l_base[nr & 0xFFFFu] + (nr >> 16);
-          if (pos < o1[v]) {
-            const uint64_t msg = s_msg[k];
-            p.bucket[2 * pos] = msg;
-            p.bucket[2 * pos + 1] = static_cast<uint64_t>(s_j0[s_mk[k]]) + (msg >> 40);
-          } else {
-            atomicOr(&p.st->error, ERR_BUCKET);
-          }
-        }
-      }
-      __syncthreads();
-    }
+    route_batch<ROUTE_THREADS, ROUTE_UNROLL>(p, L, n, bcnt, l1, l2);
   }
-  uint64_t* st = p.stats + static_cast<uint64_t>(row) * SNN_NSTAT;
+  uint64_t* st = stat_copy(p, row);
   add_stats(st + SNN_STAT_MSG_L1, l1, st + SNN_STAT_MSG_L2, l2, s_red);
 }
 
@@ -707,28 +842,29 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
 // not fit LDS: one wave per source, one atomic per message.
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level_direct(KParams p) {
   const uint32_t nF = p.st->n_fired;
-  const uint32_t row = p.st->cur_row;
+  uint32_t* bcnt = bucket_counts(p, p.st->cur_par);
+  const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t n_waves = gridDim.x * (ROUTE_THREADS / 64);
   uint64_t l1 = 0, l2 = 0;
   for (uint32_t i = blockIdx.x * (ROUTE_THREADS / 64) + (threadIdx.x >> 6); i < nF; i += n_waves) {
     const uint32_t s = p.fired[i];
-    const uint32_t own_node = static_cast<uint32_t>(p.part[s]) / p.G;
+    const uint32_t own_node = node_of(p, static_cast<uint32_t>(p.part[s]));
     const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
     for (int64_t jb = j0; jb < j1; jb += 64) {
       const int64_t j = jb + lane;
       if (j >= j1) continue;
-      const uint32_t node = p.vp_part[j] / p.G;
-      if (j != j0 && p.vp_part[j - 1] / p.G == node) continue;
+      const uint32_t node = node_of(p, p.vp_part[j]);
+      if (j != j0 && node_of(p, p.vp_part[j - 1]) == node) continue;
       const uint64_t msg = (static_cast<uint64_t>(j - j0) << 40) |
                            (static_cast<uint64_t>(node_mask(p, j, j1, node)) << 32) | s;
-      bucket_put(p, node, atomicAdd(p.bucket_cnt + node * CNT_STRIDE, 1u), msg,
+      bucket_put(p, node, atomicAdd(bcnt + node * CNT_STRIDE, 1u), msg,
                  static_cast<uint64_t>(j));
       if (node == own_node) ++l1; else ++l2;
     }
   }
   __shared__ uint64_t s_red[2 * (ROUTE_THREADS / 64)];
-  uint64_t* st = p.stats + static_cast<uint64_t>(row) * SNN_NSTAT;
+  uint64_t* st = stat_copy(p, row);
   add_stats(st + SNN_STAT_MSG_L1, l1, st + SNN_STAT_MSG_L2, l2, s_red);
 }
 
@@ -749,10 +885,10 @@ __global__ __launch_bounds__(EXPAND_THREADS) void k_expand(KParams p) {
   __shared__ uint64_t s_red[2 * NW];
   const uint32_t n = blockIdx.x;
   const uint32_t tid = threadIdx.x;
-  const uint32_t row = p.st->cur_row;
+  const uint32_t row = p.st->cur_srow;   // counter row
   const uint64_t off = p.bucket_off[n];
   const uint64_t cap = p.bucket_off[n + 1] - off;
-  const uint64_t cnt = min(static_cast<uint64_t>(p.bucket_cnt[n * CNT_STRIDE]), cap);
+  const uint64_t cnt = min(static_cast<uint64_t>(bucket_counts(p, p.st->cur_par)[n * CNT_STRIDE]), cap);
   const uint32_t gn = min(p.G, p.P - p.G * n);             // partitions of this node
   if (tid < SNN_MAX_GPUS_PER_NODE) l_run[tid] = 0;
   if (tid <= gn) l_off[tid] = p.recv_off[p.G * n + tid];
@@ -794,14 +930,14 @@ __global__ __launch_bounds__(EXPAND_THREADS) void k_expand(KParams p) {
   }
   __syncthreads();
   if (tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_RECV_ENTRIES, entries, s_red);
+  add_stat(stat_copy(p, row) + SNN_STAT_RECV_ENTRIES, entries, s_red);
 }
 
 // Flat (direct peer-to-peer) routing: one wave per fired source, one receive
 // entry (source, pair index) per destination partition.
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
   const uint32_t nF = p.st->n_fired;
-  const uint32_t row = p.st->cur_row;
+  const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t n_waves = gridDim.x * (ROUTE_THREADS / 64);
   uint64_t flat = 0;
@@ -820,7 +956,7 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
     }
   }
   __shared__ uint64_t s_red[2 * (ROUTE_THREADS / 64)];
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_FLAT_MSGS, flat, s_red);
+  add_stat(stat_copy(p, row) + SNN_STAT_FLAT_MSGS, flat, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -849,7 +985,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
   const uint32_t tid = threadIdx.x, b = blockIdx.x;
   const uint32_t md = p.D - 1;
   const uint32_t slot0 = p.st->cur_slot;
-  const uint32_t row = p.st->cur_row;
+  const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t ppb = (p.P + STAGE_BLOCKS - 1) / STAGE_BLOCKS;
   const uint32_t q0 = min(b * ppb, p.P), q1 = min(q0 + ppb, p.P);
   const uint32_t nq = q1 - q0;
@@ -955,7 +1091,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
   if (tid < md)
     p.stage_cnt[tid * STAGE_BLOCKS + b] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_REMOTE_EVENTS, events, s_red);
+  add_stat(stat_copy(p, row) + SNN_STAT_REMOTE_EVENTS, events, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -999,7 +1135,7 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   const uint32_t nF = p.st->n_fired;
   uint32_t slot = p.st->cur_slot + d;
   if (slot >= p.D) slot -= p.D;
-  const uint32_t row = p.st->cur_row;
+  const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t D = p.D;
   for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS) {
     l_run[i] = 0;
@@ -1131,7 +1267,7 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS)
     p.bin_cnt[subbin(p, slot, i, d, w)] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_run[i]), p.bin_cap));
-  add_stat(p.stats + static_cast<uint64_t>(row) * SNN_NSTAT + SNN_STAT_LOCAL_EVENTS, events, s_red);
+  add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
 }
 
 // Moves every pending binned event into the dense ring (for read-back) and
@@ -1176,27 +1312,34 @@ static inline void mark(hipEvent_t* marks, int kind, int end, hipStream_t s) {
   if (marks) (void)hipEventRecord(marks[2 * kind + end], s);
 }
 
-hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks) {
+bool fused_route_ok(const KParams& p) { return p.n_nodes <= FUSED_MAX_NODES; }
+
+hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks, bool route) {
   mark(marks, SNN_KERNEL_UPDATE, 0, s);
-  hipLaunchKernelGGL(k_update, dim3(p.n_tiles), dim3(UPDATE_THREADS), 0, s, p);
+  if (route && fused_route_ok(p))
+    hipLaunchKernelGGL(k_update<true>, dim3(p.n_tiles), dim3(UPDATE_THREADS), 0, s, p);
+  else
+    hipLaunchKernelGGL(k_update<false>, dim3(p.n_tiles), dim3(UPDATE_THREADS), 0, s, p);
   mark(marks, SNN_KERNEL_UPDATE, 1, s);
   return hipGetLastError();
 }
 
-size_t route_lds_bytes(const KParams& p) {
-  return ROUTE_STAGE * (sizeof(uint64_t) + sizeof(uint32_t) + 3 * sizeof(uint16_t)) +
-         2ull * p.n_nodes * sizeof(uint32_t);
+static size_t route_kernel_lds_bytes(const KParams& p) {
+  return route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, p.n_nodes);
 }
 
-hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks) {
+hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
+                        bool routed) {
   if (mode == SNN_ROUTE_TWO_LEVEL || mode == SNN_ROUTE_BOTH) {
-    mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 0, s);
-    if (p.n_nodes <= ROUTE_MAX_NODES_LDS)
-      hipLaunchKernelGGL(k_route_two_level, dim3(ROUTE_BLOCKS), dim3(ROUTE_THREADS),
-                         route_lds_bytes(p), s, p);
-    else
-      hipLaunchKernelGGL(k_route_two_level_direct, dim3(1024), dim3(ROUTE_THREADS), 0, s, p);
-    mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 1, s);
+    if (!routed) {
+      mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 0, s);
+      if (p.n_nodes <= ROUTE_MAX_NODES_LDS)
+        hipLaunchKernelGGL(k_route_two_level, dim3(ROUTE_BLOCKS), dim3(ROUTE_THREADS),
+                           route_kernel_lds_bytes(p), s, p);
+      else
+        hipLaunchKernelGGL(k_route_two_level_direct, dim3(1024), dim3(ROUTE_THREADS), 0, s, p);
+      mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 1, s);
+    }
     mark(marks, SNN_KERNEL_EXPAND, 0, s);
     hipLaunchKernelGGL(k_expand, dim3(p.n_nodes), dim3(EXPAND_THREADS), 0, s, p);
     mark(marks, SNN_KERNEL_EXPAND, 1, s);
@@ -1244,7 +1387,7 @@ hipError_t prepare_kernels(KParams& p) {
   if (p.dstage < DELIVER_THREADS) return hipErrorInvalidConfiguration;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_route_two_level),
                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                          static_cast<int>(route_lds_bytes(p)));
+                          static_cast<int>(route_kernel_lds_bytes(p)));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver),
                              hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -67,13 +67,13 @@ Layout layout(const snn_params* p) {
   L.st = take(sizeof(DevState));
   L.lookback = take(sizeof(uint64_t) * tiles);
   L.fired = take(sizeof(uint32_t) * uint64_t(p->n_neurons));
-  L.bucket_cnt = take(sizeof(uint32_t) * CNT_STRIDE * n_nodes_of(p));
+  L.bucket_cnt = take(2 * sizeof(uint32_t) * CNT_STRIDE * n_nodes_of(p));
   L.recv_cnt = take(sizeof(uint32_t) * CNT_STRIDE * p->n_partitions);
   L.flat_cnt = take(sizeof(uint32_t) * CNT_STRIDE * p->n_partitions);
   L.stage_cnt = take(sizeof(uint32_t) * md * STAGE_BLOCKS);
   L.bin_cnt = take(sizeof(uint32_t) * D * tiles * md * DELIVER_BLOCKS);
   L.dirty = take(sizeof(uint32_t) * D * tiles);
-  L.stats = take(sizeof(uint64_t) * SNN_NSTAT * uint64_t(p->log_steps));
+  L.stats = take(sizeof(uint64_t) * STAT_ROW_WORDS * (uint64_t(p->log_steps) + 1));
   L.pois_lut = take(POIS_LUT_SIZE);
   L.log_off = take(sizeof(uint64_t) * uint64_t(p->log_steps));
   // large buffers last: the region before them is zeroed at create
@@ -211,6 +211,8 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.N = params->n_neurons;
   k.P = params->n_partitions;
   k.G = params->gpus_per_node;
+  // node of partition v: v * ceil(2^32 / G) >> 32 for G >= 2 (exact for v < 2^16)
+  k.g_magic = k.G >= 2 ? static_cast<uint32_t>(((uint64_t(1) << 32) + k.G - 1) / k.G) : 0u;
   k.D = params->max_delay + 1;
   k.n_nodes = n_nodes_of(params);
   k.n_tiles = tiles_of(params->n_neurons);
@@ -321,6 +323,30 @@ snn_status snn_route(snn_handle h, int mode) {
   return SNN_OK;
 }
 
+snn_status snn_step_route(snn_handle h, int mode) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  if (mode < SNN_ROUTE_TWO_LEVEL || mode > SNN_ROUTE_BOTH)
+    return fail(SNN_ERR_INVALID_ARG, "route mode %d", mode);
+  if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_step_route called before snn_deliver");
+  const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(h->kp);
+  HIP_TRY(launch_update(h->kp, h->stream, nullptr, fused));
+  HIP_TRY(launch_route(h->kp, mode, h->stream, nullptr, fused));
+  h->route_mode = mode;
+  h->phase = 2;
+  h->routed_t = h->t_host + 1;
+  return SNN_OK;
+}
+
+// One whole step in route mode `mode`, two-level routing inside the update
+// kernel where the node count allows.
+static hipError_t launch_step(const KParams& kp, int mode, hipStream_t s, hipEvent_t* marks) {
+  const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(kp);
+  hipError_t e = launch_update(kp, s, marks, fused);
+  if (e == hipSuccess) e = launch_route(kp, mode, s, marks, fused);
+  if (e == hipSuccess) e = launch_deliver(kp, mode, s, marks);
+  return e;
+}
+
 snn_status snn_deliver(snn_handle h) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
   if (h->phase != 2) return fail(SNN_ERR_BAD_STATE, "snn_deliver must follow snn_route");
@@ -338,11 +364,7 @@ static snn_status ensure_graph(snn_handle h, int mode, int which) {
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (uint32_t i = 0; i < steps && e == hipSuccess; ++i) {
-    e = launch_update(h->kp, h->stream);
-    if (e == hipSuccess) e = launch_route(h->kp, mode, h->stream);
-    if (e == hipSuccess) e = launch_deliver(h->kp, mode, h->stream);
-  }
+  for (uint32_t i = 0; i < steps && e == hipSuccess; ++i) e = launch_step(h->kp, mode, h->stream, nullptr);
   hipError_t ec = hipStreamEndCapture(h->stream, &g);
   if (e != hipSuccess || ec != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -365,11 +387,7 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
   if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_run called in the middle of a step");
   if (n_steps == 0) return SNN_OK;
   if (!use_graph) {
-    for (uint32_t i = 0; i < n_steps; ++i) {
-      HIP_TRY(launch_update(h->kp, h->stream));
-      HIP_TRY(launch_route(h->kp, mode, h->stream));
-      HIP_TRY(launch_deliver(h->kp, mode, h->stream));
-    }
+    for (uint32_t i = 0; i < n_steps; ++i) HIP_TRY(launch_step(h->kp, mode, h->stream, nullptr));
   } else {
     const uint32_t n_long = n_steps / GRAPH_STEPS, n_short = n_steps % GRAPH_STEPS;
     if (n_long) {
@@ -399,8 +417,13 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
   // Every step gets its own events and nothing synchronises until the end:
   // the launches queue up behind each other as in a normal run, so no start
   // event fires on an idle queue ahead of its kernel.
-  const bool launched[SNN_NKERNEL] = {
-      true, mode != SNN_ROUTE_FLAT, mode != SNN_ROUTE_FLAT, mode != SNN_ROUTE_TWO_LEVEL, true, true};
+  const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(h->kp);
+  const bool launched[SNN_NKERNEL] = {true,
+                                      mode != SNN_ROUTE_FLAT && !fused,
+                                      mode != SNN_ROUTE_FLAT,
+                                      mode != SNN_ROUTE_TWO_LEVEL,
+                                      true,
+                                      true};
   std::vector<hipEvent_t> marks(size_t(2) * SNN_NKERNEL * n_steps, nullptr);
   snn_status st = SNN_OK;
   for (auto& e : marks) {
@@ -413,9 +436,7 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
   double total[SNN_NKERNEL] = {};
   for (uint32_t i = 0; i < n_steps && st == SNN_OK; ++i) {
     hipEvent_t* m = marks.data() + size_t(2) * SNN_NKERNEL * i;
-    hipError_t r = launch_update(h->kp, h->stream, m);
-    if (r == hipSuccess) r = launch_route(h->kp, mode, h->stream, m);
-    if (r == hipSuccess) r = launch_deliver(h->kp, mode, h->stream, m);
+    hipError_t r = launch_step(h->kp, mode, h->stream, m);
     if (r != hipSuccess) st = fail(SNN_ERR_HIP, "timed step: %s", hipGetErrorString(r));
     h->t_host += 1;
     h->route_mode = mode;
@@ -493,11 +514,16 @@ snn_status snn_read_counters(snn_handle h, uint64_t first_step, uint32_t n_steps
   if (n_steps > L) return fail(SNN_ERR_INVALID_ARG, "n_steps exceeds log_steps");
   snn_status s = sync_and_check(h, nullptr);
   if (s != SNN_OK && s != SNN_ERR_CAPACITY) return s;
-  std::vector<uint64_t> all(SNN_NSTAT * L);
+  std::vector<uint64_t> all(STAT_ROW_WORDS * (L + 1));
   HIP_TRY(hipMemcpy(all.data(), h->kp.stats, all.size() * 8, hipMemcpyDeviceToHost));
-  for (uint32_t i = 0; i < n_steps; ++i)
-    std::memcpy(out + uint64_t(i) * SNN_NSTAT, all.data() + ((first_step + i) % L) * SNN_NSTAT,
-                SNN_NSTAT * 8);
+  for (uint32_t i = 0; i < n_steps; ++i) {
+    const uint64_t* row = all.data() + ((first_step + i) % (L + 1)) * STAT_ROW_WORDS;
+    for (uint32_t k = 0; k < SNN_NSTAT; ++k) {
+      uint64_t v = 0;
+      for (uint32_t c = 0; c < STAT_LANES; ++c) v += row[c * STAT_LANE_WORDS + k];
+      out[uint64_t(i) * SNN_NSTAT + k] = v;
+    }
+  }
   return s;
 }
 
@@ -513,14 +539,14 @@ snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps, 
   HIP_TRY(hipStreamSynchronize(h->stream));
   DevState st;
   HIP_TRY(hipMemcpy(&st, h->kp.st, sizeof(st), hipMemcpyDeviceToHost));
-  std::vector<uint64_t> stats(SNN_NSTAT * L), offs(L);
+  std::vector<uint64_t> stats(STAT_ROW_WORDS * (L + 1)), offs(L);
   HIP_TRY(hipMemcpy(stats.data(), h->kp.stats, stats.size() * 8, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(offs.data(), h->kp.log_off, offs.size() * 8, hipMemcpyDeviceToHost));
   const uint64_t logcap = h->prm.log_cap;
   uint64_t total = 0;
   for (uint32_t i = 0; i < n_steps; ++i) {
     const uint64_t r = (first_step + i) % L;
-    const uint64_t cnt = stats[r * SNN_NSTAT + SNN_STAT_SPIKES];
+    const uint64_t cnt = stats[((first_step + i) % (L + 1)) * STAT_ROW_WORDS + SNN_STAT_SPIKES];
     if (per_step_counts) per_step_counts[i] = uint32_t(cnt);
     // still in the log ring?
     if (cnt && (logcap == 0 || st.log_total - offs[r] > logcap))
@@ -535,7 +561,7 @@ snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps, 
   uint64_t at = 0;
   for (uint32_t i = 0; i < n_steps; ++i) {
     const uint64_t r = (first_step + i) % L;
-    uint64_t cnt = stats[r * SNN_NSTAT + SNN_STAT_SPIKES];
+    uint64_t cnt = stats[((first_step + i) % (L + 1)) * STAT_ROW_WORDS + SNN_STAT_SPIKES];
     if (!cnt) continue;
     uint64_t pos = offs[r] % logcap;
     while (cnt) {
@@ -557,12 +583,15 @@ snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entri
   const int mode = h->route_mode;
   if ((which == 0 && mode == SNN_ROUTE_TWO_LEVEL) || (which != 0 && mode == SNN_ROUTE_FLAT))
     return fail(SNN_ERR_BAD_STATE, "the last step was not routed in a mode that fills these buffers");
-  snn_status s = sync_and_check(h, nullptr);
+  DevState dst;
+  snn_status s = sync_and_check(h, &dst);
   if (s != SNN_OK) return s;
   const uint32_t nl = which == 2 ? h->kp.n_nodes : h->kp.P;
   std::vector<uint32_t> cnt(uint64_t(nl) * CNT_STRIDE);
   std::vector<uint64_t> off(nl + 1);
-  const uint32_t* cnt_dev = which == 0 ? h->kp.flat_cnt : which == 1 ? h->kp.recv_cnt : h->kp.bucket_cnt;
+  const uint32_t* cnt_dev = which == 0   ? h->kp.flat_cnt
+                            : which == 1 ? h->kp.recv_cnt
+                                         : h->kp.bucket_cnt + uint64_t(dst.cur_par) * nl * CNT_STRIDE;
   const uint64_t* off_dev = which == 2 ? h->kp.bucket_off : h->kp.recv_off;
   HIP_TRY(hipMemcpy(cnt.data(), cnt_dev, cnt.size() * 4, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(off.data(), off_dev, (nl + 1) * 8, hipMemcpyDeviceToHost));

@@ -107,6 +107,10 @@ class Simulation:
     def route(self, mode=_abi.SNN_ROUTE_TWO_LEVEL):
         _abi.snn_route(self.h, mode)
 
+    def step_route(self, mode=_abi.SNN_ROUTE_TWO_LEVEL):
+        """snn_step_route: update and routing of one step in fewer launches."""
+        _abi.snn_step_route(self.h, mode)
+
     def deliver(self):
         _abi.snn_deliver(self.h)
 

@@ -38,40 +38,53 @@ def _same_state(sim, orc, where):
     return g, o
 
 
-def _same_routes(sim, orc, wl, where):
-    flat_e, x_e, b_g = sim.read_routes(0), sim.read_routes(1), sim.read_routes(2)
-    flat_o, x_o, b_o = orc.recv(0), orc.recv(1), orc.buckets()
+def _same_routes(sim, orc, wl, where, mode=ROUTE_BOTH):
+    """The buffers the route mode fills: flat lists (flat, both), expanded
+    lists and node buckets (two-level, both)."""
+    flat = mode != ROUTE_TWO_LEVEL
+    two = mode != ROUTE_FLAT
     src_mask = np.uint64((1 << ENTRY_SRC_BITS) - 1)
     host = sim.host
-    for p in range(wl.n_partitions):
-        fg = (flat_e[p] & src_mask).astype(np.uint32)
-        xg = (x_e[p] & src_mask).astype(np.uint32)
-        assert np.array_equal(np.sort(fg), np.sort(flat_o[p])), f"flat {p} at {where}"
-        assert np.array_equal(np.sort(xg), np.sort(x_o[p])), f"expanded {p} at {where}"
-        # the pair index each entry carries belongs to its source and names p
-        for ent in (flat_e[p], x_e[p]):
-            if len(ent) and host is not None:
-                s = (ent & src_mask).astype(np.int64)
-                j = (ent >> np.uint64(ENTRY_SRC_BITS)).astype(np.int64)
+    lists = []
+    if flat:
+        lists.append(("flat", sim.read_routes(0), orc.recv(0)))
+    if two:
+        lists.append(("expanded", sim.read_routes(1), orc.recv(1)))
+    for kind, got, want in lists:
+        for p in range(wl.n_partitions):
+            g = (got[p] & src_mask).astype(np.uint32)
+            assert np.array_equal(np.sort(g), np.sort(want[p])), f"{kind} {p} at {where}"
+            # the pair index each entry carries belongs to its source and names p
+            if len(got[p]) and host is not None:
+                s = (got[p] & src_mask).astype(np.int64)
+                j = (got[p] >> np.uint64(ENTRY_SRC_BITS)).astype(np.int64)
                 assert np.all(j >= host.vp_ptr[s]) and np.all(j < host.vp_ptr[s + 1])
                 assert np.all(host.vp_part[j] == p)
-    for n in range(wl.n_nodes):
-        # device messages carry the first destination's list index above bit 40
-        g = np.sort(b_g[n] & np.uint64((1 << 40) - 1))
-        assert np.array_equal(g, np.sort(b_o[n])), f"bucket {n} at {where}"
+    if two:
+        b_g, b_o = sim.read_routes(2), orc.buckets()
+        for n in range(wl.n_nodes):
+            # device messages carry the first destination's list index above bit 40
+            g = np.sort(b_g[n] & np.uint64((1 << 40) - 1))
+            assert np.array_equal(g, np.sort(b_o[n])), f"bucket {n} at {where}"
 
 
-def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH):
+def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH, fused=False):
+    """fused: each step as snn_step_route + snn_deliver (two-level routing in
+    the update kernel) instead of snn_step, snn_route, snn_deliver."""
     sim, orc = _pair(wl, log_steps=n_steps)
     stats_o = np.zeros((n_steps, 7), np.uint64)
     fired_o = []
     for t in range(n_steps):
-        sim.full_step(mode)
+        if fused:
+            sim.step_route(mode)
+            sim.deliver()
+        else:
+            sim.full_step(mode)
         orc.step()
         fired_o.append(orc.fired())
         stats_o[t] = orc.counters()[STAT_MAP]
         if route_every and t % route_every == 0:
-            _same_routes(sim, orc, wl, f"step {t}")
+            _same_routes(sim, orc, wl, f"step {t}", mode)
         if state_every and (t + 1) % state_every == 0:
             _same_state(sim, orc, f"after step {t}")
     ids, counts = sim.read_spikes(0, n_steps)
@@ -101,6 +114,32 @@ def test_tiny_lockstep_1000_steps(name, seed):
     spikes = int(stats[:, 0].sum())
     print(f"[gpu] {name} seed {seed}: {spikes} spikes", flush=True)
     assert spikes > (10_000 if name == "tiny_active" else 100)
+
+
+@pytest.mark.parametrize("mode", [ROUTE_TWO_LEVEL, ROUTE_BOTH])
+@pytest.mark.parametrize("name", ["tiny", "tiny_active"])
+def test_fused_route_lockstep(name, mode):
+    """snn_step_route (two-level routing inside the update kernel) against the
+    oracle: the same buckets, lists, counters and state."""
+    wl = synth.get_workload(name).replace(seed=4)
+    _lockstep(wl, 300, route_every=10, state_every=50, mode=mode, fused=True)
+
+
+def test_fused_route_many_spikes_per_tile():
+    """More fired neurons in one tile than a routing batch holds (512) and more
+    pairs than a window (1,024): the batch and window loops of the fused
+    routing, and runs of one node cut by a window's end."""
+    wl = synth.get_workload("tiny").replace(name="tiny_dense", forced=1, rate_on_hz=2000.0,
+                                            rate_off_hz=2000.0, period_steps=1, on_steps=1)
+    _, _, stats = _lockstep(wl, 40, route_every=1, state_every=10, mode=ROUTE_BOTH, fused=True)
+    assert stats[:, 0].max() > 512      # one tile: two routing batches
+
+
+def test_unfused_fallback_many_nodes():
+    """2,000 nodes of one GPU: more than the fused routing's LDS counters hold,
+    so snn_step_route falls back to the routing kernel."""
+    wl = synth.get_workload("paper_share").scaled(20_000, gpus_per_node=1)
+    _lockstep(wl, 40, route_every=5, state_every=20, mode=ROUTE_TWO_LEVEL, fused=True)
 
 
 def test_route_modes_give_identical_rasters():
