@@ -234,10 +234,11 @@ snn_status snn_route(snn_handle h, int mode);
 /* snn_step followed by snn_route(mode), in fewer launches: for the two-level
    modes the update kernel routes each tile's fired neurons itself (Sec. IV-B
    messages into the node buckets) while it waits for the spike-count prefix
-   of the tiles before it; with more than 1,024 nodes the two calls are made
+   of the tiles before it; with more than 512 nodes the two calls are made
    as they are.  The buckets hold the same messages as after snn_route (their
-   order within a bucket may differ).  Order: as snn_step; snn_deliver
-   follows. */
+   order within a bucket may differ); the mask expansion into the receive
+   lists is left to snn_deliver, which expands and stages in one kernel.
+   Order: as snn_step; snn_deliver follows. */
 snn_status snn_step_route(snn_handle h, int mode);
 
 /* Delivers the current step's synaptic events (own partition and receive

@@ -54,9 +54,9 @@ constexpr int UPDATE_NPT = TILE / UPDATE_THREADS;   // 16 neurons per thread
 constexpr int ROUTE_THREADS = 256;
 constexpr int DELIVER_THREADS = 512;
 constexpr uint32_t CNT_STRIDE = 16;                 // counters padded to 64 bytes
-constexpr uint32_t ROUTE_STAGE = 4096;              // staged messages / entries per round
+constexpr uint32_t ROUTE_STAGE = 2048;              // pairs per routing window
 constexpr uint32_t ROUTE_BLOCKS = 256;              // two-level routing blocks
-constexpr uint32_t ROUTE_MAX_NODES_LDS = 8192;      // more nodes: unstaged routing
+constexpr uint32_t ROUTE_MAX_NODES_LDS = 4096;      // more nodes: unstaged routing
 constexpr int EXPAND_THREADS = 512;                 // one expansion block per node
 constexpr uint32_t DELIVER_STAGE = 4096;            // staged events per window, at most
 constexpr uint32_t DELIVER_BLOCKS = 32;             // deliver blocks per delay
@@ -68,6 +68,9 @@ constexpr int RECV_THREADS = 512;
 constexpr uint32_t RECV_PER_THREAD = 4;                         // entries per thread per batch
 constexpr uint32_t RECV_BATCH = RECV_THREADS * RECV_PER_THREAD; // entries per batch
 static_assert(STAGE_PARTS <= RECV_THREADS, "one partition count per thread");
+constexpr uint32_t EXPAND_BUF = 4096;               // receive entries buffered per staging pass
+constexpr uint32_t EXPAND_PER_THREAD = 4;           // messages per thread per expansion round
+static_assert(EXPAND_BUF >= SNN_MAX_GPUS_PER_NODE, "one message's entries fit the buffer");
 
 // Per-step counters: each row (step mod (log_steps + 1); the spare row is the
 // next step's, cleared by the update kernel ahead of its use) holds STAT_LANES copies of
@@ -177,9 +180,12 @@ hipError_t prepare_kernels(KParams& p);   // LDS sizing (sets dstage), once per 
 bool fused_route_ok(const KParams& p);
 hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks = nullptr,
                          bool route = false);
+// With defer_expand, launch_route leaves the mask expansion to launch_deliver
+// (fused_expand), which then expands and stages in one kernel.
 hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr,
-                        bool routed = false);
-hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr);
+                        bool routed = false, bool defer_expand = false);
+hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr,
+                          bool fused_expand = false);
 hipError_t launch_flush(const KParams& p, hipStream_t s);
 
 }  // namespace snn

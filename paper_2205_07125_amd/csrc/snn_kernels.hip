@@ -200,7 +200,7 @@ constexpr int ROUTE_UNROLL = 8;           // destination-list loads in flight pe
 // block): window of pairs, and the node count up to which its counters fit
 // the LDS the update leaves free.
 constexpr uint32_t FUSED_ROUTE_WINDOW = 1024;
-constexpr uint32_t FUSED_MAX_NODES = 1024;
+constexpr uint32_t FUSED_MAX_NODES = 512;
 constexpr int FUSED_ROUTE_UNROLL = FUSED_ROUTE_WINDOW / UPDATE_THREADS;   // one load round per window
 
 // ---------------------------------------------------------------------------
@@ -254,12 +254,13 @@ __device__ __forceinline__ uint32_t* bucket_counts(const KParams& p, uint32_t pa
 struct RouteLds {
   int64_t* j0;     // [NT] first pair index of each source
   uint64_t* msg;   // [W] staged messages
+  uint64_t* base;  // [n_nodes] start reserved for the window's messages in each bucket
+  uint64_t* end;   // [n_nodes] end of each bucket
   uint32_t* pre;   // [NT + 1] list starts in the concatenation of the batch's lists
   uint32_t* src;   // [NT] source ids of the batch
-  uint32_t* own;   // [NT] node of each source
   uint32_t* nr;    // [W] node | rank among the window's messages to that node << 16
   uint32_t* cnt;   // [n_nodes] messages of the window per node
-  uint32_t* base;  // [n_nodes] their reserved start in the node's bucket
+  uint16_t* own;   // [NT] node of each source
   uint16_t* nb;    // [W] node << 3 | bit of each pair's partition in the node
   uint16_t* pk;    // [W] batch index of each pair's source
   uint16_t* off;   // [W] position of each pair in its source's list
@@ -268,8 +269,8 @@ struct RouteLds {
 };
 
 __host__ __device__ constexpr size_t route_lds_bytes(uint32_t nt, uint32_t w, uint32_t n_nodes) {
-  return size_t(nt) * 8 + size_t(w) * 8 + (size_t(nt) + 2) * 4 + size_t(nt) * 8 + size_t(w) * 4 +
-         size_t(n_nodes) * 8 + size_t(w) * 8;
+  return 8 * (size_t(nt) + w + 2 * size_t(n_nodes)) + 4 * (2 * size_t(nt) + 1 + w + n_nodes) +
+         2 * (size_t(nt) + 4 * size_t(w));
 }
 
 __device__ RouteLds route_lds(void* lds, uint32_t nt, uint32_t w, uint32_t n_nodes) {
@@ -277,12 +278,13 @@ __device__ RouteLds route_lds(void* lds, uint32_t nt, uint32_t w, uint32_t n_nod
   char* c = static_cast<char*>(lds);
   L.j0 = reinterpret_cast<int64_t*>(c);                  c += size_t(nt) * 8;
   L.msg = reinterpret_cast<uint64_t*>(c);                c += size_t(w) * 8;
-  L.pre = reinterpret_cast<uint32_t*>(c);                c += (size_t(nt) + 2) * 4;
+  L.base = reinterpret_cast<uint64_t*>(c);               c += size_t(n_nodes) * 8;
+  L.end = reinterpret_cast<uint64_t*>(c);                c += size_t(n_nodes) * 8;
+  L.pre = reinterpret_cast<uint32_t*>(c);                c += (size_t(nt) + 1) * 4;
   L.src = reinterpret_cast<uint32_t*>(c);                c += size_t(nt) * 4;
-  L.own = reinterpret_cast<uint32_t*>(c);                c += size_t(nt) * 4;
   L.nr = reinterpret_cast<uint32_t*>(c);                 c += size_t(w) * 4;
   L.cnt = reinterpret_cast<uint32_t*>(c);                c += size_t(n_nodes) * 4;
-  L.base = reinterpret_cast<uint32_t*>(c);               c += size_t(n_nodes) * 4;
+  L.own = reinterpret_cast<uint16_t*>(c);                c += size_t(nt) * 2;
   L.nb = reinterpret_cast<uint16_t*>(c);                 c += size_t(w) * 2;
   L.pk = reinterpret_cast<uint16_t*>(c);                 c += size_t(w) * 2;
   L.off = reinterpret_cast<uint16_t*>(c);                c += size_t(w) * 2;
@@ -316,7 +318,7 @@ __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uin
   if (tid < n) {
     const uint32_t s = L.src[tid];
     const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
-    L.own[tid] = node_of(p, static_cast<uint32_t>(p.part[s]));
+    L.own[tid] = static_cast<uint16_t>(node_of(p, static_cast<uint32_t>(p.part[s])));
     L.j0[tid] = j0;
     len = static_cast<uint32_t>(j1 - j0);
   }
@@ -392,35 +394,27 @@ __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uin
       if (node == L.own[k]) ++l1; else ++l2;
     }
     __syncthreads();
+    // reservations, with the bucket bounds loaded alongside (same round trip)
     for (uint32_t nn = tid; nn < p.n_nodes; nn += NT) {
       const uint32_t c = L.cnt[nn];
-      if (c) L.base[nn] = atomicAdd(bcnt + nn * CNT_STRIDE, c);
+      if (c) {
+        const uint64_t o = p.bucket_off[nn], o1 = p.bucket_off[nn + 1];
+        L.base[nn] = o + atomicAdd(bcnt + nn * CNT_STRIDE, c);
+        L.end[nn] = o1;
+      }
     }
     __syncthreads();
-    // bucket bounds of U messages loaded together (clamped
-    // indices keep the loads unconditional), then the stores
     const uint32_t n_msg = l_total;
-    for (uint32_t k0 = tid; k0 < n_msg; k0 += U * NT) {
-      uint64_t o[U], o1[U];
-#pragma unroll
-      for (int v = 0; v < U; ++v) {
-        const uint32_t node = L.nr[min(k0 + v * NT, n_msg - 1)] & 0xFFFFu;
-        o[v] = p.bucket_off[node];
-        o1[v] = p.bucket_off[node + 1];
-      }
-#pragma unroll
-      for (int v = 0; v < U; ++v) {
-        const uint32_t k = k0 + v * NT;
-        if (k >= n_msg) continue;
-        const uint32_t nr = L.nr[k];
-        const uint64_t pos = o[v] + L.base[nr & 0xFFFFu] + (nr >> 16);
-        if (pos < o1[v]) {
-          const uint64_t msg = L.msg[k];
-          p.bucket[2 * pos] = msg;
-          p.bucket[2 * pos + 1] = static_cast<uint64_t>(L.j0[L.mk[k]]) + (msg >> 40);
-        } else {
-          atomicOr(&p.st->error, ERR_BUCKET);
-        }
+    for (uint32_t k = tid; k < n_msg; k += NT) {
+      const uint32_t nr = L.nr[k];
+      const uint32_t node = nr & 0xFFFFu;
+      const uint64_t pos = L.base[node] + (nr >> 16);
+      if (pos < L.end[node]) {
+        const uint64_t msg = L.msg[k];
+        p.bucket[2 * pos] = msg;
+        p.bucket[2 * pos + 1] = static_cast<uint64_t>(L.j0[L.mk[k]]) + (msg >> 40);
+      } else {
+        atomicOr(&p.st->error, ERR_BUCKET);
       }
     }
     __syncthreads();
@@ -814,6 +808,11 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   }
 }
 
+static_assert(route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, ROUTE_MAX_NODES_LDS) <= 150u * 1024u,
+              "the routing kernel's arrays fit a CU's LDS");
+static_assert(ROUTE_STAGE <= 65536 && ROUTE_MAX_NODES_LDS <= 8192,
+              "ranks and nodes fit their 16-bit fields");
+
 // Two-level routing as a kernel of its own: block b routes a contiguous chunk
 // of the step's fired sources, ROUTE_THREADS at a time (route_batch).
 // Dynamic LDS: route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, n_nodes).
@@ -962,29 +961,121 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_flat(KParams p) {
 // ---------------------------------------------------------------------------
 // receive side: stage remote synapses per delay
 
-// Block b of STAGE_BLOCKS owns a contiguous range of partitions and their
-// receive lists.  An entry (s, j) names the receive record of pair j: the row
-// segment of s going to this partition, with its first synapse inline.  Each
-// synapse goes to the block's own queue for its delay (positions from
-// per-delay LDS counters; no global atomics: the queues belong to the block).
-// Entries are taken in batches of RECV_BATCH, RECV_PER_THREAD per thread, so
-// that their two dependent loads (entry, record) are in flight together; the
-// first synapse of every segment comes from the record, and the rest of the
-// longer segments are concatenated by a block scan and loaded as one flat
-// sequence.
+// A receive-side block's per-delay staging queues and the LDS it stages with.
+struct StageCtx {
+  Event* queue;        // queue of delay 1 of this block; delay d at + (d - 1) * qstride
+  uint64_t qstride;
+  uint32_t slot0;      // ring slot of the step in flight
+  uint32_t* l_pos;     // [SNN_MAX_DELAY] events queued per delay
+  uint64_t* s_seg;     // [RECV_BATCH] second synapse of each entry's segment
+  uint32_t* s_epre;    // [RECV_BATCH] remaining synapses: starts in the concatenation
+  uint32_t* s_wsum;    // [RECV_THREADS / 64]
+};
+
+// One synapse (tgt_delay, weight) into the queue of its delay (position from
+// an LDS counter; the queue belongs to the block), or into the dense ring
+// when the queue is full.
+__device__ __forceinline__ void stage_emit(const KParams& p, const StageCtx& c, uint32_t td,
+                                           float w) {
+  const uint32_t d1 = (td >> 27) - 1;
+  if (d1 >= p.D - 1) {                       // delay outside [1, max_delay]
+    atomicOr(&p.st->error, ERR_ROUTE);
+    return;
+  }
+  const Event ev{td & 0x07FFFFFFu, quantize_w(p, w)};
+  const uint32_t pos = atomicAdd(&c.l_pos[d1], 1u);
+  if (pos < p.stage_cap) {
+    c.queue[d1 * c.qstride + pos] = ev;
+  } else {
+    uint32_t slot = c.slot0 + d1 + 1;
+    if (slot >= p.D) slot -= p.D;
+    ring_fallback(p, slot, ev.tgt, ev.wq);
+  }
+}
+
+// Stages the synapses of nb <= RECV_BATCH receive entries, RECV_PER_THREAD
+// per thread in ent (entry tid * R + v; lanes past nb hold a valid entry and
+// contribute nothing).  An entry (s, j) names the receive record of pair j:
+// the row segment of s going to the entry's partition, with its first synapse
+// inline.  The two dependent loads (entry, record) of all entries are in
+// flight together; the first synapse of every segment comes from the record,
+// and the rest of the longer segments are concatenated by a block scan and
+// loaded as one flat sequence, GATHER_UNROLL loads in flight per thread.
+// Every thread calls it; it ends with a barrier.
+__device__ void stage_batch(const KParams& p, const StageCtx& c, const uint64_t* ent, uint32_t nb,
+                            uint64_t& events) {
+  constexpr uint32_t R = RECV_PER_THREAD;
+  const uint32_t tid = threadIdx.x;
+  uint64_t rec0[R], rec1[R];
+#pragma unroll
+  for (int v = 0; v < R; ++v) {
+    const uint64_t j = ent[v] >> ENTRY_SRC_BITS;
+    const uint64_t jc = j < p.n_pairs ? j : 0;   // entries exist, so pair 0 does
+    rec0[v] = p.vp_rec[2 * jc];
+    rec1[v] = p.vp_rec[2 * jc + 1];
+  }
+  uint32_t len[R];
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int v = 0; v < R; ++v) {
+    const bool in = tid * R + v < nb;
+    const uint64_t start = rec0[v] & ((uint64_t(1) << 40) - 1);
+    const uint32_t seg_len = static_cast<uint32_t>(rec0[v] >> 40);
+    const bool ok = (ent[v] & ENTRY_SRC_MASK) < p.N && (ent[v] >> ENTRY_SRC_BITS) < p.n_pairs &&
+                    seg_len >= 1 && start + seg_len <= p.nnz;
+    if (in && !ok) atomicOr(&p.st->error, ERR_ROUTE);
+    if (in && ok) {
+      const uint32_t wbits = static_cast<uint32_t>(rec1[v] >> 32);
+      stage_emit(p, c, static_cast<uint32_t>(rec1[v]),
+                 p.bf16 ? __uint_as_float(wbits << 16) : __uint_as_float(wbits));
+      events += seg_len;
+    }
+    c.s_seg[tid * R + v] = start + 1;
+    len[v] = in && ok ? seg_len - 1 : 0u;
+    tsum += len[v];
+  }
+  uint32_t T;
+  uint32_t run = block_excl_scan(tsum, c.s_wsum, &T);
+#pragma unroll
+  for (int v = 0; v < R; ++v) {
+    c.s_epre[tid * R + v] = run;
+    run += len[v];
+  }
+  __syncthreads();
+  // the remaining synapses of longer segments
+  for (uint32_t e0 = 0; e0 < T; e0 += GATHER_UNROLL * RECV_THREADS) {
+    uint32_t td[GATHER_UNROLL];
+    float wt[GATHER_UNROLL];
+#pragma unroll
+    for (int v = 0; v < GATHER_UNROLL; ++v) {
+      const uint32_t e = min(e0 + v * RECV_THREADS + tid, T - 1);
+      const uint32_t k = owner_of<RECV_BATCH / 2>(c.s_epre, nb, e);
+      const uint64_t x = c.s_seg[k] + (e - c.s_epre[k]);
+      td[v] = p.tgt_delay[x];
+      wt[v] = load_weight(p, x);
+    }
+#pragma unroll
+    for (int v = 0; v < GATHER_UNROLL; ++v)
+      if (e0 + v * RECV_THREADS + tid < T) stage_emit(p, c, td[v], wt[v]);
+  }
+  __syncthreads();
+}
+
+// Receive lists -> staging queues.  Block b of STAGE_BLOCKS owns a contiguous
+// range of partitions and their receive lists (expanded or flat), taken in
+// batches of RECV_BATCH entries (stage_batch).
 __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_flat) {
   constexpr uint32_t NW = RECV_THREADS / 64;
   constexpr uint32_t R = RECV_PER_THREAD;
   __shared__ uint32_t s_ppre[RECV_THREADS];     // entry starts of the block's partitions
   __shared__ uint64_t s_roff[RECV_THREADS];     // list offsets of the block's partitions
-  __shared__ uint64_t s_seg[RECV_BATCH];        // second synapse of each entry's segment
-  __shared__ uint32_t s_epre[RECV_BATCH];       // remaining synapses: starts in the concatenation
+  __shared__ uint64_t s_seg[RECV_BATCH];
+  __shared__ uint32_t s_epre[RECV_BATCH];
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
   __shared__ uint32_t l_pos[SNN_MAX_DELAY];
   const uint32_t tid = threadIdx.x, b = blockIdx.x;
   const uint32_t md = p.D - 1;
-  const uint32_t slot0 = p.st->cur_slot;
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t ppb = (p.P + STAGE_BLOCKS - 1) / STAGE_BLOCKS;
   const uint32_t q0 = min(b * ppb, p.P), q1 = min(q0 + ppb, p.P);
@@ -1001,32 +1092,12 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
   uint32_t n_ent;
   s_ppre[tid] = block_excl_scan(c, s_wsum, &n_ent);
   __syncthreads();
-  Event* queue = p.stage + static_cast<uint64_t>(b) * p.stage_cap;  // + (d-1)*STAGE_BLOCKS*cap
-  const uint64_t qstride = static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap;
+  const StageCtx ctx{p.stage + static_cast<uint64_t>(b) * p.stage_cap,
+                     static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap, p.st->cur_slot, l_pos,
+                     s_seg, s_epre, s_wsum};
   uint64_t events = 0;
-
-  // one synapse (tgt_delay, weight) into the queue of its delay
-  auto emit = [&](uint32_t td, float w) {
-    const uint32_t d1 = (td >> 27) - 1;
-    if (d1 >= md) {                            // delay outside [1, max_delay]
-      atomicOr(&p.st->error, ERR_ROUTE);
-      return;
-    }
-    const Event ev{td & 0x07FFFFFFu, quantize_w(p, w)};
-    const uint32_t pos = atomicAdd(&l_pos[d1], 1u);
-    if (pos < p.stage_cap) {
-      queue[d1 * qstride + pos] = ev;
-    } else {
-      uint32_t slot = slot0 + d1 + 1;
-      if (slot >= p.D) slot -= p.D;
-      ring_fallback(p, slot, ev.tgt, ev.wq);
-    }
-  };
-
   for (uint32_t b0 = 0; b0 < n_ent; b0 += RECV_BATCH) {
     const uint32_t nb = min(n_ent - b0, RECV_BATCH);
-    // entries tid * R + v of the batch; past the end a lane repeats the last
-    // entry (valid addresses) and contributes no synapses
     uint64_t ent[R];
 #pragma unroll
     for (int v = 0; v < R; ++v) {
@@ -1034,64 +1105,140 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
       const uint32_t k = owner_of<STAGE_PARTS / 2>(s_ppre, nq, e);
       ent[v] = lists[s_roff[k] + (e - s_ppre[k])];
     }
-    uint64_t rec0[R], rec1[R];
-#pragma unroll
-    for (int v = 0; v < R; ++v) {
-      const uint64_t j = ent[v] >> ENTRY_SRC_BITS;
-      const uint64_t jc = j < p.n_pairs ? j : 0;   // entries exist, so pair 0 does
-      rec0[v] = p.vp_rec[2 * jc];
-      rec1[v] = p.vp_rec[2 * jc + 1];
-    }
-    uint32_t len[R];
-    uint32_t tsum = 0;
-#pragma unroll
-    for (int v = 0; v < R; ++v) {
-      const bool in = tid * R + v < nb;
-      const uint64_t start = rec0[v] & ((uint64_t(1) << 40) - 1);
-      const uint32_t seg_len = static_cast<uint32_t>(rec0[v] >> 40);
-      const bool ok = (ent[v] & ENTRY_SRC_MASK) < p.N && (ent[v] >> ENTRY_SRC_BITS) < p.n_pairs &&
-                      seg_len >= 1 && start + seg_len <= p.nnz;
-      if (in && !ok) atomicOr(&p.st->error, ERR_ROUTE);
-      if (in && ok) {
-        const uint32_t wbits = static_cast<uint32_t>(rec1[v] >> 32);
-        emit(static_cast<uint32_t>(rec1[v]),
-             p.bf16 ? __uint_as_float(wbits << 16) : __uint_as_float(wbits));
-        events += seg_len;
-      }
-      s_seg[tid * R + v] = start + 1;
-      len[v] = in && ok ? seg_len - 1 : 0u;
-      tsum += len[v];
-    }
-    uint32_t T;
-    uint32_t run = block_excl_scan(tsum, s_wsum, &T);
-#pragma unroll
-    for (int v = 0; v < R; ++v) {
-      s_epre[tid * R + v] = run;
-      run += len[v];
-    }
-    __syncthreads();
-    // the remaining synapses of longer segments
-    for (uint32_t e0 = 0; e0 < T; e0 += GATHER_UNROLL * RECV_THREADS) {
-      uint32_t td[GATHER_UNROLL];
-      float wt[GATHER_UNROLL];
-#pragma unroll
-      for (int v = 0; v < GATHER_UNROLL; ++v) {
-        const uint32_t e = min(e0 + v * RECV_THREADS + tid, T - 1);
-        const uint32_t k = owner_of<RECV_BATCH / 2>(s_epre, nb, e);
-        const uint64_t x = s_seg[k] + (e - s_epre[k]);
-        td[v] = p.tgt_delay[x];
-        wt[v] = load_weight(p, x);
-      }
-#pragma unroll
-      for (int v = 0; v < GATHER_UNROLL; ++v)
-        if (e0 + v * RECV_THREADS + tid < T) emit(td[v], wt[v]);
-    }
-    __syncthreads();
+    stage_batch(p, ctx, ent, nb, events);
   }
   if (tid < md)
     p.stage_cnt[tid * STAGE_BLOCKS + b] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
   add_stat(stat_copy(p, row) + SNN_STAT_REMOTE_EVENTS, events, s_red);
+}
+
+// Expansion and staging in one pass (two-level routing): block b takes the
+// nodes b, b + STAGE_BLOCKS, ...  A node's messages are loaded EXPAND_PER_THREAD
+// consecutive ones per thread; every set bit g of a mask is one receive entry
+// (source, pair index of partition G*n + g: the node's destinations are
+// consecutive in the source's list, so the pair indices follow the message's
+// first one).  The entries go into the partition's receive list (positions
+// from LDS counters: the block owns the node's partitions) and into an LDS
+// buffer, at positions from a block scan of the masks' bit counts; the
+// buffer is staged per delay (stage_batch) when it is full and at the end,
+// without reading the receive lists back.  Messages whose entries do not fit
+// the buffer's free space are taken in the next round.
+__global__ __launch_bounds__(RECV_THREADS) void k_expand_stage(KParams p) {
+  constexpr uint32_t NW = RECV_THREADS / 64;
+  constexpr uint32_t R = RECV_PER_THREAD;
+  constexpr uint32_t EU = EXPAND_PER_THREAD;
+  constexpr uint32_t NG = SNN_MAX_GPUS_PER_NODE;
+  __shared__ uint64_t s_ent[EXPAND_BUF];
+  __shared__ uint64_t s_seg[RECV_BATCH];
+  __shared__ uint32_t s_epre[RECV_BATCH];
+  __shared__ uint32_t s_wsum[NW];
+  __shared__ uint64_t s_red[2 * NW];
+  __shared__ uint32_t l_pos[SNN_MAX_DELAY];
+  __shared__ uint32_t l_cnt[NG], l_run[NG];
+  __shared__ uint64_t l_off[NG + 1];
+  __shared__ uint32_t s_taken, s_added;
+  const uint32_t tid = threadIdx.x, b = blockIdx.x;
+  const uint32_t md = p.D - 1;
+  const uint32_t row = p.st->cur_srow;   // counter row
+  const uint32_t* bcnt = bucket_counts(p, p.st->cur_par);
+  if (tid < SNN_MAX_DELAY) l_pos[tid] = 0;
+  const StageCtx ctx{p.stage + static_cast<uint64_t>(b) * p.stage_cap,
+                     static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap, p.st->cur_slot, l_pos,
+                     s_seg, s_epre, s_wsum};
+  uint64_t events = 0, entries = 0;
+  // stages the n buffered entries (uniform n)
+  auto stage_buffer = [&](uint32_t n) {
+    for (uint32_t b0 = 0; b0 < n; b0 += RECV_BATCH) {
+      const uint32_t nb = min(n - b0, RECV_BATCH);
+      uint64_t ent[R];
+#pragma unroll
+      for (int v = 0; v < R; ++v) ent[v] = s_ent[b0 + min(tid * R + v, nb - 1)];
+      stage_batch(p, ctx, ent, nb, events);
+    }
+  };
+  uint32_t n_buf = 0;   // entries in the buffer (uniform)
+  for (uint32_t n = b; n < p.n_nodes; n += gridDim.x) {
+    const uint64_t off = p.bucket_off[n];
+    const uint32_t cnt = static_cast<uint32_t>(
+        min(static_cast<uint64_t>(bcnt[n * CNT_STRIDE]), p.bucket_off[n + 1] - off));
+    const uint32_t gn = min(p.G, p.P - p.G * n);             // partitions of this node
+    __syncthreads();   // the previous node is done with l_run, l_off
+    if (tid < NG) l_run[tid] = 0;
+    if (tid <= gn) l_off[tid] = p.recv_off[p.G * n + tid];
+    for (uint32_t m0 = 0; m0 < cnt;) {
+      uint64_t w0[EU], pair[EU];
+      uint32_t mask[EU], mine = 0;
+#pragma unroll
+      for (int v = 0; v < EU; ++v) {
+        const uint32_t m = m0 + tid * EU + v;
+        const uint64_t at = 2 * (off + min(m, cnt - 1));
+        w0[v] = p.bucket[at];
+        pair[v] = p.bucket[at + 1];
+      }
+#pragma unroll
+      for (int v = 0; v < EU; ++v) {
+        const bool in = m0 + tid * EU + v < cnt;
+        const uint32_t mk = static_cast<uint32_t>(w0[v] >> 32) & 0xFFu;
+        mask[v] = in ? mk & ((1u << gn) - 1u) : 0u;
+        if (in && mask[v] != mk) atomicOr(&p.st->error, ERR_ROUTE);
+        mine += __popc(mask[v]);
+      }
+      if (tid < NG) l_cnt[tid] = 0;
+      if (tid == 0) s_taken = s_added = 0;
+      uint32_t total;
+      uint32_t at = block_excl_scan(mine, s_wsum, &total);   // ends with the block's view of l_cnt = 0
+      const uint32_t room = EXPAND_BUF - n_buf;
+      uint32_t taken = 0, added = 0;
+#pragma unroll
+      for (int v = 0; v < EU; ++v) {
+        const uint32_t pc = __popc(mask[v]);
+        const bool in = m0 + tid * EU + v < cnt;
+        if (in && at + pc <= room) {   // taken (the taken messages are a prefix)
+          const uint64_t s = w0[v] & 0xFFFFFFFFull;
+          uint32_t mm = mask[v];
+          uint32_t k = 0;
+          while (mm) {
+            const uint32_t g = __ffs(mm) - 1;
+            mm &= mm - 1;
+            const uint64_t e = s | ((pair[v] + k) << ENTRY_SRC_BITS);
+            s_ent[n_buf + at + k] = e;
+            const uint32_t rk = atomicAdd(&l_cnt[g], 1u);
+            const uint64_t pos = l_off[g] + l_run[g] + rk;
+            if (pos < l_off[g + 1]) p.recv[pos] = e;
+            else atomicOr(&p.st->error, ERR_RECV);
+            ++k;
+          }
+          ++taken;
+          added += pc;
+        }
+        at += pc;
+      }
+      if (taken) {
+        atomicAdd(&s_taken, taken);
+        atomicAdd(&s_added, added);
+      }
+      __syncthreads();
+      const uint32_t round_taken = s_taken, round_added = s_added;
+      const uint32_t loaded = min(cnt - m0, EU * RECV_THREADS);
+      if (tid < NG) l_run[tid] += l_cnt[tid];
+      entries += tid == 0 ? round_added : 0u;
+      n_buf += round_added;
+      m0 += round_taken;
+      if (round_taken < loaded) {   // the buffer is full: stage it
+        stage_buffer(n_buf);
+        n_buf = 0;
+      }
+      __syncthreads();
+    }
+    if (tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
+  }
+  stage_buffer(n_buf);
+  if (tid < md)
+    p.stage_cnt[tid * STAGE_BLOCKS + b] =
+        static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
+  uint64_t* sc = stat_copy(p, row);
+  add_stats(sc + SNN_STAT_REMOTE_EVENTS, events, sc + SNN_STAT_RECV_ENTRIES, entries, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1329,7 +1476,7 @@ static size_t route_kernel_lds_bytes(const KParams& p) {
 }
 
 hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
-                        bool routed) {
+                        bool routed, bool defer_expand) {
   if (mode == SNN_ROUTE_TWO_LEVEL || mode == SNN_ROUTE_BOTH) {
     if (!routed) {
       mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 0, s);
@@ -1340,9 +1487,11 @@ hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* m
         hipLaunchKernelGGL(k_route_two_level_direct, dim3(1024), dim3(ROUTE_THREADS), 0, s, p);
       mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 1, s);
     }
-    mark(marks, SNN_KERNEL_EXPAND, 0, s);
-    hipLaunchKernelGGL(k_expand, dim3(p.n_nodes), dim3(EXPAND_THREADS), 0, s, p);
-    mark(marks, SNN_KERNEL_EXPAND, 1, s);
+    if (!defer_expand) {
+      mark(marks, SNN_KERNEL_EXPAND, 0, s);
+      hipLaunchKernelGGL(k_expand, dim3(p.n_nodes), dim3(EXPAND_THREADS), 0, s, p);
+      mark(marks, SNN_KERNEL_EXPAND, 1, s);
+    }
   }
   if (mode == SNN_ROUTE_FLAT || mode == SNN_ROUTE_BOTH) {
     mark(marks, SNN_KERNEL_ROUTE_FLAT, 0, s);
@@ -1360,10 +1509,14 @@ size_t deliver_lds_bytes(const KParams& p) {
   return p.dstage * DELIVER_EVENT_LDS + 3ull * p.n_tiles * sizeof(uint32_t);
 }
 
-hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks) {
+hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
+                          bool fused_expand) {
   mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
-  hipLaunchKernelGGL(k_recv_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p,
-                     mode == SNN_ROUTE_FLAT ? 1 : 0);
+  if (fused_expand && mode != SNN_ROUTE_FLAT)
+    hipLaunchKernelGGL(k_expand_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p);
+  else
+    hipLaunchKernelGGL(k_recv_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p,
+                       mode == SNN_ROUTE_FLAT ? 1 : 0);
   mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
   mark(marks, SNN_KERNEL_DELIVER, 0, s);
   hipLaunchKernelGGL(k_deliver, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),

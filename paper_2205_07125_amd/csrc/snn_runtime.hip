@@ -154,6 +154,7 @@ struct snn_ctx {
   KParams kp;
   int phase;          // 0: expects step, 1: route, 2: deliver
   int route_mode;     // mode of the step in flight
+  bool expand_deferred;  // snn_step_route left the mask expansion to snn_deliver
   uint64_t t_host;    // steps enqueued
   uint64_t routed_t;  // step whose routes are in the buffers (+1), 0 = none
   hipGraphExec_t graph[3][2];   // per route mode: one step, GRAPH_STEPS steps
@@ -330,27 +331,29 @@ snn_status snn_step_route(snn_handle h, int mode) {
   if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_step_route called before snn_deliver");
   const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(h->kp);
   HIP_TRY(launch_update(h->kp, h->stream, nullptr, fused));
-  HIP_TRY(launch_route(h->kp, mode, h->stream, nullptr, fused));
+  HIP_TRY(launch_route(h->kp, mode, h->stream, nullptr, fused, true));
   h->route_mode = mode;
+  h->expand_deferred = true;
   h->phase = 2;
   h->routed_t = h->t_host + 1;
   return SNN_OK;
 }
 
-// One whole step in route mode `mode`, two-level routing inside the update
-// kernel where the node count allows.
+// One whole step in route mode `mode`: two-level routing inside the update
+// kernel where the node count allows, mask expansion inside the staging.
 static hipError_t launch_step(const KParams& kp, int mode, hipStream_t s, hipEvent_t* marks) {
   const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(kp);
   hipError_t e = launch_update(kp, s, marks, fused);
-  if (e == hipSuccess) e = launch_route(kp, mode, s, marks, fused);
-  if (e == hipSuccess) e = launch_deliver(kp, mode, s, marks);
+  if (e == hipSuccess) e = launch_route(kp, mode, s, marks, fused, true);
+  if (e == hipSuccess) e = launch_deliver(kp, mode, s, marks, true);
   return e;
 }
 
 snn_status snn_deliver(snn_handle h) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
   if (h->phase != 2) return fail(SNN_ERR_BAD_STATE, "snn_deliver must follow snn_route");
-  HIP_TRY(launch_deliver(h->kp, h->route_mode, h->stream));
+  HIP_TRY(launch_deliver(h->kp, h->route_mode, h->stream, nullptr, h->expand_deferred));
+  h->expand_deferred = false;
   h->phase = 0;
   h->t_host += 1;
   return SNN_OK;
@@ -420,7 +423,7 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
   const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(h->kp);
   const bool launched[SNN_NKERNEL] = {true,
                                       mode != SNN_ROUTE_FLAT && !fused,
-                                      mode != SNN_ROUTE_FLAT,
+                                      false,   // expansion runs inside the staging kernel
                                       mode != SNN_ROUTE_TWO_LEVEL,
                                       true,
                                       true};
@@ -583,6 +586,8 @@ snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entri
   const int mode = h->route_mode;
   if ((which == 0 && mode == SNN_ROUTE_TWO_LEVEL) || (which != 0 && mode == SNN_ROUTE_FLAT))
     return fail(SNN_ERR_BAD_STATE, "the last step was not routed in a mode that fills these buffers");
+  if (which == 1 && h->expand_deferred)
+    return fail(SNN_ERR_BAD_STATE, "after snn_step_route the receive lists are filled by snn_deliver");
   DevState dst;
   snn_status s = sync_and_check(h, &dst);
   if (s != SNN_OK) return s;

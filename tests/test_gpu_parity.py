@@ -126,13 +126,16 @@ def test_fused_route_lockstep(name, mode):
 
 
 def test_fused_route_many_spikes_per_tile():
-    """More fired neurons in one tile than a routing batch holds (512) and more
-    pairs than a window (1,024): the batch and window loops of the fused
-    routing, and runs of one node cut by a window's end."""
-    wl = synth.get_workload("tiny").replace(name="tiny_dense", forced=1, rate_on_hz=2000.0,
-                                            rate_off_hz=2000.0, period_steps=1, on_steps=1)
-    _, _, stats = _lockstep(wl, 40, route_every=1, state_every=10, mode=ROUTE_BOTH, fused=True)
-    assert stats[:, 0].max() > 512      # one tile: two routing batches
+    """60 % of one tile firing per step: more fired neurons than a routing batch
+    holds (512) and more pairs than a window (1,024), so the batch and window
+    loops of the fused routing run, with runs of one node cut by a window's
+    end; each node gets more messages than one expansion round loads (2,048)
+    and more entries than the staging buffer holds (4,096)."""
+    wl = synth.get_workload("tiny").replace(name="tiny_dense", forced=1, rate_on_hz=6000.0,
+                                            rate_off_hz=6000.0, period_steps=1, on_steps=1)
+    _, _, stats = _lockstep(wl, 30, route_every=1, state_every=10, mode=ROUTE_BOTH, fused=True)
+    assert stats[:, 0].min() > 2048
+    assert stats[:, 6].min() > 2 * 2 * 4096    # two nodes, each over two buffers
 
 
 def test_unfused_fallback_many_nodes():
