@@ -1338,6 +1338,13 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
     __syncthreads();
   };
 
+  // The window fills with the local synapses of this block's fired sources
+  // and then, in the same window, with the staged remote ones; it is sorted
+  // and written out whenever it is full and once at the end.
+  uint32_t fill = 0;
+  // queue lengths, loaded now so that they are ready when needed
+  const uint32_t qc = tid < QPB ? p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS] : 0u;
+
   // local synapses of the fired sources assigned to this block, in batches
   // of one source per thread
   const uint32_t M = nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
@@ -1356,14 +1363,14 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
     s_pre[tid] = ex;
     __syncthreads();
     events += tid == 0 ? tot : 0u;
-    for (uint32_t e0 = 0; e0 < tot; e0 += S) {
-      const uint32_t n_win = min(tot - e0, S);
-      for (uint32_t i0 = 0; i0 < n_win; i0 += GATHER_UNROLL * DELIVER_THREADS) {
+    for (uint32_t e0 = 0; e0 < tot;) {
+      const uint32_t n_chunk = min(tot - e0, S - fill);
+      for (uint32_t i0 = 0; i0 < n_chunk; i0 += GATHER_UNROLL * DELIVER_THREADS) {
         uint32_t td[GATHER_UNROLL];
         float wt[GATHER_UNROLL];
 #pragma unroll
         for (int v = 0; v < GATHER_UNROLL; ++v) {
-          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_win - 1);
+          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_chunk - 1);
           const uint32_t k = owner_of<DELIVER_THREADS / 2>(s_pre, nsrc, e);
           const uint64_t x = s_base[k] + (e - s_pre[k]);
           td[v] = p.tgt_delay[x];
@@ -1372,42 +1379,52 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
 #pragma unroll
         for (int v = 0; v < GATHER_UNROLL; ++v) {
           const uint32_t le = i0 + v * DELIVER_THREADS + tid;
-          if (le < n_win) put(le, td[v] & 0x07FFFFFFu, quantize_w(p, wt[v]));
+          if (le < n_chunk) put(fill + le, td[v] & 0x07FFFFFFu, quantize_w(p, wt[v]));
         }
       }
-      flush(n_win);
+      e0 += n_chunk;
+      fill += n_chunk;
+      if (fill == S) {
+        flush(fill);
+        fill = 0;
+      }
     }
+    __syncthreads();   // s_pre, s_base are rewritten by the next batch
   }
 
   // remote synapses staged by the receive side for this delay: queues
   // w + k * DELIVER_BLOCKS, k < QPB, concatenated the same way
   {
-    uint32_t c = 0;
-    if (tid < QPB) c = p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS];
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(c, s_wsum, &tot);
+    const uint32_t ex = block_excl_scan(qc, s_wsum, &tot);
     if (tid < QPB) s_pre[tid] = ex;
     __syncthreads();
     const Event* q0 = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + w) * p.stage_cap;
-    for (uint32_t e0 = 0; e0 < tot; e0 += S) {
-      const uint32_t n_win = min(tot - e0, S);
-      for (uint32_t i0 = 0; i0 < n_win; i0 += GATHER_UNROLL * DELIVER_THREADS) {
+    for (uint32_t e0 = 0; e0 < tot;) {
+      const uint32_t n_chunk = min(tot - e0, S - fill);
+      for (uint32_t i0 = 0; i0 < n_chunk; i0 += GATHER_UNROLL * DELIVER_THREADS) {
         Event x[GATHER_UNROLL];
 #pragma unroll
         for (int v = 0; v < GATHER_UNROLL; ++v) {
-          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_win - 1);
+          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_chunk - 1);
           const uint32_t k = owner_of<QPB / 2>(s_pre, QPB, e);
           x[v] = q0[static_cast<uint64_t>(k) * DELIVER_BLOCKS * p.stage_cap + (e - s_pre[k])];
         }
 #pragma unroll
         for (int v = 0; v < GATHER_UNROLL; ++v) {
           const uint32_t le = i0 + v * DELIVER_THREADS + tid;
-          if (le < n_win) put(le, x[v].tgt, x[v].wq);
+          if (le < n_chunk) put(fill + le, x[v].tgt, x[v].wq);
         }
       }
-      flush(n_win);
+      e0 += n_chunk;
+      fill += n_chunk;
+      if (fill == S) {
+        flush(fill);
+        fill = 0;
+      }
     }
   }
+  if (fill) flush(fill);
   __syncthreads();
 
   // publish this block's counts for slot `slot`, every tile (zeros included)
