@@ -239,17 +239,22 @@ def main():
     fused = mode == SNN_ROUTE_TWO_LEVEL and kt.get("route_two_level", 0.0) == 0.0
     if fused:
         alg["update"] += alg["route_two_level"]
-    # mask expansion done inside the staging kernel: its bytes belong there
+    # mask expansion and the own-partition delivery done inside the
+    # receive-side launch: their bytes belong there; the last launch then
+    # delivers only the staged remote synapses (8 B per staged event read)
     fused_x = mode == SNN_ROUTE_TWO_LEVEL and kt.get("expand", 0.0) == 0.0
     if fused_x:
-        alg["recv_stage"] += alg["expand"]
+        alg["recv_stage"] += alg["expand"] + alg["deliver"]
+        alg["deliver"] = 8.0 * e_rem
     kernels = {k: {"ms": kt[k], "alg_bytes": alg[k],
                    "gbs": alg[k] / (kt[k] * 1e-3) / 1e9 if kt[k] > 0 else None}
                for k in kt if kt[k] > 0}
     if fused:
         kernels["update"]["includes"] = "two-level routing of the tile's fired neurons"
     if fused_x:
-        kernels["recv_stage"]["includes"] = "mask expansion of the node's messages"
+        kernels["recv_stage"]["includes"] = ("mask expansion of the node's messages; delivery of "
+                                             "the fired sources' own-partition synapses")
+        kernels["deliver"]["includes"] = "the staged remote synapses only"
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     b, t_ms = kernels[dom]["alg_bytes"], kernels[dom]["ms"]
     achieved = b / (t_ms * 1e-3) / 1e9

@@ -68,7 +68,7 @@ constexpr int RECV_THREADS = 512;
 constexpr uint32_t RECV_PER_THREAD = 4;                         // entries per thread per batch
 constexpr uint32_t RECV_BATCH = RECV_THREADS * RECV_PER_THREAD; // entries per batch
 static_assert(STAGE_PARTS <= RECV_THREADS, "one partition count per thread");
-constexpr uint32_t EXPAND_BUF = 4096;               // receive entries buffered per staging pass
+constexpr uint32_t EXPAND_BUF = 2048;               // receive entries buffered per staging pass
 constexpr uint32_t EXPAND_PER_THREAD = 4;           // messages per thread per expansion round
 static_assert(EXPAND_BUF >= SNN_MAX_GPUS_PER_NODE, "one message's entries fit the buffer");
 
@@ -130,7 +130,9 @@ struct KParams {
   uint64_t stage_cap;
   float wq_scale;      // 2^F: weight -> fixed point
   double wq_inv;       // 2^-F
-  uint32_t dstage;     // deliver window (events), set by prepare_kernels
+  uint32_t dstage;     // deliver windows (events), set by prepare_kernels: whole deliver,
+  uint32_t dstage_r;   // its remote part alone,
+  uint32_t dstage_h;   // its local part beside the receive side (k_recv_local)
   // network (caller-owned device memory)
   const int64_t* row_ptr;
   const uint32_t* n_local;
@@ -173,7 +175,7 @@ struct KParams {
 // With non-null marks, events marks[2k], marks[2k + 1] are recorded around
 // each launch of kernel kind k (SNN_KERNEL_*).
 uint32_t tiles_of(uint32_t n);
-hipError_t prepare_kernels(KParams& p);   // LDS sizing (sets dstage), once per handle
+hipError_t prepare_kernels(KParams& p);   // LDS sizing (deliver windows), once per handle
 // With route, the update kernel also routes the step two-level where the node
 // count allows (fused_route_ok); launch_route is then told so (routed) and
 // launches only what remains (expansion, flat lists).

@@ -1114,7 +1114,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
 }
 
 // Expansion and staging in one pass (two-level routing): block b takes the
-// nodes b, b + STAGE_BLOCKS, ...  A node's messages are loaded EXPAND_PER_THREAD
+// nodes b, b + nblocks, ...  A node's messages are loaded EXPAND_PER_THREAD
 // consecutive ones per thread; every set bit g of a mask is one receive entry
 // (source, pair index of partition G*n + g: the node's destinations are
 // consecutive in the source's list, so the pair indices follow the message's
@@ -1124,21 +1124,22 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
 // buffer is staged per delay (stage_batch) when it is full and at the end,
 // without reading the receive lists back.  Messages whose entries do not fit
 // the buffer's free space are taken in the next round.
-__global__ __launch_bounds__(RECV_THREADS) void k_expand_stage(KParams p) {
+// Block b of nblocks; dyn holds EXPAND_STAGE_LDS bytes of LDS.
+__device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblocks, uint64_t* dyn) {
   constexpr uint32_t NW = RECV_THREADS / 64;
   constexpr uint32_t R = RECV_PER_THREAD;
   constexpr uint32_t EU = EXPAND_PER_THREAD;
   constexpr uint32_t NG = SNN_MAX_GPUS_PER_NODE;
-  __shared__ uint64_t s_ent[EXPAND_BUF];
-  __shared__ uint64_t s_seg[RECV_BATCH];
-  __shared__ uint32_t s_epre[RECV_BATCH];
+  uint64_t* s_ent = dyn;                                                   // [EXPAND_BUF]
+  uint64_t* s_seg = s_ent + EXPAND_BUF;                                    // [RECV_BATCH]
+  uint32_t* s_epre = reinterpret_cast<uint32_t*>(s_seg + RECV_BATCH);      // [RECV_BATCH]
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
   __shared__ uint32_t l_pos[SNN_MAX_DELAY];
   __shared__ uint32_t l_cnt[NG], l_run[NG];
   __shared__ uint64_t l_off[NG + 1];
   __shared__ uint32_t s_taken, s_added;
-  const uint32_t tid = threadIdx.x, b = blockIdx.x;
+  const uint32_t tid = threadIdx.x;
   const uint32_t md = p.D - 1;
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t* bcnt = bucket_counts(p, p.st->cur_par);
@@ -1158,7 +1159,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_expand_stage(KParams p) {
     }
   };
   uint32_t n_buf = 0;   // entries in the buffer (uniform)
-  for (uint32_t n = b; n < p.n_nodes; n += gridDim.x) {
+  for (uint32_t n = b; n < p.n_nodes; n += nblocks) {
     const uint64_t off = p.bucket_off[n];
     const uint32_t cnt = static_cast<uint32_t>(
         min(static_cast<uint64_t>(bcnt[n * CNT_STRIDE]), p.bucket_off[n + 1] - off));
@@ -1261,10 +1262,13 @@ __global__ __launch_bounds__(RECV_THREADS) void k_expand_stage(KParams p) {
 // Dynamic LDS: a window of dstage events + tile/rank words + permutation +
 // 3 * n_tiles counters (dstage <= DELIVER_STAGE, set by prepare_kernels to
 // what the device's LDS holds).
-__global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
-  extern __shared__ uint64_t lds_u64[];
-  const uint32_t S = p.dstage;                                            // window (events)
-  Event* s_ev = reinterpret_cast<Event*>(lds_u64);                        // [S]
+// LOCAL / REMOTE select the parts a block does; a remote-only block appends
+// to the sub-bins after the counts the local part published.  dyn holds
+// deliver_lds_bytes(S, n_tiles) bytes.
+template <bool LOCAL, bool REMOTE>
+__device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint32_t S,
+                              uint64_t* dyn) {
+  Event* s_ev = reinterpret_cast<Event*>(dyn);                            // [S]
   uint32_t* s_tr = reinterpret_cast<uint32_t*>(s_ev + S);                 // tile | rank << 16
   uint32_t* l_cnt = s_tr + S;                                             // [n_tiles]
   uint32_t* l_run = l_cnt + p.n_tiles;                                    // [n_tiles]
@@ -1277,7 +1281,6 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
   const uint32_t tid = threadIdx.x;
-  const uint32_t w = blockIdx.x, d = blockIdx.y + 1;
 
   const uint32_t nF = p.st->n_fired;
   uint32_t slot = p.st->cur_slot + d;
@@ -1285,7 +1288,7 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t D = p.D;
   for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS) {
-    l_run[i] = 0;
+    l_run[i] = LOCAL ? 0u : p.bin_cnt[subbin(p, slot, i, d, w)];
     l_cnt[i] = 0;
   }
   uint64_t events = 0;
@@ -1343,11 +1346,12 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   // and written out whenever it is full and once at the end.
   uint32_t fill = 0;
   // queue lengths, loaded now so that they are ready when needed
-  const uint32_t qc = tid < QPB ? p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS] : 0u;
+  const uint32_t qc =
+      REMOTE && tid < QPB ? p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS] : 0u;
 
   // local synapses of the fired sources assigned to this block, in batches
   // of one source per thread
-  const uint32_t M = nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
+  const uint32_t M = LOCAL && nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
   for (uint32_t m0 = 0; m0 < M; m0 += DELIVER_THREADS) {
     const uint32_t nsrc = min(M - m0, static_cast<uint32_t>(DELIVER_THREADS));
     uint32_t len = 0;
@@ -1394,7 +1398,7 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
 
   // remote synapses staged by the receive side for this delay: queues
   // w + k * DELIVER_BLOCKS, k < QPB, concatenated the same way
-  {
+  if (REMOTE) {
     uint32_t tot;
     const uint32_t ex = block_excl_scan(qc, s_wsum, &tot);
     if (tid < QPB) s_pre[tid] = ex;
@@ -1431,7 +1435,39 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS)
     p.bin_cnt[subbin(p, slot, i, d, w)] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_run[i]), p.bin_cap));
-  add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
+  if (LOCAL) add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
+}
+
+__global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
+  extern __shared__ uint64_t lds_u64[];
+  deliver_block<true, true>(p, blockIdx.x, blockIdx.y + 1, p.dstage, lds_u64);
+}
+
+// The staged remote synapses of (w, d) = (blockIdx.x, blockIdx.y + 1), after
+// k_recv_local delivered the local ones.
+__global__ __launch_bounds__(DELIVER_THREADS) void k_deliver_remote(KParams p) {
+  extern __shared__ uint64_t lds_u64[];
+  deliver_block<false, true>(p, blockIdx.x, blockIdx.y + 1, p.dstage_r, lds_u64);
+}
+
+// Two independent jobs in one launch, so that they overlap: blocks
+// [0, STAGE_BLOCKS) expand and stage the two-level messages
+// (expand_stage_block), the rest deliver the fired sources' local synapses
+// (deliver_block, local part; block STAGE_BLOCKS + i takes (w, d) =
+// (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)).  The local part needs only
+// the fired list, not the receive side.  Three blocks of 8 waves per CU (6
+// waves per SIMD, at most 80 VGPRs), so that all blocks of both jobs are
+// resident at once.
+static_assert(RECV_THREADS == DELIVER_THREADS, "one block size for both jobs");
+__global__ __launch_bounds__(RECV_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
+void k_recv_local(KParams p) {
+  extern __shared__ uint64_t lds_u64[];
+  if (blockIdx.x < STAGE_BLOCKS) {
+    expand_stage_block(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
+  } else {
+    const uint32_t i = blockIdx.x - STAGE_BLOCKS;
+    deliver_block<true, false>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, p.dstage_h, lds_u64);
+  }
 }
 
 // Moves every pending binned event into the dense ring (for read-back) and
@@ -1522,46 +1558,90 @@ hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* m
 constexpr size_t DELIVER_EVENT_LDS = sizeof(Event) + sizeof(uint32_t) + sizeof(uint16_t);
 static_assert(DELIVER_STAGE <= 65536, "window ranks and permutation fit 16 bits");
 
-size_t deliver_lds_bytes(const KParams& p) {
-  return p.dstage * DELIVER_EVENT_LDS + 3ull * p.n_tiles * sizeof(uint32_t);
+static size_t deliver_lds_bytes(uint32_t S, uint32_t n_tiles) {
+  return S * DELIVER_EVENT_LDS + 3ull * n_tiles * sizeof(uint32_t);
+}
+
+// Expansion and staging: the entry buffer, and per batch each entry's
+// segment start and its remaining synapses' start.
+constexpr size_t EXPAND_STAGE_LDS =
+    EXPAND_BUF * sizeof(uint64_t) + RECV_BATCH * (sizeof(uint64_t) + sizeof(uint32_t));
+
+static size_t recv_local_lds_bytes(const KParams& p) {
+  return std::max(EXPAND_STAGE_LDS, deliver_lds_bytes(p.dstage_h, p.n_tiles));
 }
 
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
                           bool fused_expand) {
+  if (fused_expand && mode != SNN_ROUTE_FLAT) {
+    mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
+    hipLaunchKernelGGL(k_recv_local, dim3(STAGE_BLOCKS + DELIVER_BLOCKS * (p.D - 1)),
+                       dim3(RECV_THREADS), recv_local_lds_bytes(p), s, p);
+    mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
+    mark(marks, SNN_KERNEL_DELIVER, 0, s);
+    hipLaunchKernelGGL(k_deliver_remote, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
+                       deliver_lds_bytes(p.dstage_r, p.n_tiles), s, p);
+    mark(marks, SNN_KERNEL_DELIVER, 1, s);
+    return hipGetLastError();
+  }
   mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
-  if (fused_expand && mode != SNN_ROUTE_FLAT)
-    hipLaunchKernelGGL(k_expand_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p);
-  else
-    hipLaunchKernelGGL(k_recv_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p,
-                       mode == SNN_ROUTE_FLAT ? 1 : 0);
+  hipLaunchKernelGGL(k_recv_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p,
+                     mode == SNN_ROUTE_FLAT ? 1 : 0);
   mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
   mark(marks, SNN_KERNEL_DELIVER, 0, s);
   hipLaunchKernelGGL(k_deliver, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
-                     deliver_lds_bytes(p), s, p);
+                     deliver_lds_bytes(p.dstage, p.n_tiles), s, p);
   mark(marks, SNN_KERNEL_DELIVER, 1, s);
   return hipGetLastError();
 }
 
+// The largest deliver window (a multiple of DELIVER_THREADS, at most
+// DELIVER_STAGE) whose LDS, with static_bytes of static LDS, fits budget.
+static uint32_t window_for(int64_t budget, size_t static_bytes, uint32_t n_tiles) {
+  const int64_t room = budget - int64_t(static_bytes) - int64_t(3ull * n_tiles * sizeof(uint32_t));
+  const int64_t fit = room > 0 ? (room / int64_t(DELIVER_EVENT_LDS)) & ~int64_t(DELIVER_THREADS - 1) : 0;
+  return static_cast<uint32_t>(std::min<int64_t>(DELIVER_STAGE, fit));
+}
+
 hipError_t prepare_kernels(KParams& p) {
-  // deliver window: DELIVER_STAGE events, less where many tiles leave less LDS
-  int dev = 0, lds_max = 0;
+  int dev = 0, lds_max = 0, lds_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  hipFuncAttributes fa{};
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  hipFuncAttributes fa{}, fr{}, fh{};
   if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_deliver));
+  if (e == hipSuccess) e = hipFuncGetAttributes(&fr, reinterpret_cast<const void*>(&k_deliver_remote));
+  if (e == hipSuccess) e = hipFuncGetAttributes(&fh, reinterpret_cast<const void*>(&k_recv_local));
   if (e != hipSuccess) return e;
-  const int64_t room = int64_t(lds_max) - int64_t(fa.sharedSizeBytes) -
-                       int64_t(3ull * p.n_tiles * sizeof(uint32_t));
-  const int64_t fit = room > 0 ? (room / int64_t(DELIVER_EVENT_LDS)) & ~int64_t(DELIVER_THREADS - 1) : 0;
-  p.dstage = static_cast<uint32_t>(std::min<int64_t>(DELIVER_STAGE, fit));
-  if (p.dstage < DELIVER_THREADS) return hipErrorInvalidConfiguration;
+  // whole deliver and remote part: windows of up to DELIVER_STAGE events,
+  // less where many tiles leave less LDS
+  p.dstage = window_for(lds_max, fa.sharedSizeBytes, p.n_tiles);
+  p.dstage_r = window_for(lds_max, fr.sharedSizeBytes, p.n_tiles);
+  // receive side with local delivery: three blocks per CU where a window of
+  // DELIVER_THREADS or more fits that, else what one block may hold
+  const int64_t third = int64_t(lds_cu) / 3;
+  p.dstage_h = window_for(third, fh.sharedSizeBytes, p.n_tiles);
+  if (p.dstage_h < DELIVER_THREADS || int64_t(fh.sharedSizeBytes + EXPAND_STAGE_LDS) > third)
+    p.dstage_h = window_for(lds_max, fh.sharedSizeBytes, p.n_tiles);
+  if (p.dstage < DELIVER_THREADS || p.dstage_r < DELIVER_THREADS || p.dstage_h < DELIVER_THREADS ||
+      int64_t(fh.sharedSizeBytes + EXPAND_STAGE_LDS) > lds_max)
+    return hipErrorInvalidConfiguration;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_route_two_level),
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           static_cast<int>(route_kernel_lds_bytes(p)));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver_remote),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(deliver_lds_bytes(p.dstage_r, p.n_tiles)));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recv_local),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(recv_local_lds_bytes(p)));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver),
                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(deliver_lds_bytes(p)));
+                             static_cast<int>(deliver_lds_bytes(p.dstage, p.n_tiles)));
 }
 
 hipError_t launch_flush(const KParams& p, hipStream_t s) {
