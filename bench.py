@@ -264,8 +264,11 @@ def main():
         with open(tf) as fh:
             tj = json.load(fh).get(wl.name, {})
         h = kernel_source_hash()
+        # counters are keyed by kernel symbol; the combined receive-side
+        # launch and the remote-only deliver have their own
+        symbol = {"recv_stage": "recv_local", "deliver": "deliver_remote"} if fused_x else {}
         for k, v in kernels.items():
-            ent = tj.get(k)
+            ent = tj.get(symbol.get(k, k))
             v["traffic_bytes"] = ent["bytes_per_launch"] if ent and ent.get("kernel_hash") == h else None
         traffic = kernels[dom].get("traffic_bytes")
     # whole step (survey's per-step algorithmic bytes, ring RMW excluded)
