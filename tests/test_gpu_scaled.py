@@ -27,11 +27,17 @@ SCALED = {
 }
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
 @pytest.mark.parametrize("name", sorted(SCALED))
-def test_scaled_workload_lockstep(name):
+def test_scaled_workload_lockstep(name, fused):
+    """fused: snn_step_route + snn_deliver, as snn_run launches a step (routing
+    inside the update; expansion, staging and local delivery in one launch);
+    paper_share_4k's 500 nodes run the staging blocks' node loop and come
+    close to the fused routing's node limit."""
     wl = SCALED[name]()
     steps = 80
-    _, orc, stats = _lockstep(wl, steps, route_every=8, state_every=40, mode=ROUTE_BOTH)
+    _, orc, stats = _lockstep(wl, steps, route_every=8, state_every=40, mode=ROUTE_BOTH,
+                              fused=fused)
     assert stats[:, 0].sum() > 0
     print(f"[gpu] {name}: {int(stats[:, 0].sum())} spikes, "
           f"{int(stats[:, 1].sum() + stats[:, 2].sum())} events, "
