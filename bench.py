@@ -209,6 +209,19 @@ def main():
     # per-kernel durations: eager steps, every kernel bracketed by HIP events
     # on the simulation stream (the stream all kernels are launched on)
     kt = sim.kernel_times(args.phase_steps, mode)
+    # connections of the last step (the paper's per-GPU count, Sec. VI, Fig. 4):
+    # destination partitions reached (what flat exchange opens) against
+    # destination nodes reached (what two-level exchange opens), and the
+    # largest message count on one of them
+    links = None
+    if mode == SNN_ROUTE_TWO_LEVEL:
+        per_part = sim.route_sizes(1)
+        per_node = sim.route_sizes(2)
+        links = {"partitions_reached": int((per_part > 0).sum()),
+                 "nodes_reached": int((per_node > 0).sum()),
+                 "max_entries_per_partition": int(per_part.max()),
+                 "max_msgs_per_node": int(per_node.max()),
+                 "of": "the last step of the per-kernel timing"}
     pc = sim.read_counters(args.warmup + args.steps, args.phase_steps).astype(np.float64)
     log("kernels (ms): " + "  ".join(f"{k} {v:.4f}" for k, v in kt.items() if v > 0))
     N = wl.n_neurons
@@ -299,6 +312,7 @@ def main():
                           "flat": flat / args.steps},
         "hbm_frac_step": step_bytes / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
         "kernels": kernels,
+        "links": links,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": b, "avg_launch_ms": t_ms,

@@ -154,6 +154,17 @@ class Simulation:
                                      counts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
         return ids[:n.value], counts
 
+    def route_sizes(self, which: int) -> np.ndarray:
+        """Entries per list (which 0 flat, 1 expanded, per partition) or
+        messages per node bucket (which 2) of the last routed step, without
+        copying the entries (snn_read_routes with entries = NULL)."""
+        nl = self.wl.n_nodes if which == 2 else self.wl.n_partitions
+        sizes = np.zeros(nl, np.uint64)
+        n = ctypes.c_uint64()
+        _abi.check(_abi.lib().snn_read_routes(self.h, which, sizes.ctypes.data_as(ctypes.c_void_p),
+                                              None, 0, ctypes.byref(n)))
+        return sizes
+
     def read_routes(self, which: int, sources_only: bool = False):
         """which 0 flat lists, 1 expanded lists (per partition), 2 node buckets
         (per node); uint64 elements (see include/snn.h), or just the source ids

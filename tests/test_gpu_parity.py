@@ -125,6 +125,22 @@ def test_fused_route_lockstep(name, mode):
     _lockstep(wl, 300, route_every=10, state_every=50, mode=mode, fused=True)
 
 
+def test_connection_counts_match_oracle():
+    """Per-list sizes without the entries (snn_read_routes with entries = NULL,
+    as the bench reads the connections of a step): partitions and nodes
+    reached and the message counts per node equal the oracle's."""
+    wl = synth.get_workload("tiny_active").replace(seed=5)
+    sim, orc = _pair(wl, log_steps=50)
+    for _ in range(50):
+        sim.step_route(ROUTE_TWO_LEVEL)
+        sim.deliver()
+        orc.step()
+        per_part = sim.route_sizes(1)
+        per_node = sim.route_sizes(2)
+        assert np.array_equal(per_part, np.array([len(x) for x in orc.recv(1)], np.uint64))
+        assert np.array_equal(per_node, np.array([len(x) for x in orc.buckets()], np.uint64))
+
+
 def test_fused_route_many_spikes_per_tile():
     """60 % of one tile firing per step: more fired neurons than a routing batch
     holds (512) and more pairs than a window (1,024), so the batch and window
