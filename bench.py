@@ -32,11 +32,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def code_text(src: str) -> str:
+    """Source text without // comments and blank lines: what the compiler
+    sees of it (a comment edit does not invalidate measured counters)."""
+    lines = []
+    for line in src.splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            lines.append(code)
+    return "\n".join(lines)
+
+
+def kernel_source_hash(read=None) -> str:
     h = hashlib.sha256()
     for f in ("snn_kernels.hip", "snn_internal.h"):
-        with open(os.path.join(ROOT, "paper_2205_07125_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        path = os.path.join("paper_2205_07125_amd", "csrc", f)
+        if read is None:
+            with open(os.path.join(ROOT, path)) as fh:
+                text = fh.read()
+        else:
+            text = read(path)
+        h.update(code_text(text).encode())
     return h.hexdigest()[:16]
 
 

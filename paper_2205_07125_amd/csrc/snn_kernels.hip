@@ -1,18 +1,28 @@
 // snn_kernels.hip — the per-step kernels for gfx950 (wave64, CDNA4).
 //
-//   update       one block per tile of TILE neurons: sums the tile's arriving
-//                synaptic events into LDS from its bins, runs the LIF update
-//                and threshold, compacts fired ids in ascending order (wave
-//                ballots, block scan, decoupled look-back across tiles)
-//   route        two-level: one (source, node mask) message per destination
-//                node into per-node buckets (Sec. IV-B), then mask expansion
-//                into per-partition receive lists (the bridge's forwarding);
-//                flat: one receive entry per destination partition
-//   recv_stage   receive side: each entry's synapses for its partition,
-//                staged per delay in per-block queues
-//   deliver      per delay: the own-partition synapses of every fired source
-//                plus the staged remote ones, counting-sorted by tile in LDS
-//                and written as runs into per-(slot, tile, delay, block) bins
+// The work of a step, as device functions shared by the kernels:
+//   k_update       one block per tile of TILE neurons: sums the tile's arriving
+//                  synaptic events into LDS from its bins, runs the LIF update
+//                  and threshold, compacts fired ids in ascending order (wave
+//                  ballots, block scan, decoupled look-back across tiles)
+//   route_batch    two-level routing: one (source, node mask) message per
+//                  destination node into per-node buckets (Sec. IV-B)
+//   expand_stage_block / k_expand
+//                  mask expansion into per-partition receive lists (the
+//                  bridge's forwarding)
+//   stage_batch    receive side: each entry's synapses for its partition,
+//                  staged per delay in per-block queues
+//   deliver_block  per delay: the own-partition synapses of fired sources and
+//                  the staged remote ones, counting-sorted by tile in LDS and
+//                  written as runs into per-(slot, tile, delay, block) bins
+//   k_route_flat   flat routing: one receive entry per destination partition
+//
+// A whole step is three launches: k_update<true> (update, compaction and the
+// tile's own two-level routing, which overlaps the look-back),
+// k_recv_local (expansion and staging beside the own-partition delivery: two
+// independent jobs in one launch) and k_deliver_remote (the staged remote
+// synapses).  The step-by-step entry points use one kernel per job instead
+// (k_update<false>, k_route_two_level, k_expand, k_recv_stage, k_deliver).
 //
 // Global atomics run at roughly 20 G/s on random addresses and serialise on
 // hot counters, so every scatter goes through LDS first: reservations are one
