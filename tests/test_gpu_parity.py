@@ -195,6 +195,15 @@ def test_unfused_fallback_many_nodes():
     _lockstep(wl, 40, route_every=5, state_every=20, mode=ROUTE_TWO_LEVEL, fused=True)
 
 
+def test_direct_route_beyond_lds_nodes():
+    """5,000 nodes of one GPU: more than the routing kernel's LDS counters
+    hold (4,096), so two-level routing takes the unstaged kernel (one atomic
+    per message); buckets, lists and state against the oracle."""
+    wl = synth.get_workload("paper_share").scaled(20_000, n_partitions=5000, gpus_per_node=1)
+    assert wl.n_nodes > 4096
+    _lockstep(wl, 30, route_every=5, state_every=15, mode=ROUTE_BOTH)
+
+
 def test_route_modes_give_identical_rasters():
     wl = synth.get_workload("tiny_active")
     from paper_2205_07125_amd import Simulation
