@@ -14,7 +14,8 @@
  * On one GPU every partition and node other than the GPU's own is a virtual
  * buffer in HBM; groups are nodes of gpus_per_node (<= 8) partitions, so a
  * node's destination set is an 8-bit mask.  One step is three calls, always
- * in this order:
+ * in this order (snn_step_route does the first two in fewer launches, and
+ * snn_run replays whole steps):
  *
  *   snn_step     neuron update and threshold for step t, then compaction of
  *                the fired neuron IDs into an ascending list
@@ -52,8 +53,8 @@
  *  - Device pointers are caller-owned (e.g. torch tensors), borrowed for the
  *    handle's lifetime, never freed by the library.  Host pointers are only
  *    read or written during the call.
- *  - step/route/deliver/run only enqueue work on the handle's stream and
- *    never synchronise.  Device-side capacity overflow is sticky and is
+ *  - step/route/step_route/deliver/run only enqueue work on the handle's
+ *    stream and never synchronise.  Device-side capacity overflow is sticky and is
  *    reported as SNN_ERR_CAPACITY by the next synchronising call
  *    (snn_read_*, snn_sync, snn_destroy); buffers are never silently
  *    truncated.
@@ -109,7 +110,10 @@ enum {
   SNN_NSTAT = 7
 };
 
-/* Kernel kinds of a step, in launch order (snn_kernel_times). */
+/* Kernel kinds of a step, in launch order (snn_kernel_times).  In a whole
+   step as snn_run launches it, UPDATE also routes two-level (up to 512
+   nodes), RECV_STAGE also expands the masks and bins the own-partition
+   synapses, and DELIVER bins the received ones. */
 enum {
   SNN_KERNEL_UPDATE = 0,           /* neuron update, threshold, compaction */
   SNN_KERNEL_ROUTE_TWO_LEVEL = 1,  /* per-node messages with partition masks */
