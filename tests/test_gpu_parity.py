@@ -116,11 +116,12 @@ def test_tiny_lockstep_1000_steps(name, seed):
     assert spikes > (10_000 if name == "tiny_active" else 100)
 
 
-@pytest.mark.parametrize("mode", [ROUTE_TWO_LEVEL, ROUTE_BOTH])
+@pytest.mark.parametrize("mode", [ROUTE_TWO_LEVEL, ROUTE_BOTH, ROUTE_FLAT])
 @pytest.mark.parametrize("name", ["tiny", "tiny_active"])
 def test_fused_route_lockstep(name, mode):
-    """snn_step_route (two-level routing inside the update kernel) against the
-    oracle: the same buckets, lists, counters and state."""
+    """snn_step_route (two-level routing inside the update kernel; flat mode
+    takes the separate kernels) against the oracle: the same buckets, lists,
+    counters and state."""
     wl = synth.get_workload(name).replace(seed=4)
     _lockstep(wl, 300, route_every=10, state_every=50, mode=mode, fused=True)
 
