@@ -127,7 +127,10 @@ enum {
 /* Largest supported sizes. */
 #define SNN_MAX_GPUS_PER_NODE 8u
 #define SNN_MAX_DELAY 15u
-#define SNN_MAX_NEURONS (1u << 27)    /* target ids share 32 bits with the delay */
+#define SNN_MAX_NEURONS (1u << 27)    /* target ids share 32 bits with the delay; the
+                                         deliver kernels' per-tile LDS counters limit a
+                                         handle to about 1e8 (snn_create reports
+                                         SNN_ERR_UNSUPPORTED above that) */
 #define SNN_MAX_PARTITIONS 65535u
 
 /* All by value; validated by snn_workspace_size and snn_create. */

@@ -295,7 +295,15 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.pois_lut, c->pois_lut.data(), POIS_LUT_SIZE, hipMemcpyHostToDevice,
                        c->stream);
-  if (e == hipSuccess) e = prepare_kernels(k);
+  if (e == hipSuccess) {
+    e = prepare_kernels(k);
+    if (e == hipErrorInvalidConfiguration) {
+      delete c;
+      return fail(SNN_ERR_UNSUPPORTED,
+                  "create: %u tiles of neurons leave no deliver window in the device's LDS "
+                  "(about 1e8 neurons at most)", k.n_tiles);
+    }
+  }
   if (e != hipSuccess) {
     delete c;
     return fail(SNN_ERR_HIP, "create: %s", hipGetErrorString(e));
