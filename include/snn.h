@@ -129,7 +129,7 @@ enum {
 #define SNN_MAX_DELAY 15u
 #define SNN_MAX_NEURONS (1u << 27)    /* target ids share 32 bits with the delay; the
                                          deliver kernels' per-tile LDS counters limit a
-                                         handle to about 1e8 (snn_create reports
+                                         handle to about 8e7 (snn_create reports
                                          SNN_ERR_UNSUPPORTED above that) */
 #define SNN_MAX_PARTITIONS 65535u
 

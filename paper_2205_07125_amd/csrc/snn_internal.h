@@ -58,7 +58,6 @@ constexpr uint32_t ROUTE_STAGE = 2048;              // pairs per routing window
 constexpr uint32_t ROUTE_BLOCKS = 256;              // two-level routing blocks
 constexpr uint32_t ROUTE_MAX_NODES_LDS = 4096;      // more nodes: unstaged routing
 constexpr int EXPAND_THREADS = 512;                 // one expansion block per node
-constexpr uint32_t DELIVER_STAGE = 4096;            // staged events per window, at most
 constexpr uint32_t DELIVER_BLOCKS = 32;             // deliver blocks per delay
 constexpr uint32_t STAGE_BLOCKS = 256;              // receive-side blocks (one queue each)
 constexpr uint32_t STAGE_PARTS = 256;               // partitions per receive-side block, at most
@@ -130,9 +129,6 @@ struct KParams {
   uint64_t stage_cap;
   float wq_scale;      // 2^F: weight -> fixed point
   double wq_inv;       // 2^-F
-  uint32_t dstage;     // deliver windows (events), set by prepare_kernels: whole deliver,
-  uint32_t dstage_r;   // its remote part alone,
-  uint32_t dstage_h;   // its local part beside the receive side (k_recv_local)
   // network (caller-owned device memory)
   const int64_t* row_ptr;
   const uint32_t* n_local;
@@ -175,7 +171,7 @@ struct KParams {
 // With non-null marks, events marks[2k], marks[2k + 1] are recorded around
 // each launch of kernel kind k (SNN_KERNEL_*).
 uint32_t tiles_of(uint32_t n);
-hipError_t prepare_kernels(KParams& p);   // LDS sizing (deliver windows), once per handle
+hipError_t prepare_kernels(KParams& p);   // LDS limits of the kernels, once per handle
 // With route, the update kernel also routes the step two-level where the node
 // count allows (fused_route_ok); launch_route is then told so (routed) and
 // launches only what remains (expansion, flat lists).

@@ -1256,40 +1256,44 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
 // deliver: per delay, counting-sort events by tile into private sub-bins
 
 // Block (w, d): the delay-d run of the local segment of fired sources
-// w, w + DELIVER_BLOCKS, ..., then the staging queues q = w (mod
+// w, w + DELIVER_BLOCKS, ..., and the staging queues q = w (mod
 // DELIVER_BLOCKS) of delay d.  Every event lands in ring slot (t + d) mod D,
 // so the block counting-sorts them by tile in LDS and writes each tile's run
 // into sub-bin (slot, tile, d, w).  That sub-bin is written by this block
 // only, once per ring cycle, and read by the tile's update D - d steps later:
 // positions and counts need no atomics.
-// The runs are taken as one flat sequence: one thread per source loads the
-// run's start and length, a block scan concatenates them, and the events are
-// loaded in windows of DELIVER_STAGE with GATHER_UNROLL loads in flight per
-// thread (the owner of an event is found by a power-of-two search).
-// Each window is written out in tile order (a scan of the per-tile counts
-// and a permutation in LDS), so consecutive threads write consecutive
-// positions of one sub-bin.
-// Dynamic LDS: a window of dstage events + tile/rank words + permutation +
-// 3 * n_tiles counters (dstage <= DELIVER_STAGE, set by prepare_kernels to
-// what the device's LDS holds).
-// LOCAL / REMOTE select the parts a block does; a remote-only block appends
-// to the sub-bins after the counts the local part published.  dyn holds
-// deliver_lds_bytes(S, n_tiles) bytes.
-template <bool LOCAL, bool REMOTE>
-__device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint32_t S,
-                              uint64_t* dyn) {
-  Event* s_ev = reinterpret_cast<Event*>(dyn);                            // [S]
-  uint32_t* s_tr = reinterpret_cast<uint32_t*>(s_ev + S);                 // tile | rank << 16
-  uint32_t* l_cnt = s_tr + S;                                             // [n_tiles]
+// The runs (source segments, then queues) are taken as one flat sequence:
+// one thread per segment loads its start and length, a block scan
+// concatenates them, and the events are taken in rounds of DELIVER_ROUND,
+// GATHER_UNROLL per thread held in registers (the owner of an event is found
+// by a power-of-two search).  A round is sorted where it stands: each event's
+// rank in its tile comes from an LDS counter, a scan of the counts gives the
+// tiles' starts, the events are placed in tile order in LDS (8 bytes each),
+// and consecutive threads then write consecutive positions of one sub-bin.
+// PART selects what a block does: DELIVER_ALL; DELIVER_LOCAL (the source
+// segments only, beside the receive side) followed by DELIVER_REMOTE (the
+// queues, appended after the counts the local part published).
+// dyn holds deliver_lds_bytes(n_tiles) bytes.
+enum DeliverPart { DELIVER_ALL, DELIVER_LOCAL, DELIVER_REMOTE };
+constexpr uint32_t DELIVER_ROUND = GATHER_UNROLL * DELIVER_THREADS;
+static_assert(DELIVER_ROUND <= 65536, "window positions fit 16 bits");
+template <DeliverPart PART>
+__device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t* dyn) {
+  constexpr bool LOCAL = PART != DELIVER_REMOTE;
+  constexpr bool REMOTE = PART != DELIVER_LOCAL;
+  constexpr uint32_t NT = DELIVER_THREADS;
+  constexpr uint32_t NW = NT / 64;
+  constexpr uint32_t QPB = STAGE_BLOCKS / DELIVER_BLOCKS;                 // queues per block
+  constexpr uint32_t SRC_BATCH = NT - (REMOTE ? QPB : 0);                 // sources per batch
+  Event* s_sorted = reinterpret_cast<Event*>(dyn);                        // [DELIVER_ROUND]
+  uint32_t* l_cnt = reinterpret_cast<uint32_t*>(s_sorted + DELIVER_ROUND);  // [n_tiles]
   uint32_t* l_run = l_cnt + p.n_tiles;                                    // [n_tiles]
   uint32_t* l_pre = l_run + p.n_tiles;                                    // [n_tiles]
-  uint16_t* s_perm = reinterpret_cast<uint16_t*>(l_pre + p.n_tiles);      // [S]
-  constexpr uint32_t NW = DELIVER_THREADS / 64;
-  constexpr uint32_t QPB = STAGE_BLOCKS / DELIVER_BLOCKS;                 // queues per block
-  __shared__ uint64_t s_base[DELIVER_THREADS];   // first event of each segment
-  __shared__ uint32_t s_pre[DELIVER_THREADS];    // segment starts in the concatenation
+  __shared__ uint64_t s_base[NT];   // first event of each segment (synapse or queue index)
+  __shared__ uint32_t s_pre[NT];    // segment starts in the concatenation
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
+  __shared__ uint32_t s_qc[QPB];    // queue lengths
   const uint32_t tid = threadIdx.x;
 
   const uint32_t nF = p.st->n_fired;
@@ -1297,26 +1301,27 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint32_t
   if (slot >= p.D) slot -= p.D;
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t D = p.D;
-  for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS) {
+  if (REMOTE && tid < QPB) s_qc[tid] = p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS];
+  for (uint32_t i = tid; i < p.n_tiles; i += NT) {
     l_run[i] = LOCAL ? 0u : p.bin_cnt[subbin(p, slot, i, d, w)];
     l_cnt[i] = 0;
   }
+  __syncthreads();
   uint64_t events = 0;
+  const uint64_t dw = (d - 1) * DELIVER_BLOCKS + w;
 
-  // event (global target, quantized weight) into LDS slot k
-  auto put = [&](uint32_t k, uint32_t tgt, int32_t wq) {
-    const uint32_t tile = tgt >> TILE_SHIFT;
-    const uint32_t rk = atomicAdd(&l_cnt[tile], 1u);
-    s_ev[k] = Event{tgt & (TILE - 1), wq};
-    s_tr[k] = tile | (rk << 16);
-  };
-  // write the n staged events into the sub-bins in tile order and advance
-  // the running counts
-  auto flush = [&](uint32_t n) {
+  // sorts the n events of a round (global target tg[v], weight wq[v] of
+  // event v * NT + tid, those with on[v]) by tile and writes them out
+  auto sort_round = [&](uint32_t n, const uint32_t (&tg)[GATHER_UNROLL],
+                        const int32_t (&wq)[GATHER_UNROLL], const bool (&on)[GATHER_UNROLL]) {
+    uint32_t rk[GATHER_UNROLL];
+#pragma unroll
+    for (int v = 0; v < GATHER_UNROLL; ++v)
+      rk[v] = on[v] ? atomicAdd(&l_cnt[tg[v] >> TILE_SHIFT], 1u) : 0u;
     __syncthreads();
     {
-      // exclusive scan of the window's per-tile counts into l_pre
-      const uint32_t per = (p.n_tiles + DELIVER_THREADS - 1) / DELIVER_THREADS;
+      // exclusive scan of the round's per-tile counts into l_pre
+      const uint32_t per = (p.n_tiles + NT - 1) / NT;
       const uint32_t i0 = min(tid * per, p.n_tiles), i1 = min(i0 + per, p.n_tiles);
       uint32_t sum = 0;
       for (uint32_t i = i0; i < i1; ++i) sum += l_cnt[i];
@@ -1328,42 +1333,36 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint32_t
       }
     }
     __syncthreads();
-    for (uint32_t k = tid; k < n; k += DELIVER_THREADS) {
-      const uint32_t tr = s_tr[k];
-      s_perm[l_pre[tr & 0xFFFFu] + (tr >> 16)] = static_cast<uint16_t>(k);
-    }
+#pragma unroll
+    for (int v = 0; v < GATHER_UNROLL; ++v)
+      if (on[v]) s_sorted[l_pre[tg[v] >> TILE_SHIFT] + rk[v]] = Event{tg[v], wq[v]};
     __syncthreads();
-    for (uint32_t j = tid; j < n; j += DELIVER_THREADS) {
-      const uint32_t k = s_perm[j];
-      const uint32_t tile = s_tr[k] & 0xFFFFu;
+    for (uint32_t j = tid; j < n; j += NT) {
+      const Event ev = s_sorted[j];
+      const uint32_t tile = ev.tgt >> TILE_SHIFT;
       const uint64_t pos = static_cast<uint64_t>(l_run[tile]) + (j - l_pre[tile]);
-      if (pos < p.bin_cap) {
-        p.bins[bin_data(p, slot, tile, (d - 1) * DELIVER_BLOCKS + w) + pos] = s_ev[k];
-      } else {
-        ring_fallback(p, slot, (tile << TILE_SHIFT) | s_ev[k].tgt, s_ev[k].wq);
-      }
+      if (pos < p.bin_cap)
+        p.bins[bin_data(p, slot, tile, static_cast<uint32_t>(dw)) + pos] =
+            Event{ev.tgt & (TILE - 1), ev.wq};
+      else
+        ring_fallback(p, slot, ev.tgt, ev.wq);
     }
     __syncthreads();
-    for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS) {
+    for (uint32_t i = tid; i < p.n_tiles; i += NT) {
       l_run[i] += l_cnt[i];
       l_cnt[i] = 0;
     }
     __syncthreads();
   };
 
-  // The window fills with the local synapses of this block's fired sources
-  // and then, in the same window, with the staged remote ones; it is sorted
-  // and written out whenever it is full and once at the end.
-  uint32_t fill = 0;
-  // queue lengths, loaded now so that they are ready when needed
-  const uint32_t qc =
-      REMOTE && tid < QPB ? p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS] : 0u;
-
-  // local synapses of the fired sources assigned to this block, in batches
-  // of one source per thread
+  // segments: this block's fired sources (w + m * DELIVER_BLOCKS), batches of
+  // SRC_BATCH, then, with the last batch, its QPB queues of delay d
   const uint32_t M = LOCAL && nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
-  for (uint32_t m0 = 0; m0 < M; m0 += DELIVER_THREADS) {
-    const uint32_t nsrc = min(M - m0, static_cast<uint32_t>(DELIVER_THREADS));
+  const Event* q0 = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + w) * p.stage_cap;
+  for (uint32_t m0 = 0;; m0 += SRC_BATCH) {
+    const uint32_t nsrc = min(M - min(m0, M), SRC_BATCH);
+    const bool last = m0 + nsrc >= M;
+    const uint32_t nseg = nsrc + (REMOTE && last ? QPB : 0u);
     uint32_t len = 0;
     if (tid < nsrc) {
       const uint32_t s = p.fired[w + (m0 + tid) * DELIVER_BLOCKS];
@@ -1371,78 +1370,52 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint32_t
       const uint32_t a = p.delay_off[o + d - 1], z = p.delay_off[o + d];
       s_base[tid] = static_cast<uint64_t>(p.row_ptr[s]) + a;
       len = z - a;
+      events += len;
+    }
+    if (REMOTE && last && tid >= nsrc && tid < nseg) {
+      s_base[tid] = static_cast<uint64_t>(tid - nsrc) * DELIVER_BLOCKS * p.stage_cap;
+      len = s_qc[tid - nsrc];
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan(len, s_wsum, &tot);
     s_pre[tid] = ex;
     __syncthreads();
-    events += tid == 0 ? tot : 0u;
-    for (uint32_t e0 = 0; e0 < tot;) {
-      const uint32_t n_chunk = min(tot - e0, S - fill);
-      for (uint32_t i0 = 0; i0 < n_chunk; i0 += GATHER_UNROLL * DELIVER_THREADS) {
-        uint32_t td[GATHER_UNROLL];
-        float wt[GATHER_UNROLL];
+    for (uint32_t r0 = 0; r0 < tot; r0 += DELIVER_ROUND) {
+      const uint32_t n = min(tot - r0, DELIVER_ROUND);
+      uint32_t tg[GATHER_UNROLL];
+      int32_t wq[GATHER_UNROLL];
+      bool on[GATHER_UNROLL];
 #pragma unroll
-        for (int v = 0; v < GATHER_UNROLL; ++v) {
-          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_chunk - 1);
-          const uint32_t k = owner_of<DELIVER_THREADS / 2>(s_pre, nsrc, e);
-          const uint64_t x = s_base[k] + (e - s_pre[k]);
-          td[v] = p.tgt_delay[x];
-          wt[v] = load_weight(p, x);
-        }
-#pragma unroll
-        for (int v = 0; v < GATHER_UNROLL; ++v) {
-          const uint32_t le = i0 + v * DELIVER_THREADS + tid;
-          if (le < n_chunk) put(fill + le, td[v] & 0x07FFFFFFu, quantize_w(p, wt[v]));
+      for (int v = 0; v < GATHER_UNROLL; ++v) {
+        const uint32_t i = v * NT + tid;
+        on[v] = i < n;
+        const uint32_t e = r0 + min(i, n - 1);
+        const uint32_t k = owner_of<NT / 2>(s_pre, nseg, e);
+        const uint64_t x = s_base[k] + (e - s_pre[k]);
+        if (PART == DELIVER_LOCAL) {
+          tg[v] = p.tgt_delay[x] & 0x07FFFFFFu;
+          wq[v] = quantize_w(p, load_weight(p, x));
+        } else if (PART == DELIVER_REMOTE) {
+          const Event ev = q0[x];
+          tg[v] = ev.tgt;
+          wq[v] = ev.wq;
+        } else if (k < nsrc) {   // both kinds of segment (one kernel per row)
+          tg[v] = p.tgt_delay[x] & 0x07FFFFFFu;
+          wq[v] = quantize_w(p, load_weight(p, x));
+        } else {
+          const Event ev = q0[x];
+          tg[v] = ev.tgt;
+          wq[v] = ev.wq;
         }
       }
-      e0 += n_chunk;
-      fill += n_chunk;
-      if (fill == S) {
-        flush(fill);
-        fill = 0;
-      }
+      sort_round(n, tg, wq, on);
     }
+    if (last) break;
     __syncthreads();   // s_pre, s_base are rewritten by the next batch
   }
 
-  // remote synapses staged by the receive side for this delay: queues
-  // w + k * DELIVER_BLOCKS, k < QPB, concatenated the same way
-  if (REMOTE) {
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(qc, s_wsum, &tot);
-    if (tid < QPB) s_pre[tid] = ex;
-    __syncthreads();
-    const Event* q0 = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + w) * p.stage_cap;
-    for (uint32_t e0 = 0; e0 < tot;) {
-      const uint32_t n_chunk = min(tot - e0, S - fill);
-      for (uint32_t i0 = 0; i0 < n_chunk; i0 += GATHER_UNROLL * DELIVER_THREADS) {
-        Event x[GATHER_UNROLL];
-#pragma unroll
-        for (int v = 0; v < GATHER_UNROLL; ++v) {
-          const uint32_t e = e0 + min(i0 + v * DELIVER_THREADS + tid, n_chunk - 1);
-          const uint32_t k = owner_of<QPB / 2>(s_pre, QPB, e);
-          x[v] = q0[static_cast<uint64_t>(k) * DELIVER_BLOCKS * p.stage_cap + (e - s_pre[k])];
-        }
-#pragma unroll
-        for (int v = 0; v < GATHER_UNROLL; ++v) {
-          const uint32_t le = i0 + v * DELIVER_THREADS + tid;
-          if (le < n_chunk) put(fill + le, x[v].tgt, x[v].wq);
-        }
-      }
-      e0 += n_chunk;
-      fill += n_chunk;
-      if (fill == S) {
-        flush(fill);
-        fill = 0;
-      }
-    }
-  }
-  if (fill) flush(fill);
-  __syncthreads();
-
   // publish this block's counts for slot `slot`, every tile (zeros included)
-  for (uint32_t i = tid; i < p.n_tiles; i += DELIVER_THREADS)
+  for (uint32_t i = tid; i < p.n_tiles; i += NT)
     p.bin_cnt[subbin(p, slot, i, d, w)] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_run[i]), p.bin_cap));
   if (LOCAL) add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
@@ -1450,14 +1423,14 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint32_t
 
 __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   extern __shared__ uint64_t lds_u64[];
-  deliver_block<true, true>(p, blockIdx.x, blockIdx.y + 1, p.dstage, lds_u64);
+  deliver_block<DELIVER_ALL>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
 }
 
 // The staged remote synapses of (w, d) = (blockIdx.x, blockIdx.y + 1), after
 // k_recv_local delivered the local ones.
 __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver_remote(KParams p) {
   extern __shared__ uint64_t lds_u64[];
-  deliver_block<false, true>(p, blockIdx.x, blockIdx.y + 1, p.dstage_r, lds_u64);
+  deliver_block<DELIVER_REMOTE>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
 }
 
 // Two independent jobs in one launch, so that they overlap: blocks
@@ -1476,7 +1449,7 @@ void k_recv_local(KParams p) {
     expand_stage_block(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
   } else {
     const uint32_t i = blockIdx.x - STAGE_BLOCKS;
-    deliver_block<true, false>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, p.dstage_h, lds_u64);
+    deliver_block<DELIVER_LOCAL>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
   }
 }
 
@@ -1564,12 +1537,10 @@ hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* m
   return hipGetLastError();
 }
 
-// LDS bytes of one deliver event and of the per-tile counters.
-constexpr size_t DELIVER_EVENT_LDS = sizeof(Event) + sizeof(uint32_t) + sizeof(uint16_t);
-static_assert(DELIVER_STAGE <= 65536, "window ranks and permutation fit 16 bits");
-
-static size_t deliver_lds_bytes(uint32_t S, uint32_t n_tiles) {
-  return S * DELIVER_EVENT_LDS + 3ull * n_tiles * sizeof(uint32_t);
+// LDS of a deliver block: a round of events in tile order and three
+// counters per tile.
+static size_t deliver_lds_bytes(uint32_t n_tiles) {
+  return DELIVER_ROUND * sizeof(Event) + 3ull * n_tiles * sizeof(uint32_t);
 }
 
 // Expansion and staging: the entry buffer, and per batch each entry's
@@ -1578,7 +1549,7 @@ constexpr size_t EXPAND_STAGE_LDS =
     EXPAND_BUF * sizeof(uint64_t) + RECV_BATCH * (sizeof(uint64_t) + sizeof(uint32_t));
 
 static size_t recv_local_lds_bytes(const KParams& p) {
-  return std::max(EXPAND_STAGE_LDS, deliver_lds_bytes(p.dstage_h, p.n_tiles));
+  return std::max(EXPAND_STAGE_LDS, deliver_lds_bytes(p.n_tiles));
 }
 
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
@@ -1590,7 +1561,7 @@ hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t*
     mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
     mark(marks, SNN_KERNEL_DELIVER, 0, s);
     hipLaunchKernelGGL(k_deliver_remote, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
-                       deliver_lds_bytes(p.dstage_r, p.n_tiles), s, p);
+                       deliver_lds_bytes(p.n_tiles), s, p);
     mark(marks, SNN_KERNEL_DELIVER, 1, s);
     return hipGetLastError();
   }
@@ -1600,58 +1571,38 @@ hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t*
   mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
   mark(marks, SNN_KERNEL_DELIVER, 0, s);
   hipLaunchKernelGGL(k_deliver, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
-                     deliver_lds_bytes(p.dstage, p.n_tiles), s, p);
+                     deliver_lds_bytes(p.n_tiles), s, p);
   mark(marks, SNN_KERNEL_DELIVER, 1, s);
   return hipGetLastError();
 }
 
-// The largest deliver window (a multiple of DELIVER_THREADS, at most
-// DELIVER_STAGE) whose LDS, with static_bytes of static LDS, fits budget.
-static uint32_t window_for(int64_t budget, size_t static_bytes, uint32_t n_tiles) {
-  const int64_t room = budget - int64_t(static_bytes) - int64_t(3ull * n_tiles * sizeof(uint32_t));
-  const int64_t fit = room > 0 ? (room / int64_t(DELIVER_EVENT_LDS)) & ~int64_t(DELIVER_THREADS - 1) : 0;
-  return static_cast<uint32_t>(std::min<int64_t>(DELIVER_STAGE, fit));
-}
-
 hipError_t prepare_kernels(KParams& p) {
-  int dev = 0, lds_max = 0, lds_cu = 0;
+  int dev = 0, lds_max = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (e == hipSuccess)
-    e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
   hipFuncAttributes fa{}, fr{}, fh{};
   if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_deliver));
   if (e == hipSuccess) e = hipFuncGetAttributes(&fr, reinterpret_cast<const void*>(&k_deliver_remote));
   if (e == hipSuccess) e = hipFuncGetAttributes(&fh, reinterpret_cast<const void*>(&k_recv_local));
   if (e != hipSuccess) return e;
-  // whole deliver and remote part: windows of up to DELIVER_STAGE events,
-  // less where many tiles leave less LDS
-  p.dstage = window_for(lds_max, fa.sharedSizeBytes, p.n_tiles);
-  p.dstage_r = window_for(lds_max, fr.sharedSizeBytes, p.n_tiles);
-  // receive side with local delivery: three blocks per CU where a window of
-  // DELIVER_THREADS or more fits that, else what one block may hold
-  const int64_t third = int64_t(lds_cu) / 3;
-  p.dstage_h = window_for(third, fh.sharedSizeBytes, p.n_tiles);
-  if (p.dstage_h < DELIVER_THREADS || int64_t(fh.sharedSizeBytes + EXPAND_STAGE_LDS) > third)
-    p.dstage_h = window_for(lds_max, fh.sharedSizeBytes, p.n_tiles);
-  if (p.dstage < DELIVER_THREADS || p.dstage_r < DELIVER_THREADS || p.dstage_h < DELIVER_THREADS ||
-      int64_t(fh.sharedSizeBytes + EXPAND_STAGE_LDS) > lds_max)
+  // the deliver kernels' per-tile counters must leave room for a round
+  const size_t dl = deliver_lds_bytes(p.n_tiles), rl = recv_local_lds_bytes(p);
+  if (int64_t(fa.sharedSizeBytes + dl) > lds_max || int64_t(fr.sharedSizeBytes + dl) > lds_max ||
+      int64_t(fh.sharedSizeBytes + rl) > lds_max)
     return hipErrorInvalidConfiguration;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_route_two_level),
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           static_cast<int>(route_kernel_lds_bytes(p)));
   if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dl));
+  if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver_remote),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(deliver_lds_bytes(p.dstage_r, p.n_tiles)));
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dl));
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recv_local),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(recv_local_lds_bytes(p)));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(deliver_lds_bytes(p.dstage, p.n_tiles)));
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rl));
+  return e;
 }
 
 hipError_t launch_flush(const KParams& p, hipStream_t s) {

@@ -301,7 +301,7 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
       delete c;
       return fail(SNN_ERR_UNSUPPORTED,
                   "create: %u tiles of neurons leave no deliver window in the device's LDS "
-                  "(about 1e8 neurons at most)", k.n_tiles);
+                  "(about 8e7 neurons at most)", k.n_tiles);
     }
   }
   if (e != hipSuccess) {
