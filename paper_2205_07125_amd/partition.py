@@ -1,0 +1,169 @@
+"""Neuron -> GPU partitioning (Algorithm 1, Sec. IV-A), on the host.
+
+Inputs are the neuron connection probabilities P[M, M] and the neuron
+weights W[M].  W is the data volume that a neuron sends.  P may be a dense
+array or a scipy sparse matrix; the brain's is very sparse.  The output is
+the neuron -> GPU map PM[M].  The objective is the traffic cut by the map,
+the sum of P[i, j] * W[i] * W[j] over neurons on different GPUs, with every
+GPU's total weight near the mean sum(W) / N.
+
+The paper gives the loop of Algorithm 1 but not its rules.  This module
+reads it so:
+  * Each pass starts every GPU from one seed neuron.  The seeds are N
+    distinct neurons drawn with the pass's seeded generator.
+  * Then the GPUs take turns, in order.  A GPU whose weight is still below
+    the mean takes the unassigned neuron with the largest summed connection
+    probability, in either direction, to its members.  That is x_{i,t}, the
+    neuron that pass t places on GPU i.  A GPU stops once its weight reaches
+    the mean.  The turns end when no unassigned neuron is left, or no GPU is
+    below the mean.  Any neuron still unassigned then goes to the lightest
+    GPU, heaviest neuron first.
+  * After T passes the map kept is the one with the least cut traffic.
+Every GPU then ends below mean + max(W).  When turns run out, the neurons
+left over land on the lightest GPU, which is itself below the mean.
+
+gpu_graph() turns a map into the inputs of Algorithm 2, PG[N, N] and
+WG[N].  Plain numpy / scipy; nothing here runs on the GPU."""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def _sym_csr(P) -> sp.csr_matrix:
+    """P + P^T as CSR, with the diagonal dropped."""
+    A = sp.csr_matrix(P, dtype=np.float64)
+    A = (A + A.T).tocsr()
+    A.setdiag(0.0)
+    A.eliminate_zeros()
+    return A
+
+
+def cut_traffic(P, W: np.ndarray, pm: np.ndarray) -> float:
+    """Sum of P[i, j] * W[i] * W[j] over pairs i, j on different GPUs."""
+    C = sp.coo_matrix(P)
+    W = np.asarray(W, np.float64)
+    diff = pm[C.row] != pm[C.col]
+    return float((C.data[diff] * W[C.row[diff]] * W[C.col[diff]]).sum())
+
+
+def gpu_traffic(P, W: np.ndarray, pm: np.ndarray, n_gpus: int) -> np.ndarray:
+    """Traffic each GPU sends to other GPUs: for GPU g, the sum of
+    P[i, j] * W[i] * W[j] over i on g and j elsewhere."""
+    C = sp.coo_matrix(P)
+    W = np.asarray(W, np.float64)
+    diff = pm[C.row] != pm[C.col]
+    t = C.data[diff] * W[C.row[diff]] * W[C.col[diff]]
+    return np.bincount(pm[C.row[diff]], weights=t, minlength=n_gpus)
+
+
+def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
+                A: sp.csr_matrix | None = None) -> np.ndarray:
+    """One pass of Algorithm 1's loop from the given seed neurons (one per
+    GPU, distinct).  Returns PM[M] in [0, n_gpus)."""
+    W = np.asarray(W, np.float64)
+    M = len(W)
+    if not 1 <= n_gpus <= M:
+        raise ValueError("need 1 <= number of GPUs <= number of neurons")
+    seeds = np.asarray(seeds, np.int64)
+    if len(seeds) != n_gpus or len(np.unique(seeds)) != n_gpus:
+        raise ValueError("need one distinct seed neuron per GPU")
+    A = _sym_csr(P) if A is None else A
+    target = W.sum() / n_gpus
+    pm = np.full(M, -1, np.int64)
+    load = np.zeros(n_gpus)
+    aff = np.zeros((n_gpus, M))               # summed probability to each GPU's members
+    free = np.ones(M, bool)
+
+    def place(i, j):
+        pm[j] = i
+        free[j] = False
+        load[i] += W[j]
+        lo, hi = A.indptr[j], A.indptr[j + 1]
+        aff[i, A.indices[lo:hi]] += A.data[lo:hi]
+
+    for i, j in enumerate(seeds):
+        place(i, int(j))
+    n_free = M - n_gpus
+    while n_free:
+        moved = False
+        for i in range(n_gpus):
+            if not n_free:
+                break
+            if load[i] >= target:
+                continue
+            cand = np.where(free, aff[i], -np.inf)
+            place(i, int(np.argmax(cand)))
+            n_free -= 1
+            moved = True
+        if not moved:
+            break
+    for j in np.where(free)[0][np.argsort(-W[free], kind="stable")]:
+        place(int(np.argmin(load)), int(j))
+    return pm
+
+
+def partition_neurons(P, W: np.ndarray, n_gpus: int, iters: int = 4,
+                      seed: int = 0) -> np.ndarray:
+    """Algorithm 1: `iters` greedy passes from seeded random seed neurons,
+    keeping the map with the least cut traffic.  Returns PM[M]."""
+    W = np.asarray(W, np.float64)
+    A = _sym_csr(P)
+    rng = np.random.default_rng(seed)
+    best, best_cost = None, np.inf
+    for _ in range(max(iters, 1)):
+        pm = greedy_pass(P, W, n_gpus, rng.choice(len(W), n_gpus, replace=False), A)
+        cost = cut_traffic(P, W, pm)
+        if cost < best_cost:
+            best, best_cost = pm, cost
+    return best
+
+
+def gpu_graph(P, W: np.ndarray, pm: np.ndarray, n_gpus: int) -> tuple[np.ndarray, np.ndarray]:
+    """Inputs of Algorithm 2 from a neuron map.  WG[g] is the total weight of
+    the neurons on GPU g.  PG[g, h] is the W-weighted mean of P over the pairs
+    from g to h: sum of P[i, j] * W[i] * W[j], i on g and j on h, divided by
+    WG[g] * WG[h].  PG[g, h] * WG[g] * WG[h] is then exactly the neuron
+    traffic from g to h, so Algorithm 2's objective is the part of Algorithm
+    1's cut that crosses groups."""
+    C = sp.coo_matrix(P)
+    W = np.asarray(W, np.float64)
+    WG = np.bincount(pm, weights=W, minlength=n_gpus)
+    t = C.data * W[C.row] * W[C.col]
+    T = np.bincount(pm[C.row] * n_gpus + pm[C.col], weights=t,
+                    minlength=n_gpus * n_gpus).reshape(n_gpus, n_gpus)
+    np.fill_diagonal(T, 0.0)
+    denom = np.outer(WG, WG)
+    PG = np.divide(T, denom, out=np.zeros_like(T), where=denom > 0)
+    return PG, WG
+
+
+def synthetic_neurons(M: int, n_clusters: int, k_in: float, k_out: float, seed: int,
+                      rate_sigma: float = 0.5) -> tuple[sp.csr_matrix, np.ndarray]:
+    """Seeded clustered connectivity: neurons get random clusters of uneven
+    size.  Each neuron draws about k_in targets in its own cluster and k_out
+    elsewhere, each with a uniform probability in (0, 1].  W is the
+    out-degree times a lognormal rate.  Returns (P as CSR, W)."""
+    rng = np.random.default_rng(seed)
+    cl = np.sort(rng.integers(0, n_clusters, M))
+    rows, cols = [], []
+    members = [np.where(cl == c)[0] for c in range(n_clusters)]
+    for i in range(M):
+        own = members[cl[i]]
+        ni = min(rng.poisson(k_in), len(own))
+        rows.append(np.full(ni, i))
+        cols.append(rng.choice(own, ni, replace=False))
+        no = rng.poisson(k_out)
+        rows.append(np.full(no, i))
+        cols.append(rng.integers(0, M, no))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    keep = r != c
+    P = sp.csr_matrix((1.0 - rng.random(int(keep.sum())), (r[keep], c[keep])), shape=(M, M))
+    P.sum_duplicates()
+    P.data = np.minimum(P.data, 1.0)
+    deg = np.diff(P.indptr).astype(np.float64)
+    W = np.maximum(deg, 1.0) * np.exp(rng.normal(0.0, rate_sigma, M))
+    perm = rng.permutation(M)                 # hide the clusters from the neuron order
+    P = P[perm][:, perm].tocsr()
+    return P, W[perm]

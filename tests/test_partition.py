@@ -1,0 +1,139 @@
+"""Neuron -> GPU partitioning (Algorithm 1, Sec. IV-A) against brute force on
+small cases, planted clusters, its balance bound and closed forms of the
+GPU graph it hands to Algorithm 2.  CPU only."""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2205_07125_amd import grouping as gr
+from paper_2205_07125_amd import partition as pt
+
+
+def _rand_p(M, density, seed):
+    rng = np.random.default_rng(seed)
+    P = (rng.random((M, M)) < density) * rng.random((M, M))
+    np.fill_diagonal(P, 0.0)
+    return P, np.exp(rng.normal(0.0, 0.5, M))
+
+
+def _planted(n_clusters, s, seed, noise=0.0):
+    rng = np.random.default_rng(seed)
+    M = n_clusters * s
+    truth = rng.permutation(np.repeat(np.arange(n_clusters), s))
+    same = truth[:, None] == truth[None, :]
+    P = np.where(same, 0.5 + 0.5 * rng.random((M, M)), noise * rng.random((M, M)))
+    np.fill_diagonal(P, 0.0)
+    return P, np.ones(M), truth
+
+
+def _same_partition(a, b):
+    return len(set(zip(a.tolist(), b.tolist()))) == len(set(a.tolist())) == len(set(b.tolist()))
+
+
+def test_cut_and_gpu_traffic_brute_force():
+    P, W = _rand_p(11, 0.5, 3)
+    pm = np.array([0, 1, 2, 0, 1, 2, 0, 1, 2, 0, 1])
+    want = np.zeros(3)
+    for i in range(11):
+        for j in range(11):
+            if pm[i] != pm[j]:
+                want[pm[i]] += P[i, j] * W[i] * W[j]
+    assert pt.cut_traffic(P, W, pm) == pytest.approx(want.sum(), rel=1e-12)
+    assert np.allclose(pt.gpu_traffic(P, W, pm, 3), want, rtol=1e-12, atol=0)
+    assert pt.cut_traffic(P, W, np.zeros(11, np.int64)) == 0.0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_planted_clusters_recovered(seed):
+    P, W, truth = _planted(4, 6, seed)
+    pm = pt.partition_neurons(P, W, 4, iters=16, seed=seed)
+    assert _same_partition(pm, truth)
+    assert pt.cut_traffic(P, W, pm) == 0.0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_matches_exhaustive_optimum(seed):
+    """8 neurons on 2 GPUs of equal weight, planted clusters with weak noise
+    across: the kept map is the best of all 35 balanced splits."""
+    P, W, truth = _planted(2, 4, seed, noise=0.2)
+    best = np.inf
+    for first in itertools.combinations(range(1, 8), 3):
+        pm = np.ones(8, np.int64)
+        pm[[0, *first]] = 0
+        best = min(best, pt.cut_traffic(P, W, pm))
+    pm = pt.partition_neurons(P, W, 2, iters=8, seed=seed)
+    assert np.bincount(pm).tolist() == [4, 4]
+    assert pt.cut_traffic(P, W, pm) == pytest.approx(best, rel=1e-12)
+
+
+@pytest.mark.parametrize("M,N,seed", [(50, 4, 0), (200, 7, 1), (31, 31, 2), (40, 1, 3)])
+def test_balance_bound_and_cover(M, N, seed):
+    P, W = _rand_p(M, 0.1, seed)
+    pm = pt.partition_neurons(P, W, N, iters=2, seed=seed)
+    assert pm.min() == 0 and pm.max() == N - 1 and len(pm) == M
+    load = np.bincount(pm, weights=W, minlength=N)
+    assert np.all(load < W.sum() / N + W.max())
+    assert load.sum() == pytest.approx(W.sum(), rel=1e-12)
+
+
+def test_beats_random_on_clustered_input():
+    P, W = pt.synthetic_neurons(3000, 12, 15, 3, seed=4)
+    N = 6
+    pm = pt.partition_neurons(P, W, N, iters=2, seed=0)
+    rnd = np.random.default_rng(0).permutation(np.arange(3000) % N)
+    assert pt.cut_traffic(P, W, pm) < 0.6 * pt.cut_traffic(P, W, rnd)
+    assert pt.gpu_traffic(P, W, pm, N).max() < pt.gpu_traffic(P, W, rnd, N).max()
+
+
+def test_sparse_and_dense_inputs_agree():
+    P, W = _rand_p(60, 0.2, 5)
+    seeds = np.array([3, 17, 42])
+    a = pt.greedy_pass(P, W, 3, seeds)
+    b = pt.greedy_pass(sp.csr_matrix(P), W, 3, seeds)
+    assert np.array_equal(a, b)
+    assert np.array_equal(pt.partition_neurons(P, W, 3, iters=3, seed=1),
+                          pt.partition_neurons(sp.csr_matrix(P), W, 3, iters=3, seed=1))
+
+
+def test_more_passes_never_worse():
+    P, W = pt.synthetic_neurons(800, 6, 10, 4, seed=6)
+    one = pt.partition_neurons(P, W, 4, iters=1, seed=2)
+    many = pt.partition_neurons(P, W, 4, iters=6, seed=2)
+    assert pt.cut_traffic(P, W, many) <= pt.cut_traffic(P, W, one)
+
+
+def test_bad_arguments():
+    P, W = _rand_p(5, 0.5, 0)
+    with pytest.raises(ValueError):
+        pt.greedy_pass(P, W, 2, np.array([1, 1]))
+    with pytest.raises(ValueError):
+        pt.greedy_pass(P, W, 6, np.arange(6))
+
+
+def test_gpu_graph_closed_form_constant_p():
+    """P = c for every pair: PG[g, h] = c off the diagonal, whatever the
+    map and the weights."""
+    M, c = 30, 0.375
+    P = np.full((M, M), c)
+    np.fill_diagonal(P, 0.0)
+    W = np.exp(np.random.default_rng(1).normal(0, 0.5, M))
+    pm = np.random.default_rng(2).permutation(np.arange(M) % 4)
+    PG, WG = pt.gpu_graph(P, W, pm, 4)
+    assert np.allclose(PG[~np.eye(4, dtype=bool)], c, rtol=1e-12, atol=0)
+    assert np.all(np.diag(PG) == 0.0)
+    assert np.allclose(WG, np.bincount(pm, weights=W))
+
+
+def test_gpu_graph_feeds_algorithm_2():
+    """Algorithm 2's objective on PG, WG equals the neuron traffic between
+    GPUs of different groups, counted pair by pair."""
+    P, W = _rand_p(40, 0.3, 8)
+    pm = pt.partition_neurons(P, W, 8, iters=2, seed=0)
+    PG, WG = pt.gpu_graph(P, W, pm, 8)
+    assert np.all((PG >= 0) & (PG <= 1))
+    go = gr.group_gpus(PG, WG, 3, iters=2)
+    want = sum(P[i, j] * W[i] * W[j] for i in range(40) for j in range(40)
+               if go[pm[i]] != go[pm[j]])
+    assert gr.inter_group_traffic(PG, WG, go) == pytest.approx(want, rel=1e-12)
