@@ -19,17 +19,16 @@ The paper outlines the algorithm without every rule; this module reads it so:
   * In the first iteration, seeds are taken by decreasing total connection
     probability.  Later iterations take them in a seeded random order.  The
     grouping kept is the one with the least inter-group traffic.
-  * Bridges are spread over the members of a group.  The destination groups
-    are taken by decreasing traffic from g.  Each one goes to the member with
-    the fewest bridge roles so far, ties going to the member with the most
-    traffic to that group.  No GPU then holds more than one role above any
-    other member.  The paper's balance concern (Sec. IV-B) is why: one
-    member bridging every group would carry all of the group's level-2
-    connections.
+  * Bridges are spread over the members of a group, as the paper asks for
+    balanced traffic (Sec. III, Sec. IV-B): one member bridging every group
+    would carry all of the group's level-2 traffic.  The destination groups
+    are taken by decreasing traffic from g.  Each goes to the member with the
+    least level-2 traffic so far.  select_bridges(balance="roles") balances
+    the number of roles instead.
 
 With every pair connected, a GPU in a group of s has s - 1 level-1
-connections.  It bridges about (n_groups - 1) / s groups, each fanning out to
-s GPUs.  That is about s + N / s - 2 connections, which is least at s near
+connections.  On average it bridges (n_groups - 1) / s groups, each fanning
+out to s GPUs.  That is a mean of about s + N / s - 2 connections, which is least at s near
 sqrt(N): 88 for N = 2000, the mean the paper reports for its 2,000 GPUs
 (Sec. VI, Fig. 4).
 
@@ -111,10 +110,23 @@ def group_gpus(PG: np.ndarray, WG: np.ndarray, n_groups: int, iters: int = 8,
     return best
 
 
-def select_bridges(PG: np.ndarray, WG: np.ndarray, group_of: np.ndarray) -> np.ndarray:
+def select_bridges(PG: np.ndarray, WG: np.ndarray, group_of: np.ndarray,
+                   balance: str = "traffic") -> np.ndarray:
     """Returns bridge[g, h], the member of group g that forwards g's traffic
-    to group h.  The entry is -1 on the diagonal.  Roles are balanced over
-    the members."""
+    to group h.  The entry is -1 on the diagonal.  Destination groups are
+    taken by decreasing traffic from g.
+      balance="traffic": each goes to the member with the least level-2
+                         traffic so far, ties to the member with the most
+                         traffic to h, as in scheduling the largest job
+                         first onto the least loaded machine.  No bridge
+                         then carries more than its fair share of g's
+                         level-2 traffic plus the largest single flow.
+      balance="roles":   each goes to the member with the fewest roles so
+                         far, ties to the member with the most traffic to h.
+                         Connection counts come out even, but one bridge may
+                         carry much more traffic than another."""
+    if balance not in ("roles", "traffic"):
+        raise ValueError("balance must be 'roles' or 'traffic'")
     n_groups = int(group_of.max()) + 1
     T = np.asarray(PG, np.float64) * np.outer(WG, WG)
     to_group = np.zeros((len(WG), n_groups))
@@ -124,13 +136,16 @@ def select_bridges(PG: np.ndarray, WG: np.ndarray, group_of: np.ndarray) -> np.n
     for g in range(n_groups):
         members = np.where(group_of == g)[0]
         roles = np.zeros(len(members), np.int64)
+        load = np.zeros(len(members))
+        flow = to_group[members].sum(axis=0)          # g's traffic to each group
         others = [h for h in range(n_groups) if h != g]
-        others.sort(key=lambda h: (-to_group[members, h].sum(), h))
+        others.sort(key=lambda h: (-flow[h], h))
         for h in others:
-            free = roles == roles.min()
+            free = roles == roles.min() if balance == "roles" else load == load.min()
             k = int(np.argmax(np.where(free, to_group[members, h], -np.inf)))
             bridge[g, h] = members[k]
             roles[k] += 1
+            load[k] += flow[h]
     return bridge
 
 
@@ -245,7 +260,7 @@ def partition_graph(part: np.ndarray, vp_ptr: np.ndarray, vp_part: np.ndarray,
 
 
 def routing_report(PG: np.ndarray, WG: np.ndarray, n_groups: int, iters: int = 8,
-                   seed: int = 0) -> dict:
+                   seed: int = 0, balance: str = "traffic") -> dict:
     """Algorithm 2 end to end, and what the paper measures of it (Sec. VI,
     Figs. 3(b) and 4).  Groups, bridges and TB come first.  Then, per GPU,
     the connections under flat and two-level routing, and the traffic T =
@@ -253,7 +268,7 @@ def routing_report(PG: np.ndarray, WG: np.ndarray, n_groups: int, iters: int = 8
     PG = np.asarray(PG, np.float64)
     WG = np.asarray(WG, np.float64)
     go = group_gpus(PG, WG, n_groups, iters, seed)
-    br = select_bridges(PG, WG, go)
+    br = select_bridges(PG, WG, go, balance)
     TB = routing_table(go, br)
     T = PG * np.outer(WG, WG)
     np.fill_diagonal(T, 0.0)

@@ -111,7 +111,39 @@ def _bridges_ok(PG, WG, go, br):
 def test_bridges_balanced_and_in_group():
     PG, WG = _rand_pg(50, 0.4, 2)
     go = gr.group_gpus(PG, WG, 9, iters=2)
-    _bridges_ok(PG, WG, go, gr.select_bridges(PG, WG, go))
+    _bridges_ok(PG, WG, go, gr.select_bridges(PG, WG, go, balance="roles"))
+    with pytest.raises(ValueError):
+        gr.select_bridges(PG, WG, go, balance="random")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_traffic_balanced_bridges_meet_list_scheduling_bound(seed):
+    """Largest flow first onto the least loaded member: no bridge carries
+    more than the mean load of its group's members plus the largest flow
+    (Graham's bound), and the heaviest bridge is no heavier than under
+    role balancing on uneven traffic."""
+    PG, WG = gr.synthetic_pg(160, 20, 0.9, 0.05, seed=seed, wg_sigma=0.8)
+    go = gr.group_gpus(PG, WG, 20, iters=2)
+    T = PG * np.outer(WG, WG)
+    n_groups = go.max() + 1
+    flow = np.array([[T[np.ix_(go == g, go == h)].sum() for h in range(n_groups)]
+                     for g in range(n_groups)])
+    np.fill_diagonal(flow, 0.0)
+    peak = {}
+    for balance in ("traffic", "roles"):
+        br = gr.select_bridges(PG, WG, go, balance=balance)
+        load = np.zeros(len(WG))
+        for g in range(n_groups):
+            for h in range(n_groups):
+                if h != g:
+                    assert go[br[g, h]] == g
+                    load[br[g, h]] += flow[g, h]
+        peak[balance] = load.max()
+        if balance == "traffic":
+            for g in range(n_groups):
+                m = go == g
+                assert load[m].max() <= flow[g].sum() / m.sum() + flow[g].max() + 1e-9
+    assert peak["traffic"] <= peak["roles"]
 
 
 def test_bridge_prefers_member_with_traffic():
@@ -168,7 +200,7 @@ def test_connections_closed_form_full_exchange():
     N, s = 48, 6
     PG = np.ones((N, N)) - np.eye(N)
     go = gr.group_gpus(PG, np.ones(N), N // s, iters=1)
-    br = gr.select_bridges(PG, np.ones(N), go)
+    br = gr.select_bridges(PG, np.ones(N), go, balance="roles")
     conn = gr.connections(PG, gr.routing_table(go, br))
     roles = np.array([np.count_nonzero(br == i) for i in range(N)])
     assert np.array_equal(conn, (s - 1) + roles * s)
