@@ -42,3 +42,54 @@ def link_traffic(sim, part: np.ndarray, two_level: bool = True) -> dict:
                    max_node_link=int(nm.max()) if nm.size else 0,
                    connections_two_level=(nm > 0).sum(axis=1))
     return out
+
+
+def bridge_load(node_matrix: np.ndarray, gpus_per_node: int, policy: str = "balanced") -> dict:
+    """Receive-side bridges of two-level routing: which GPU of node n takes
+    the level-2 messages of source partition p, and then expands their masks
+    for the node (Sec. IV-B).  node_matrix[p, n] counts messages from p to n
+    (link_traffic's node_matrix).  Messages to the source's own node are
+    level 1 and need no bridge.
+      policy="fixed":    the node's first GPU bridges everything.
+      policy="rotate":   GPU p mod G of the node, so that the sources take
+                         turns whatever their traffic.
+      policy="balanced": per node, the sources by decreasing message count,
+                         each onto the member with the fewest level-2
+                         messages so far (largest job first, least loaded
+                         machine; ties to the lower GPU).  No member then
+                         takes more than the node's mean plus one source's
+                         messages.
+    Returns dict:
+      bridge [P][n_nodes]   receiving GPU (partition id), -1 where p sends
+                            nothing or n is p's own node
+      load [P]              level-2 messages each partition receives as a bridge
+      peak                  load.max()
+      connections [P]       distinct bridges each source partition sends to
+    The bridge choice does not change what is delivered, only where the
+    level-2 messages land."""
+    nm = np.asarray(node_matrix, np.int64)
+    P, n_nodes = nm.shape
+    G = int(gpus_per_node)
+    if policy not in ("fixed", "rotate", "balanced"):
+        raise ValueError("policy must be 'fixed', 'rotate' or 'balanced'")
+    own = np.arange(P) // G
+    bridge = np.full((P, n_nodes), -1, np.int64)
+    load = np.zeros(P, np.int64)
+    for n in range(n_nodes):
+        members = np.arange(n * G, min((n + 1) * G, P))
+        srcs = np.nonzero((nm[:, n] > 0) & (own != n))[0]
+        if not len(srcs) or not len(members):
+            continue
+        if policy == "fixed":
+            bridge[srcs, n] = members[0]
+        elif policy == "rotate":
+            bridge[srcs, n] = members[srcs % len(members)]
+        else:
+            acc = np.zeros(len(members), np.int64)
+            for p in srcs[np.argsort(-nm[srcs, n], kind="stable")]:
+                k = int(np.argmin(acc))
+                bridge[p, n] = members[k]
+                acc[k] += nm[p, n]
+        np.add.at(load, bridge[srcs, n], nm[srcs, n])
+    conn = (bridge >= 0).sum(axis=1)
+    return dict(bridge=bridge, load=load, peak=int(load.max()) if P else 0, connections=conn)

@@ -5,6 +5,7 @@ connection counts."""
 import types
 
 import numpy as np
+import pytest
 
 from paper_2205_07125_amd.links import link_traffic
 
@@ -50,3 +51,50 @@ def test_link_traffic_flat_only():
     got = link_traffic(_FakeSim(lists, None, 2, 1), part, two_level=False)
     assert np.array_equal(got["partition_matrix"], np.array([[0, 1], [1, 0]]))
     assert "node_matrix" not in got
+
+
+def test_bridge_load_hand_example():
+    from paper_2205_07125_amd.links import bridge_load
+    # 4 partitions on 2 nodes of 2; messages per (source partition, node)
+    nm = np.array([[9, 5],      # p0 (node 0): 5 level-2 messages to node 1
+                   [0, 3],      # p1 (node 0): 3 to node 1
+                   [4, 7],      # p2 (node 1): 4 to node 0
+                   [2, 1]])     # p3 (node 1): 2 to node 0
+    f = bridge_load(nm, 2, "fixed")
+    assert f["bridge"].tolist() == [[-1, 2], [-1, 2], [0, -1], [0, -1]]
+    assert f["load"].tolist() == [6, 0, 8, 0] and f["peak"] == 8
+    r = bridge_load(nm, 2, "rotate")
+    assert r["bridge"].tolist() == [[-1, 2], [-1, 3], [0, -1], [1, -1]]
+    assert r["load"].tolist() == [4, 2, 5, 3] and r["peak"] == 5
+    b = bridge_load(nm, 2, "balanced")
+    assert b["load"].tolist() == [4, 2, 5, 3]
+    assert f["connections"].tolist() == [1, 1, 1, 1]
+
+
+def test_bridge_load_policies_on_random_traffic():
+    from paper_2205_07125_amd.links import bridge_load
+    rng = np.random.default_rng(5)
+    P, G = 40, 8
+    nm = rng.poisson(rng.gamma(0.7, 6.0, (P, P // G)))
+    own = np.arange(P) // G
+    level2 = nm.copy()
+    level2[np.arange(P), own] = 0
+    res = {pol: bridge_load(nm, G, pol) for pol in ("fixed", "rotate", "balanced")}
+    for pol, r in res.items():
+        # every level-2 message lands on one member of its destination node
+        assert r["load"].sum() == level2.sum()
+        br = r["bridge"]
+        sent = level2 > 0
+        assert np.all((br >= 0) == sent)
+        assert np.all(br[sent] // G == np.nonzero(sent)[1])
+        assert np.array_equal(r["connections"], sent.sum(axis=1))
+    # the fixed bridge takes the whole node's level-2 inflow
+    assert res["fixed"]["peak"] == level2.sum(axis=0).max()
+    # list-scheduling bound per node for the balanced policy
+    load = res["balanced"]["load"]
+    for n in range(P // G):
+        m = slice(n * G, (n + 1) * G)
+        assert load[m].max() <= level2[:, n].sum() / G + level2[:, n].max()
+    assert res["balanced"]["peak"] <= res["fixed"]["peak"]
+    with pytest.raises(ValueError):
+        bridge_load(nm, G, "random")
