@@ -72,7 +72,8 @@ def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
     target = W.sum() / n_gpus
     pm = np.full(M, -1, np.int64)
     load = np.zeros(n_gpus)
-    aff = np.zeros((n_gpus, M))               # summed probability to each GPU's members
+    # summed probability from each GPU's members to each neuron; -inf once placed
+    aff = np.zeros((n_gpus, M))
     free = np.ones(M, bool)
 
     def place(i, j):
@@ -81,6 +82,7 @@ def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
         load[i] += W[j]
         lo, hi = A.indptr[j], A.indptr[j + 1]
         aff[i, A.indices[lo:hi]] += A.data[lo:hi]
+        aff[:, j] = -np.inf
 
     for i, j in enumerate(seeds):
         place(i, int(j))
@@ -92,8 +94,7 @@ def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
                 break
             if load[i] >= target:
                 continue
-            cand = np.where(free, aff[i], -np.inf)
-            place(i, int(np.argmax(cand)))
+            place(i, int(np.argmax(aff[i])))
             n_free -= 1
             moved = True
         if not moved:
