@@ -285,3 +285,39 @@ def routing_report(PG: np.ndarray, WG: np.ndarray, n_groups: int, iters: int = 8
                 level2_flat=level2_flat, level2_two_level=level2_two,
                 peak_level2_flat=float(level2_flat.max()),
                 peak_level2_two_level=float(level2_two.max()))
+
+
+def _main(argv=None) -> None:
+    """Connections per GPU, flat against two-level, on a seeded random PG in
+    which a GPU reaches a given mean number of others.  This is the count of
+    Sec. VI, Fig. 4."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(prog="python -m paper_2205_07125_amd.grouping")
+    ap.add_argument("--gpus", type=int, default=2000)
+    ap.add_argument("--reach", type=float, default=1552.0,
+                    help="mean number of GPUs each GPU sends to")
+    ap.add_argument("--group-size", type=int, default=0,
+                    help="GPUs per group (default: dense_group_size)")
+    ap.add_argument("--iters", type=int, default=1)
+    ap.add_argument("--balance", choices=["traffic", "roles"], default="traffic")
+    ap.add_argument("--seed", type=int, default=2205)
+    a = ap.parse_args(argv)
+    n = a.gpus
+    rng = np.random.default_rng(a.seed)
+    PG = (rng.random((n, n)) < a.reach / max(n - 1, 1)) * rng.random((n, n))
+    np.fill_diagonal(PG, 0.0)
+    WG = np.exp(rng.normal(0.0, 0.3, n))
+    s = a.group_size or dense_group_size(n)
+    r = routing_report(PG, WG, -(-n // s), a.iters, a.seed, a.balance)
+    print(json.dumps({
+        "gpus": n, "group_size": s, "groups": -(-n // s),
+        "mean_connections_flat": round(r["mean_connections_flat"], 2),
+        "mean_connections_two_level": round(r["mean_connections_two_level"], 2),
+        "max_connections_two_level": int(r["connections_two_level"].max()),
+        "peak_level2_flat": round(r["peak_level2_flat"], 1),
+        "peak_level2_two_level": round(r["peak_level2_two_level"], 1)}))
+
+
+if __name__ == "__main__":
+    _main()

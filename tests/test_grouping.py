@@ -295,3 +295,13 @@ def test_routing_report_consistent():
     bridges = set(r["bridge"][r["bridge"] >= 0].tolist())
     assert all(k in bridges for k in np.nonzero(r["level2_two_level"])[0])
     assert r["mean_connections_two_level"] <= r["mean_connections_flat"]
+
+
+def test_command_line_report(capsys):
+    import json
+    gr._main(["--gpus", "100", "--reach", "99", "--group-size", "10"])
+    out = json.loads(capsys.readouterr().out)
+    # every pair connected, groups of 10: s + n_groups - 2 = 18 on average
+    assert out["mean_connections_flat"] == 99
+    assert out["mean_connections_two_level"] == 18
+    assert out["groups"] == 10
