@@ -68,9 +68,11 @@ def _same_routes(sim, orc, wl, where, mode=ROUTE_BOTH):
             assert np.array_equal(g, np.sort(b_o[n])), f"bucket {n} at {where}"
 
 
-def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH, fused=False):
+def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH, fused=False,
+              fp64_bound=1e-4):
     """fused: each step as snn_step_route + snn_deliver (two-level routing in
-    the update kernel) instead of snn_step, snn_route, snn_deliver."""
+    the update kernel) instead of snn_step, snn_route, snn_deliver.
+    fp64_bound: largest |u - u_fp64| allowed (mV); None reports it only."""
     sim, orc = _pair(wl, log_steps=n_steps)
     stats_o = np.zeros((n_steps, 7), np.uint64)
     fired_o = []
@@ -100,9 +102,13 @@ def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH, fused=Fals
     g, o = _same_state(sim, orc, "end")
     # FP64 trajectory: device u within 1e-4 mV while the rasters agree
     acc = orc.accuracy()
-    if acc["first_divergence"] < 0:
-        assert np.max(np.abs(g["u"].astype(np.float64) - o["u64"])) < 1e-4
-    assert acc["max_dv"] < 1e-4
+    if fp64_bound is None:
+        print(f"[gpu] {wl.name}: max |u - u_fp64| = {acc['max_dv']:.3e} mV, "
+              f"max |u| = {np.max(np.abs(o['u64'])):.1f} mV", flush=True)
+    else:
+        if acc["first_divergence"] < 0:
+            assert np.max(np.abs(g["u"].astype(np.float64) - o["u64"])) < fp64_bound
+        assert acc["max_dv"] < fp64_bound
     return sim, orc, stats_o
 
 

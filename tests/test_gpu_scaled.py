@@ -24,7 +24,21 @@ SCALED = {
     # oracle stays small
     "heavy": lambda: synth.get_workload("heavy").scaled(12_000, k_in=1500, period_steps=40,
                                                         on_steps=10),
+    # the same at the full in-degree of 10,000 (1.2e8 synapses, bins sized
+    # for bursts of 1.2e6 events per step)
+    "heavy_full_k": lambda: synth.get_workload("heavy").scaled(12_000, period_steps=40,
+                                                               on_steps=10),
 }
+
+
+# Where the FP64 bound of 1e-4 mV is not checked, and why.  At the full
+# in-degree of 10,000, inhibition drives |u| to about 400 mV, where binary32's
+# spacing is 2^-15 mV (3e-5): the rounding of u * alpha and u + I alone
+# drifts the FP32 state by 2.8e-4 mV from the FP64 trajectory within 80
+# steps, in the oracle's own binary32 trajectory too.  That is the stated
+# precision's limit, not the kernels': the device still equals the oracle's
+# binary32 trajectory bit for bit.
+FP64_UNCHECKED = {"heavy_full_k"}
 
 
 @pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
@@ -37,7 +51,8 @@ def test_scaled_workload_lockstep(name, fused):
     wl = SCALED[name]()
     steps = 80
     _, orc, stats = _lockstep(wl, steps, route_every=8, state_every=40, mode=ROUTE_BOTH,
-                              fused=fused)
+                              fused=fused,
+                              fp64_bound=None if name in FP64_UNCHECKED else 1e-4)
     assert stats[:, 0].sum() > 0
     print(f"[gpu] {name}: {int(stats[:, 0].sum())} spikes, "
           f"{int(stats[:, 1].sum() + stats[:, 2].sum())} events, "
