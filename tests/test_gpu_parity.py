@@ -100,7 +100,7 @@ def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH, fused=Fals
         stats_o[:, 6] = 0
     assert np.array_equal(stats_g, stats_o)
     g, o = _same_state(sim, orc, "end")
-    # FP64 trajectory: device u within 1e-4 mV while the rasters agree
+    # FP64 trajectory: device u within fp64_bound while the rasters agree
     acc = orc.accuracy()
     if fp64_bound is None:
         print(f"[gpu] {wl.name}: max |u - u_fp64| = {acc['max_dv']:.3e} mV, "
