@@ -63,6 +63,7 @@ def greedy_groups(PG: np.ndarray, WG: np.ndarray, n_groups: int,
         order = np.argsort(-sym.sum(axis=1), kind="stable")
     group_of = np.full(N, -1, np.int64)
     size = np.zeros(n_groups, np.int64)
+    n_free = N
     g = 0
     for s in order:
         if g == n_groups:
@@ -71,20 +72,21 @@ def greedy_groups(PG: np.ndarray, WG: np.ndarray, n_groups: int,
             continue
         group_of[s] = g
         size[g] = 1
+        n_free -= 1
         vol = WG[s]
         affinity = sym[s].copy()
-        while size[g] < cap and vol < target:
+        # grow, but leave one unassigned GPU to seed each group still to open
+        while size[g] < cap and vol < target and n_free > n_groups - g - 1:
             cand = np.where(group_of < 0, affinity, -np.inf)
             j = int(np.argmax(cand))
-            if group_of[j] >= 0:          # nobody left
-                break
             group_of[j] = g
             size[g] += 1
+            n_free -= 1
             vol += WG[j]
             affinity += sym[j]
         g += 1
     # Leftover GPUs: most connected group with room.  Every group is open by
-    # now, or every GPU is placed, since n_groups <= N.
+    # now: each growth step left a GPU for every group still to open.
     for i in np.where(group_of < 0)[0]:
         strength = np.bincount(group_of[group_of >= 0], weights=sym[i, group_of >= 0],
                                minlength=n_groups)
@@ -128,6 +130,8 @@ def select_bridges(PG: np.ndarray, WG: np.ndarray, group_of: np.ndarray,
     if balance not in ("roles", "traffic"):
         raise ValueError("balance must be 'roles' or 'traffic'")
     n_groups = int(group_of.max()) + 1
+    if np.any(np.bincount(group_of, minlength=n_groups) == 0):
+        raise ValueError("every group id below the largest must have members")
     T = np.asarray(PG, np.float64) * np.outer(WG, WG)
     to_group = np.zeros((len(WG), n_groups))
     for h in range(n_groups):

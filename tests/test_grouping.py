@@ -74,11 +74,16 @@ def test_more_iterations_never_worse():
     assert np.array_equal(gr.group_gpus(PG, WG, 8, iters=1), first)
 
 
-@pytest.mark.parametrize("N,n_groups", [(10, 3), (64, 8), (37, 5), (7, 7), (5, 1)])
+@pytest.mark.parametrize("N,n_groups", [(10, 3), (64, 8), (37, 5), (7, 7), (5, 1), (5, 4),
+                                        (9, 8), (17, 16)])
 def test_groups_cover_and_respect_cap(N, n_groups):
     PG, WG = _rand_pg(N, 0.5, N)
     go = gr.group_gpus(PG, WG, n_groups, iters=3)
     sizes = np.bincount(go, minlength=n_groups)
+    # no group left empty, also with equal volumes and a full PG
+    full = np.bincount(gr.greedy_groups(np.ones((N, N)) - np.eye(N), np.ones(N), n_groups),
+                       minlength=n_groups)
+    assert full.min() >= 1 and full.max() <= -(-N // n_groups)
     assert len(sizes) == n_groups and sizes.min() >= 1
     assert sizes.max() <= -(-N // n_groups) and sizes.sum() == N
     with pytest.raises(ValueError):
@@ -114,6 +119,8 @@ def test_bridges_balanced_and_in_group():
     _bridges_ok(PG, WG, go, gr.select_bridges(PG, WG, go, balance="roles"))
     with pytest.raises(ValueError):
         gr.select_bridges(PG, WG, go, balance="random")
+    with pytest.raises(ValueError):
+        gr.select_bridges(PG, WG, np.where(go == 0, go.max() + 1, go))   # group 0 empty
 
 
 @pytest.mark.parametrize("seed", range(3))
