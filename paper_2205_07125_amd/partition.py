@@ -19,8 +19,9 @@ reads it so:
     below the mean.  Any neuron still unassigned then goes to the lightest
     GPU, heaviest neuron first.
   * After T passes the map kept is the one with the least cut traffic.
-Every GPU then ends below mean + max(W).  When turns run out, the neurons
-left over land on the lightest GPU, which is itself below the mean.
+Every GPU then ends below mean + max(W): it takes a neuron only while below
+the mean.  Turns end with neurons left over only when every GPU has reached
+the mean, so all weight is placed already and the leftovers weigh nothing.
 
 gpu_graph() turns a map into the inputs of Algorithm 2, PG[N, N] and
 WG[N].  Plain numpy / scipy; nothing here runs on the GPU."""
