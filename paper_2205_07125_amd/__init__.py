@@ -7,6 +7,10 @@ binding over it: ``_abi`` mirrors the C declarations under the same names,
 ``network`` drives the host setup entry points, ``sim`` owns the device
 tensors and the stream.  There is no CPU fallback: without libsnn.so (or
 without a GPU) the calls raise.
+
+``partition`` (Algorithm 1), ``grouping`` (Algorithm 2) and ``links``
+(per-link traffic and bridge choice) are host-side setup and analysis in
+numpy / scipy; they are imported on demand and run nothing on the GPU.
 """
 from ._abi import (  # noqa: F401
     SNN_ROUTE_BOTH,
