@@ -9,8 +9,10 @@ GPU's total weight near the mean sum(W) / N.
 
 The paper gives the loop of Algorithm 1 but not its rules.  This module
 reads it so:
-  * Each pass starts every GPU from one seed neuron.  The seeds are N
-    distinct neurons drawn with the pass's seeded generator.
+  * Each pass starts every GPU from one seed neuron.  The first pass takes
+    them farthest-first: the heaviest neuron, then each time the neuron
+    least connected to the seeds so far, so that separate clusters each get
+    a seed.  Later passes draw N distinct neurons with a seeded generator.
   * Then the GPUs take turns, in order.  A GPU whose weight is still below
     the mean takes the unassigned neuron with the largest summed connection
     probability, in either direction, to its members.  That is x_{i,t}, the
@@ -105,16 +107,37 @@ def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
     return pm
 
 
+def spread_seeds(A: sp.csr_matrix, W: np.ndarray, n_gpus: int) -> np.ndarray:
+    """Farthest-first seeds: the heaviest neuron (lowest id on ties), then
+    repeatedly the neuron with the least summed connection probability to
+    the seeds so far (lowest id on ties).  Clusters with no links between
+    them each get a seed before any cluster gets a second."""
+    M = len(W)
+    seeds = [int(np.argmax(W))]
+    tot = np.zeros(M)
+    taken = np.zeros(M, bool)
+    for _ in range(n_gpus - 1):
+        j = seeds[-1]
+        taken[j] = True
+        lo, hi = A.indptr[j], A.indptr[j + 1]
+        tot[A.indices[lo:hi]] += A.data[lo:hi]
+        seeds.append(int(np.argmin(np.where(taken, np.inf, tot))))
+    return np.array(seeds, np.int64)
+
+
 def partition_neurons(P, W: np.ndarray, n_gpus: int, iters: int = 4,
                       seed: int = 0) -> np.ndarray:
-    """Algorithm 1: `iters` greedy passes from seeded random seed neurons,
-    keeping the map with the least cut traffic.  Returns PM[M]."""
+    """Algorithm 1: `iters` greedy passes, the first from spread_seeds and
+    the others from seeded random seed neurons, keeping the map with the
+    least cut traffic.  Returns PM[M]."""
     W = np.asarray(W, np.float64)
     A = _sym_csr(P)
     rng = np.random.default_rng(seed)
     best, best_cost = None, np.inf
-    for _ in range(max(iters, 1)):
-        pm = greedy_pass(P, W, n_gpus, rng.choice(len(W), n_gpus, replace=False), A)
+    for t in range(max(iters, 1)):
+        seeds = (spread_seeds(A, W, n_gpus) if t == 0
+                 else rng.choice(len(W), n_gpus, replace=False))
+        pm = greedy_pass(P, W, n_gpus, seeds, A)
         cost = cut_traffic(P, W, pm)
         if cost < best_cost:
             best, best_cost = pm, cost
@@ -169,3 +192,19 @@ def synthetic_neurons(M: int, n_clusters: int, k_in: float, k_out: float, seed: 
     perm = rng.permutation(M)                 # hide the clusters from the neuron order
     P = P[perm][:, perm].tocsr()
     return P, W[perm]
+
+
+def plan(P, W: np.ndarray, n_gpus: int, n_groups: int, iters: int = 4, seed: int = 0,
+         balance: str = "traffic") -> dict:
+    """The paper's setup end to end (Sec. IV).  Algorithm 1 maps neurons to
+    GPUs.  gpu_graph() derives the GPU graph.  Algorithm 2 groups the GPUs,
+    picks the bridges and builds the routing table.  Returns
+    grouping.routing_report's dict plus PM (neuron -> GPU), PG, WG, the cut
+    traffic of the map, and the per-GPU traffic that leaves its GPU."""
+    from . import grouping
+    pm = partition_neurons(P, W, n_gpus, iters, seed)
+    PG, WG = gpu_graph(P, W, pm, n_gpus)
+    rep = grouping.routing_report(PG, WG, n_groups, iters, seed, balance)
+    rep.update(PM=pm, PG=PG, WG=WG, cut_traffic=cut_traffic(P, W, pm),
+               gpu_traffic=gpu_traffic(P, W, pm, n_gpus))
+    return rep

@@ -137,3 +137,46 @@ def test_gpu_graph_feeds_algorithm_2():
     want = sum(P[i, j] * W[i] * W[j] for i in range(40) for j in range(40)
                if go[pm[i]] != go[pm[j]])
     assert gr.inter_group_traffic(PG, WG, go) == pytest.approx(want, rel=1e-12)
+
+
+def test_plan_recovers_two_levels_of_structure():
+    """Neurons in 12 clusters of 10, clusters in 4 super-clusters of 3:
+    strong links inside a cluster, weaker ones inside a super-cluster, none
+    across.  Algorithm 1 puts each cluster on one GPU, Algorithm 2 puts each
+    super-cluster's GPUs in one group, so no traffic crosses groups and every
+    GPU talks only to its own group."""
+    rng = np.random.default_rng(11)
+    n_cl, per, sup = 12, 10, 3
+    M = n_cl * per
+    perm = rng.permutation(M)
+    cluster = np.repeat(np.arange(n_cl), per)[perm]
+    group = cluster // sup
+    same_c = cluster[:, None] == cluster[None, :]
+    same_g = group[:, None] == group[None, :]
+    P = np.where(same_c, 0.9, np.where(same_g, 0.05, 0.0)) * (0.5 + 0.5 * rng.random((M, M)))
+    np.fill_diagonal(P, 0.0)
+    W = np.ones(M)
+    r = pt.plan(sp.csr_matrix(P), W, n_cl, n_cl // sup, iters=16, seed=3)
+    assert _same_partition(r["PM"], cluster)
+    assert _same_partition(r["group_of"][r["PM"]], group)
+    assert r["inter_group_traffic"] == 0.0
+    # flat: a GPU reaches the other two GPUs of its super-cluster; two-level:
+    # the same two, inside its group, and nothing else
+    assert np.all(r["connections_flat"] == sup - 1)
+    assert np.all(r["connections_two_level"] == sup - 1)
+    assert r["cut_traffic"] == pytest.approx(r["gpu_traffic"].sum(), rel=1e-12)
+    assert r["peak_level2_two_level"] == 0.0
+
+
+def test_spread_seeds_one_per_separate_cluster():
+    """Clusters with no links between them: the first seeds fall in distinct
+    clusters, the heaviest neuron first."""
+    rng = np.random.default_rng(4)
+    cl = rng.permutation(np.repeat(np.arange(7), 9))
+    P = np.where(cl[:, None] == cl[None, :], rng.random((63, 63)), 0.0)
+    np.fill_diagonal(P, 0.0)
+    W = rng.random(63)
+    seeds = pt.spread_seeds(pt._sym_csr(P), W, 7)
+    assert seeds[0] == int(np.argmax(W))
+    assert len(set(cl[seeds].tolist())) == 7
+    assert len(set(seeds.tolist())) == 7
