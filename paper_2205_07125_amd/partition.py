@@ -208,3 +208,30 @@ def plan(P, W: np.ndarray, n_gpus: int, n_groups: int, iters: int = 4, seed: int
     rep.update(PM=pm, PG=PG, WG=WG, cut_traffic=cut_traffic(P, W, pm),
                gpu_traffic=gpu_traffic(P, W, pm, n_gpus))
     return rep
+
+
+def device_layout(pm: np.ndarray, group_of: np.ndarray, gpus_per_node: int) -> dict:
+    """The renumbering that puts a plan on the device path's layout.  The
+    device takes each partition as a contiguous range of neuron ids, and
+    node n as partitions [n G, (n+1) G).  Groups must all have G members.
+    Returns
+      partition_id [N]    new id of each GPU: groups in order, members by old id
+      neuron_id [M]       new id of each neuron: by new partition, then by old id
+      starts [N + 1]      first new neuron id of each new partition
+    so that neuron_id[i] lies in [starts[q], starts[q + 1]) with
+    q = partition_id[pm[i]], and q div G is the group of pm[i]."""
+    from . import grouping
+    pm = np.asarray(pm, np.int64)
+    group_of = np.asarray(group_of, np.int64)
+    G = int(gpus_per_node)
+    sizes = np.bincount(group_of)
+    if G < 1 or np.any(sizes != G):
+        raise ValueError("every group must hold exactly gpus_per_node GPUs")
+    part_id = grouping.relabel(group_of)
+    new_part = part_id[pm]
+    order = np.lexsort((np.arange(len(pm)), new_part))
+    neuron_id = np.empty(len(pm), np.int64)
+    neuron_id[order] = np.arange(len(pm))
+    starts = np.zeros(len(group_of) + 1, np.int64)
+    starts[1:] = np.cumsum(np.bincount(new_part, minlength=len(group_of)))
+    return dict(partition_id=part_id, neuron_id=neuron_id, starts=starts)

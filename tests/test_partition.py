@@ -180,3 +180,24 @@ def test_spread_seeds_one_per_separate_cluster():
     assert seeds[0] == int(np.argmax(W))
     assert len(set(cl[seeds].tolist())) == 7
     assert len(set(seeds.tolist())) == 7
+
+
+def test_device_layout_contiguous_ranges():
+    rng = np.random.default_rng(8)
+    M, N, G = 200, 12, 4
+    pm = rng.integers(0, N, M)
+    group_of = rng.permutation(np.repeat(np.arange(N // G), G))
+    lay = pt.device_layout(pm, group_of, G)
+    q = lay["partition_id"][pm]
+    nid, st = lay["neuron_id"], lay["starts"]
+    assert sorted(nid.tolist()) == list(range(M))
+    assert sorted(lay["partition_id"].tolist()) == list(range(N))
+    assert np.all((st[q] <= nid) & (nid < st[q + 1]))
+    assert np.array_equal(np.diff(st), np.bincount(q, minlength=N))
+    assert np.array_equal(lay["partition_id"] // G, group_of)      # node = group
+    # old order kept inside a partition
+    for p in range(N):
+        ids = np.where(q == p)[0]
+        assert np.all(np.diff(nid[ids]) == 1)
+    with pytest.raises(ValueError):
+        pt.device_layout(pm, np.array([0] * 5 + [1] * 7), G)
