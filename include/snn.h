@@ -12,10 +12,10 @@
  * it improves on (Sec. II, Table II) is kept beside it.
  *
  * On one GPU every partition and node other than the GPU's own is a virtual
- * buffer in HBM; groups are nodes of gpus_per_node (<= 8) partitions, so a
- * node's destination set is an 8-bit mask.  One step is three calls, always
- * in this order (snn_step_route does the first two in fewer launches, and
- * snn_run replays whole steps):
+ * buffer in HBM; groups are nodes of gpus_per_node (<= 64) consecutive
+ * partitions, so a node's destination set is a mask of up to 64 bits.  One
+ * step is three calls, always in this order (snn_step_route does the first
+ * two in fewer launches, and snn_run replays whole steps):
  *
  *   snn_step     neuron update and threshold for step t, then compaction of
  *                the fired neuron IDs into an ascending list
@@ -111,9 +111,9 @@ enum {
 };
 
 /* Kernel kinds of a step, in launch order (snn_kernel_times).  In a whole
-   step as snn_run launches it, UPDATE also routes two-level (up to 512
-   nodes), RECV_STAGE also expands the masks and bins the own-partition
-   synapses, and DELIVER bins the received ones. */
+   two-level step as snn_run launches it, UPDATE also routes (up to 512 nodes
+   of at most 8 partitions), and RECV_STAGE also expands the masks and bins
+   both the own-partition and the received synapses (no DELIVER launch). */
 enum {
   SNN_KERNEL_UPDATE = 0,           /* neuron update, threshold, compaction */
   SNN_KERNEL_ROUTE_TWO_LEVEL = 1,  /* per-node messages with partition masks */
@@ -125,7 +125,7 @@ enum {
 };
 
 /* Largest supported sizes. */
-#define SNN_MAX_GPUS_PER_NODE 8u
+#define SNN_MAX_GPUS_PER_NODE 64u
 #define SNN_MAX_DELAY 15u
 #define SNN_MAX_NEURONS (1u << 27)    /* target ids share 32 bits with the delay; the
                                          deliver kernels' per-tile LDS counters limit a
@@ -137,7 +137,7 @@ enum {
 typedef struct {
   uint32_t n_neurons;         /* neurons on this GPU (all materialised partitions) */
   uint32_t n_partitions;      /* partitions (GPUs), real and virtual */
-  uint32_t gpus_per_node;     /* group size G, 1..8: mask bit b <-> partition G*n + b */
+  uint32_t gpus_per_node;     /* group size G, 1..64: mask bit b <-> partition G*n + b */
   uint32_t max_delay;         /* synaptic delays in [1, max_delay], max_delay <= 15 */
   float alpha;                /* membrane decay per step, fl32(exp(-dt/tau_m)) */
   float theta;                /* threshold relative to rest (mV) */
@@ -307,13 +307,14 @@ snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps,
               partition; vp_rec[2j], vp_rec[2j+1] the record the receiver uses to
               find its synapses);
    which = 1: expanded two-level receive lists, same format;
-   which = 2: per-node send buckets: bits 0..31 source id, bits 32..39
-              partition mask of the node, bits 40..63 index of the node's first
-              destination in the source's destination list (on the device a
-              message also carries that destination's pair index, not copied).
-   sizes[n_partitions or n_nodes] receives the counts; entries (may be NULL)
-   receives the lists concatenated in partition / node order, at most cap
-   entries.  Order inside a list is unspecified.  Synchronises. */
+   which = 2: per-node send buckets, TWO uint64 per message: bits 0..31 source
+              id and bits 32..63 the pair index of the node's first destination
+              (its followers in the node are the next pairs), then the mask of
+              the node's destination partitions (bit b <-> partition G*n + b).
+   sizes[n_partitions or n_nodes] receives the counts (messages for which = 2);
+   entries (may be NULL) receives the lists concatenated in partition / node
+   order, at most cap lists entries (cap counts messages for which = 2, each
+   16 bytes).  Order inside a list is unspecified.  Synchronises. */
 snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entries,
                            uint64_t cap, uint64_t* n_entries);
 

@@ -4,10 +4,12 @@
  * Partition assignment and the routing table are setup steps of the paper's
  * design, run before the simulation (Algorithm 1 produces the neuron-GPU
  * mapping PM, Sec. IV-A; Algorithm 2 the routing table TB, Sec. IV-B).  Here
- * PM is taken as given by the seeded network description (contiguous
- * partitions, or every neuron in partition 0 for one GPU's share with virtual
- * remote partitions) and TB degenerates to each source's ascending list of
- * destination partitions, grouped into nodes of gpus_per_node.
+ * PM is given: by the seeded network description (contiguous partitions, or
+ * every neuron in partition 0 for one GPU's share with virtual remote
+ * partitions), or explicitly as a neuron -> partition map (for instance
+ * Algorithm 1's, with partitions numbered so that Algorithm 2's groups are
+ * consecutive nodes of gpus_per_node).  TB becomes each source's ascending
+ * list of destination partitions, grouped into nodes of gpus_per_node.
  *
  * The setup regenerates the synapse list twice from the counter-based
  * generator (once to count out-degrees, once to place synapses), so host
@@ -46,22 +48,28 @@ typedef struct {
   uint32_t max_delay;       /* delays in [1, max_delay], <= 15 */
   uint32_t n_partitions;
   uint32_t topology;        /* 0 materialised, 1 loopback, 2 loopback with per-source
-                               partition sets, 3 uneven partitions */
+                               partition sets, 3 uneven partitions, 4 clustered */
   uint32_t vp_set_size;
   double remote_frac;
   double w_exc, w_inh;      /* mV */
   double w_jitter;
-  uint32_t gpus_per_node;   /* 1..8 */
+  uint32_t gpus_per_node;   /* 1..64 */
   uint32_t weight_type;     /* SNN_W_FP32 or SNN_W_BF16 (round to nearest even) */
   uint32_t n_threads;       /* 0: OpenMP default */
   uint32_t verbose;         /* nonzero: progress lines on stderr during long passes */
+  uint32_t n_clusters;      /* topology 4: clusters of neurons */
+  double p_in;              /* topology 4: probability that an input comes from the
+                               target's own cluster */
 } snn_setup_spec;
 
-/* part_start: n_partitions+1 ascending neuron offsets for topologies 0 and 3
-   (NULL otherwise); cross_frac: n_partitions probabilities for topology 3.
+/* part_start: n_partitions+1 ascending neuron offsets for topologies 0, 3 and
+   4 (NULL otherwise); cross_frac: n_partitions probabilities for topology 3;
+   part_map: NULL, or n_neurons partitions in [0, n_partitions) replacing the
+   contiguous ranges (topologies 0 and 4; SNN_ERR_INVALID_ARG otherwise).
    Counts out-degrees (first pass over the synapses). */
 snn_status snn_setup_create(const snn_setup_spec* spec, const uint32_t* part_start,
-                            const double* cross_frac, snn_setup_handle* out);
+                            const double* cross_frac, const int32_t* part_map,
+                            snn_setup_handle* out);
 
 /* nnz = total synapses (known after create); pairs, bucket_total and
    recv_total are known after snn_setup_fill_rows (0 before). */

@@ -259,9 +259,11 @@ class Sim:
         return [ent[offs[p]:offs[p + 1]].copy() for p in range(self.P)]
 
     def buckets(self):
+        """Per node, the messages of the last step as an (n, 2) uint64 array of
+        (source id, mask of the node's destination partitions)."""
         sizes = np.zeros(self.n_nodes, np.uint64)
         total = lib().orc_buckets(self.h, _p(sizes), None)
-        msgs = np.zeros(max(int(total), 1), np.uint64)
+        msgs = np.zeros((max(int(total), 1), 2), np.uint64)
         lib().orc_buckets(self.h, _p(sizes), _p(msgs))
         offs = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
         return [msgs[offs[n]:offs[n + 1]].copy() for n in range(self.n_nodes)]
@@ -276,17 +278,17 @@ class Sim:
         return out
 
     def accuracy(self) -> dict:
-        out = np.zeros(4, np.float64)
+        out = np.zeros(5, np.float64)
         lib().orc_accuracy(self.h, _p(out))
         return dict(max_dv=out[0], first_divergence=int(out[1]), agree_steps=int(out[2]),
-                    min_margin=out[3])
+                    min_margin=out[3], max_abs_u=out[4])
 
 
-def sim_for_workload(wl, **over) -> "Sim":
+def sim_for_workload(wl, part_map=None, **over) -> "Sim":
     """Build the reference simulation of a (small) workload from the seeded
-    generator."""
+    generator (with an explicit neuron -> partition map if given)."""
     import synth
-    gen = synth.Generator(wl)
+    gen = synth.Generator(wl, part_map=part_map)
     edges = gen.edges()
     part = gen.part_map()
     u0 = synth.initial_u(wl)

@@ -76,7 +76,8 @@ struct orc_sim {
   uint32_t* fired64;
   uint32_t n_fired64;
   uint64_t stats[ORC_NSTAT];
-  /* routes of the last step: per-partition / per-node growable lists */
+  /* routes of the last step: per-partition / per-node growable lists (a
+     node's bucket holds (source, mask) as two words per message) */
   uint32_t** flat;
   uint64_t* flat_n;
   uint64_t* flat_cap;
@@ -90,12 +91,13 @@ struct orc_sim {
   uint64_t* seen;    /* per partition: stamp of the source that last marked it */
   uint64_t stamp;
   uint32_t* vps;     /* distinct vps of one source */
-  uint32_t* node_mask;
+  uint64_t* node_mask;
   /* accuracy */
   double max_dv;
   int64_t first_div;
   uint64_t agree_steps;
   double min_margin;
+  double max_abs_u;
 };
 
 /* ---- Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
@@ -197,7 +199,7 @@ orc_sim* orc_create(const orc_params* p, uint64_t M, const uint32_t* src,
                     const uint32_t* tgt, const uint8_t* delay,
                     const uint16_t* vp, const float* w, const int32_t* part,
                     const float* u0) {
-  if (!p || p->n_neurons == 0 || p->gpus_per_node == 0 || p->gpus_per_node > 32 ||
+  if (!p || p->n_neurons == 0 || p->gpus_per_node == 0 || p->gpus_per_node > 64 ||
       p->n_partitions == 0 || p->max_delay == 0)
     return NULL;
   orc_sim* s = (orc_sim*)xcalloc(1, sizeof(orc_sim));
@@ -272,7 +274,7 @@ orc_sim* orc_create(const orc_params* p, uint64_t M, const uint32_t* src,
   s->bucket_cap = (uint64_t*)xcalloc(s->n_nodes, sizeof(uint64_t));
   s->seen = (uint64_t*)xcalloc(s->P, sizeof(uint64_t));
   s->vps = (uint32_t*)xcalloc(s->P, sizeof(uint32_t));
-  s->node_mask = (uint32_t*)xcalloc(s->n_nodes, sizeof(uint32_t));
+  s->node_mask = (uint64_t*)xcalloc(s->n_nodes, sizeof(uint64_t));
   s->first_div = -1;
   s->min_margin = INFINITY;
   return s;
@@ -372,6 +374,7 @@ static void update_neurons(orc_sim* s) {
       s->u64[i] = s->u64[i] * (double)s->alpha + (syn64 + ext64);
       double margin = fabs(s->u64[i] - (double)s->theta);
       if (margin < s->min_margin) s->min_margin = margin;
+      if (fabs(s->u64[i]) > s->max_abs_u) s->max_abs_u = fabs(s->u64[i]);
     }
     int spike64 = forced ? forced_spike : (integrating64 && s->u64[i] >= (double)s->theta);
     if (spike64) {
@@ -380,7 +383,8 @@ static void update_neurons(orc_sim* s) {
       s->fired64[s->n_fired64++] = i;
     }
   }
-  /* accuracy bookkeeping */
+  /* accuracy bookkeeping: rasters compared step by step; before the first
+     step whose rasters differ, the largest |u32 - u64| over every neuron */
   int agree = s->n_fired == s->n_fired64 &&
               memcmp(s->fired, s->fired64, sizeof(uint32_t) * s->n_fired) == 0;
   if (agree) s->agree_steps++;
@@ -420,32 +424,34 @@ static void route(orc_sim* s, int keep_lists) {
     s->stats[ORC_FLAT_MSGS] += nv;
     for (uint32_t j = 0; j < nv; ++j)
       if (keep_lists) push32(&s->flat[s->vps[j]], &s->flat_n[s->vps[j]], &s->flat_cap[s->vps[j]], src);
-    /* two-level: OR the partition bits per destination node */
+    /* two-level: OR the partition bits per destination node (bit b of
+       node n's mask is partition G*n + b, G <= 64) */
     for (uint32_t j = 0; j < nv; ++j) {
       uint32_t node = s->vps[j] / s->G;
-      s->node_mask[node] |= 1u << (s->vps[j] - s->G * node);
+      s->node_mask[node] |= (uint64_t)1 << (s->vps[j] - s->G * node);
     }
     for (uint32_t j = 0; j < nv; ++j) {
       uint32_t node = s->vps[j] / s->G;
-      uint32_t mask = s->node_mask[node];
+      uint64_t mask = s->node_mask[node];
       if (mask == 0) continue;           /* node already emitted */
       s->node_mask[node] = 0;
       if (node == own_node) s->stats[ORC_MSG_L1]++;
       else s->stats[ORC_MSG_L2]++;
       for (uint32_t b = 0; b < s->G; ++b)
-        if (mask & (1u << b)) s->stats[ORC_RECV_ENTRIES]++;
-      if (keep_lists)
-        push64(&s->bucket[node], &s->bucket_n[node], &s->bucket_cap[node],
-               ((uint64_t)mask << 32) | src);
+        if ((mask >> b) & 1) s->stats[ORC_RECV_ENTRIES]++;
+      if (keep_lists) {
+        push64(&s->bucket[node], &s->bucket_n[node], &s->bucket_cap[node], src);
+        push64(&s->bucket[node], &s->bucket_n[node], &s->bucket_cap[node], mask);
+      }
     }
   }
   /* expansion at each destination node: mask bit b -> partition G*n + b */
   for (uint32_t n = 0; n < s->n_nodes; ++n) {
-    for (uint64_t m = 0; m < s->bucket_n[n]; ++m) {
-      uint64_t msg = s->bucket[n][m];
-      uint32_t src = (uint32_t)msg, mask = (uint32_t)(msg >> 32);
+    for (uint64_t m = 0; m < s->bucket_n[n]; m += 2) {
+      uint32_t src = (uint32_t)s->bucket[n][m];
+      uint64_t mask = s->bucket[n][m + 1];
       for (uint32_t b = 0; b < s->G; ++b)
-        if (mask & (1u << b)) {
+        if ((mask >> b) & 1) {
           uint32_t p = s->G * n + b;
           push32(&s->xrecv[p], &s->xrecv_n[p], &s->xrecv_cap[p], src);
         }
@@ -526,9 +532,10 @@ uint64_t orc_recv(const orc_sim* s, int which, uint64_t* sizes, uint32_t* entrie
 uint64_t orc_buckets(const orc_sim* s, uint64_t* sizes, uint64_t* msgs) {
   uint64_t total = 0;
   for (uint32_t n = 0; n < s->n_nodes; ++n) {
-    if (sizes) sizes[n] = s->bucket_n[n];
-    if (msgs && s->bucket_n[n]) memcpy(msgs + total, s->bucket[n], sizeof(uint64_t) * s->bucket_n[n]);
-    total += s->bucket_n[n];
+    const uint64_t nm = s->bucket_n[n] / 2;
+    if (sizes) sizes[n] = nm;
+    if (msgs && nm) memcpy(msgs + 2 * total, s->bucket[n], sizeof(uint64_t) * 2 * nm);
+    total += nm;
   }
   return total;
 }
@@ -549,6 +556,7 @@ void orc_accuracy(const orc_sim* s, double* out) {
   out[1] = (double)s->first_div;
   out[2] = (double)s->agree_steps;
   out[3] = s->min_margin;
+  out[4] = s->max_abs_u;
 }
 
 /* ---- Forced raster at any size, without the synapse list of the whole

@@ -20,7 +20,7 @@ extern "C" {
 typedef struct {
   uint32_t n_neurons;
   uint32_t n_partitions;
-  uint32_t gpus_per_node;   /* group (node) size; mask bit b <-> partition G*n+b */
+  uint32_t gpus_per_node;   /* group (node) size, <= 64; mask bit b <-> partition G*n+b */
   uint32_t max_delay;       /* ring has max_delay + 1 slots */
   double dt_ms, tau_m_ms;
   double theta_mv;          /* threshold relative to rest */
@@ -71,17 +71,21 @@ void orc_counters(const orc_sim* s, uint64_t* out);       /* ORC_NSTAT */
 /* which: 0 = flat lists, 1 = expanded two-level lists; sizes[n_partitions],
    entries concatenated by partition (may be NULL to get sizes only). */
 uint64_t orc_recv(const orc_sim* s, int which, uint64_t* sizes, uint32_t* entries);
-/* per-node messages ((uint64)mask << 32 | src), concatenated by node. */
+/* per-node messages, two words each (source id, 64-bit mask of the node's
+   destination partitions: bit b <-> partition G*n + b), concatenated by
+   node; sizes[n_nodes] counts messages; returns the message total. */
 uint64_t orc_buckets(const orc_sim* s, uint64_t* sizes, uint64_t* msgs);
 
 /* Current state; any pointer may be NULL. ring: [max_delay+1][n_neurons]. */
 void orc_state(const orc_sim* s, float* u, uint8_t* ref, float* ring,
                double* u64, uint8_t* ref64, double* ring64);
 
-/* FP64-vs-binary32 accuracy so far: out[0] = max |u32 - u64| over all
-   neuron-steps before the first raster divergence, out[1] = step of first
-   divergence (-1 if none), out[2] = number of steps whose rasters agree,
-   out[3] = min |u64 - theta| seen on integrating neurons. */
+/* FP64-vs-binary32 accuracy so far (out[5]): out[0] = max |u32 - u64| over
+   all neuron-steps (after each step's update) before the first step whose
+   rasters differ, out[1] = that step (-1 if none), out[2] = number of steps
+   whose rasters agree, out[3] = min |u64 - theta| over integrating
+   neuron-steps, out[4] = max |u64| over integrating neuron-steps (the
+   magnitude at which the update rounds). */
 void orc_accuracy(const orc_sim* s, double* out);
 
 /* Derived constants, exposed so tests can compare them with the device

@@ -72,6 +72,7 @@ class snn_setup_spec(ctypes.Structure):
         ("n_partitions", u32), ("topology", u32), ("vp_set_size", u32),
         ("remote_frac", f64), ("w_exc", f64), ("w_inh", f64), ("w_jitter", f64),
         ("gpus_per_node", u32), ("weight_type", u32), ("n_threads", u32), ("verbose", u32),
+        ("n_clusters", u32), ("p_in", f64),
     ]
 
 
@@ -120,7 +121,8 @@ def lib() -> ctypes.CDLL:
             "snn_read_counters": (I, [vp, u64, u32, vp]),
             "snn_destroy": (I, [vp]),
             "snn_last_error": (ctypes.c_char_p, []),
-            "snn_setup_create": (I, [ctypes.POINTER(snn_setup_spec), vp, vp, ctypes.POINTER(vp)]),
+            "snn_setup_create": (I, [ctypes.POINTER(snn_setup_spec), vp, vp, vp,
+                                     ctypes.POINTER(vp)]),
             "snn_setup_sizes": (I, [vp] + [ctypes.POINTER(u64)] * 4),
             "snn_setup_fill_rows": (I, [vp] * 6),
             "snn_setup_fill_routes": (I, [vp] * 9),

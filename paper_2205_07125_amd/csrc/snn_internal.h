@@ -15,7 +15,16 @@ enum : uint32_t {
   ERR_RECV = 2u,     // an expanded receive list overflowed
   ERR_FLAT = 4u,     // a flat receive list overflowed
   ERR_LOG = 8u,      // a step had more spikes than the spike log holds
-  ERR_ROUTE = 16u    // a receive entry names a partition its source does not reach
+  ERR_ROUTE = 16u,   // a receive entry names a partition its source does not reach
+  ERR_TIMEOUT = 32u  // a device-scope wait gave up (a block it waited for never arrived)
+};
+
+// Words of the in-launch synchronisation area (KParams::sync), each on a
+// 64-byte line of its own; every launch that uses one leaves it at zero.
+enum : uint32_t {
+  SYNC_STAGED = 0,    // staging blocks of the combined receive launch that are done
+  SYNC_RETIRED = 16,  // delivery blocks of that launch that are done
+  SYNC_WORDS = 64
 };
 
 // Device-resident step state.  Every step-dependent value lives here so that
@@ -57,7 +66,6 @@ constexpr uint32_t CNT_STRIDE = 16;                 // counters padded to 64 byt
 constexpr uint32_t ROUTE_STAGE = 2048;              // pairs per routing window
 constexpr uint32_t ROUTE_BLOCKS = 256;              // two-level routing blocks
 constexpr uint32_t ROUTE_MAX_NODES_LDS = 4096;      // more nodes: unstaged routing
-constexpr int EXPAND_THREADS = 512;                 // one expansion block per node
 constexpr uint32_t DELIVER_BLOCKS = 32;             // deliver blocks per delay
 constexpr uint32_t STAGE_BLOCKS = 256;              // receive-side blocks (one queue each)
 constexpr uint32_t STAGE_PARTS = 256;               // partitions per receive-side block, at most
@@ -151,8 +159,8 @@ struct KParams {
   uint64_t* lookback;   // [n_tiles] decoupled look-back words
   uint32_t* fired;      // [N] ascending fired ids of the step in flight
   uint32_t* bucket_cnt; // [2][n_nodes * CNT_STRIDE] two sets, by step parity
-  uint64_t* bucket;     // [2 * bucket_total] messages: source | mask << 32 | first
-                        // destination's list index << 40, then its pair index
+  uint64_t* bucket;     // [2 * bucket_total] messages: source | pair index of the
+                        // node's first destination << 32, then the partition mask
   uint32_t* recv_cnt;   // [P * CNT_STRIDE] expanded lists
   uint64_t* recv;       // [recv_total]
   uint32_t* flat_cnt;   // [P * CNT_STRIDE]
@@ -163,6 +171,7 @@ struct KParams {
   uint32_t* dirty;      // [D * n_tiles] ring tile holds events
   Event* bins;          // [D][n_tiles][bin_cap]
   uint64_t* stats;      // [log_steps + 1][STAT_LANES][STAT_LANE_WORDS]
+  uint32_t* sync;       // [SYNC_WORDS] in-launch arrival counters
   uint64_t* log_off;    // [log_steps] first log position of each step
   uint32_t* log;        // [log_cap] spike-log ring
 };

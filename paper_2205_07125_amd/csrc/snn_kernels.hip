@@ -17,12 +17,13 @@
 //                  written as runs into per-(slot, tile, delay, block) bins
 //   k_route_flat   flat routing: one receive entry per destination partition
 //
-// A whole step is three launches: k_update<true> (update, compaction and the
-// tile's own two-level routing, which overlaps the look-back),
-// k_recv_local (expansion and staging beside the own-partition delivery: two
-// independent jobs in one launch) and k_deliver_remote (the staged remote
-// synapses).  The step-by-step entry points use one kernel per job instead
-// (k_update<false>, k_route_two_level, k_expand, k_recv_stage, k_deliver).
+// A whole step is two launches: k_update<true> (update, compaction and the
+// tile's own two-level routing, which overlaps the look-back) and
+// k_recv_deliver (expansion and staging, and beside them the own-partition
+// delivery, whose blocks then wait for the staging blocks and bin the staged
+// remote synapses).  The step-by-step entry points use one kernel per job
+// instead (k_update<false>, k_route_two_level, k_expand, k_recv_stage,
+// k_deliver).
 //
 // Global atomics run at roughly 20 G/s on random addresses and serialise on
 // hot counters, so every scatter goes through LDS first: reservations are one
@@ -33,6 +34,7 @@
 // Compiled with -ffp-contract=off: the membrane update rounds after every
 // operation, exactly as specified.
 #include <algorithm>
+#include <type_traits>
 
 #include "snn_internal.h"
 
@@ -86,12 +88,18 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
+// Weight of synapse e.  The kernels that read weights are instantiated per
+// weight type, so a BF16 load is never followed by a widening inside a
+// run-time branch (which would make each 16-bit load wait for every load in
+// flight before the next is issued).
+template <bool BF16>
 __device__ __forceinline__ float load_weight(const KParams& p, uint64_t e) {
-  if (p.bf16) {
+  if constexpr (BF16) {
     const uint16_t b = static_cast<const uint16_t*>(p.weight)[e];
     return __uint_as_float(static_cast<uint32_t>(b) << 16);
+  } else {
+    return static_cast<const float*>(p.weight)[e];
   }
-  return static_cast<const float*>(p.weight)[e];
 }
 
 // Adds the block's sum of two per-thread counters into two global u64s with
@@ -216,37 +224,36 @@ constexpr int FUSED_ROUTE_UNROLL = FUSED_ROUTE_WINDOW / UPDATE_THREADS;   // one
 // ---------------------------------------------------------------------------
 // route
 
-// Node of partition v (v < 2^16, G <= 8): v / G as one high multiply; with
+// Node of partition v (v < 2^16, G <= 64): v / G as one high multiply; with
 // M = ceil(2^32 / G) the product exceeds v / G by less than 2^-16, too little
 // to pass the next integer.
 __device__ __forceinline__ uint32_t node_of(const KParams& p, uint32_t v) {
   return p.G == 1 ? v : __umulhi(v, p.g_magic);
 }
 
-// Message to node n for source s: bits 0..31 source, 32..39 mask of the
-// node's destination partitions, 40..63 index (in s's destination list) of
-// the node's first destination partition.
-__device__ __forceinline__ uint32_t node_mask(const KParams& p, int64_t j, int64_t j1,
+// Mask of node `node`'s destination partitions in s's list from position j
+// (the node's first) on: bit b <-> partition G * node + b.
+__device__ __forceinline__ uint64_t node_mask(const KParams& p, int64_t j, int64_t j1,
                                               uint32_t node) {
-  uint32_t mask = 0;
+  uint64_t mask = 0;
   for (int64_t jj = j; jj < j1; ++jj) {
     const uint32_t vv = p.vp_part[jj];
     if (node_of(p, vv) != node) break;
-    mask |= 1u << (vv - p.G * node);
+    mask |= uint64_t(1) << (vv - p.G * node);
   }
   return mask;
 }
 
-// Message of node `node` at position pos of its bucket: word 0 = source |
-// mask << 32 | list index of the node's first destination << 40, word 1 =
-// that destination's pair index (the receive record the expansion hands on).
+// A message in a node's bucket is two words: source | pair index of the
+// node's first destination (the receive record the expansion hands on, its
+// followers are the next pairs) << 32, then the 64-bit partition mask.
 __device__ __forceinline__ void bucket_put(const KParams& p, uint32_t node, uint32_t pos,
-                                           uint64_t msg, uint64_t pair) {
+                                           uint64_t src_pair, uint64_t mask) {
   const uint64_t off = p.bucket_off[node];
   if (off + pos < p.bucket_off[node + 1]) {
     uint64_t* m = p.bucket + 2 * (off + pos);
-    m[0] = msg;
-    m[1] = pair;
+    m[0] = src_pair;
+    m[1] = mask;
   } else {
     atomicOr(&p.st->error, ERR_BUCKET);
   }
@@ -260,10 +267,13 @@ __device__ __forceinline__ uint32_t* bucket_counts(const KParams& p, uint32_t pa
 }
 
 // LDS arrays of the two-level routing of a batch of at most NT sources of
-// one block, over windows of W (source, destination) pairs.
+// one block, over windows of W (source, destination) pairs.  Narrow masks
+// (groups of at most 8) travel inside the staged message word; wide ones
+// (up to 64) in an array of their own.
 struct RouteLds {
   int64_t* j0;     // [NT] first pair index of each source
-  uint64_t* msg;   // [W] staged messages
+  uint64_t* msg;   // [W] staged messages: source | list position << 32 (| mask << 48, narrow)
+  uint64_t* mask;  // [W] their masks (wide only)
   uint64_t* base;  // [n_nodes] start reserved for the window's messages in each bucket
   uint64_t* end;   // [n_nodes] end of each bucket
   uint32_t* pre;   // [NT + 1] list starts in the concatenation of the batch's lists
@@ -271,23 +281,25 @@ struct RouteLds {
   uint32_t* nr;    // [W] node | rank among the window's messages to that node << 16
   uint32_t* cnt;   // [n_nodes] messages of the window per node
   uint16_t* own;   // [NT] node of each source
-  uint16_t* nb;    // [W] node << 3 | bit of each pair's partition in the node
+  uint16_t* nb;    // [W] destination partition of each pair
   uint16_t* pk;    // [W] batch index of each pair's source
   uint16_t* off;   // [W] position of each pair in its source's list
   uint16_t* mk;    // [W] batch index of each message's source
   uint32_t W;
 };
 
-__host__ __device__ constexpr size_t route_lds_bytes(uint32_t nt, uint32_t w, uint32_t n_nodes) {
-  return 8 * (size_t(nt) + w + 2 * size_t(n_nodes)) + 4 * (2 * size_t(nt) + 1 + w + n_nodes) +
-         2 * (size_t(nt) + 4 * size_t(w));
+__host__ __device__ constexpr size_t route_lds_bytes(uint32_t nt, uint32_t w, uint32_t n_nodes,
+                                                     bool wide) {
+  return 8 * (size_t(nt) + w + (wide ? w : 0) + 2 * size_t(n_nodes)) +
+         4 * (2 * size_t(nt) + 1 + w + n_nodes) + 2 * (size_t(nt) + 4 * size_t(w));
 }
 
-__device__ RouteLds route_lds(void* lds, uint32_t nt, uint32_t w, uint32_t n_nodes) {
+__device__ RouteLds route_lds(void* lds, uint32_t nt, uint32_t w, uint32_t n_nodes, bool wide) {
   RouteLds L;
   char* c = static_cast<char*>(lds);
   L.j0 = reinterpret_cast<int64_t*>(c);                  c += size_t(nt) * 8;
   L.msg = reinterpret_cast<uint64_t*>(c);                c += size_t(w) * 8;
+  L.mask = reinterpret_cast<uint64_t*>(c);               c += wide ? size_t(w) * 8 : 0;
   L.base = reinterpret_cast<uint64_t*>(c);               c += size_t(n_nodes) * 8;
   L.end = reinterpret_cast<uint64_t*>(c);                c += size_t(n_nodes) * 8;
   L.pre = reinterpret_cast<uint32_t*>(c);                c += (size_t(nt) + 1) * 4;
@@ -303,21 +315,24 @@ __device__ RouteLds route_lds(void* lds, uint32_t nt, uint32_t w, uint32_t n_nod
   return L;
 }
 
+// Group sizes up to which the staged message word carries the mask.
+constexpr uint32_t NARROW_G = 8;
+
 // Two-level routing (Sec. IV-B) of the n <= NT sources in L.src: one message
 // per (source, destination node) into the node buckets counted by bcnt.
 // The sources' destination lists are taken as one flat sequence of pairs: one
 // thread per source loads the list bounds, a block scan concatenates the
 // lists, and windows of W pairs are loaded into LDS, U loads in flight per
-// thread, each pair stored as its node and its partition's bit in
-// the node.  A pair that starts a run of equal node in its source's
-// (ascending) list ORs the run into the mask: the run has at most G pairs, so
-// the next SNN_MAX_GPUS_PER_NODE - 1 pairs are read at once from LDS (global
-// memory only for a run that continues past the window's end).  Messages are
-// staged in LDS with their rank among the window's messages to their node;
-// one atomic per (window, node) then reserves the node's bucket space.  A
-// window has at most as many messages as pairs, so the stage never
-// overflows.  Every thread of the block calls it; it ends with a barrier.
-template <uint32_t NT, int U>
+// thread, each pair stored as its partition.  A pair that starts a run of
+// equal node in its source's (ascending) list ORs the run into the mask: the
+// run has at most G pairs; narrow groups read the next NARROW_G - 1 pairs at
+// once from LDS, wide ones walk the run (global memory only for a run that
+// continues past the window's end).  Messages are staged in LDS with their
+// rank among the window's messages to their node; one atomic per (window,
+// node) then reserves the node's bucket space.  A window has at most as many
+// messages as pairs, so the stage never overflows.  Every thread of the block
+// calls it; it ends with a barrier.
+template <uint32_t NT, int U, bool WIDE>
 __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uint32_t* bcnt,
                             uint64_t& l1, uint64_t& l2) {
   __shared__ uint32_t l_total, s_prev_node;
@@ -361,8 +376,7 @@ __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uin
       for (int v = 0; v < U; ++v) {
         const uint32_t i = i0 + v * NT + tid;
         if (i < nwin) {
-          const uint32_t node = node_of(p, vp[v]);
-          L.nb[i] = static_cast<uint16_t>((node << 3) | (vp[v] - G * node));
+          L.nb[i] = static_cast<uint16_t>(vp[v]);
           L.pk[i] = static_cast<uint16_t>(kk[v]);
           L.off[i] = static_cast<uint16_t>(o[v]);
         }
@@ -371,34 +385,50 @@ __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uin
     __syncthreads();
     // one message per run of equal node
     for (uint32_t i = tid; i < nwin; i += NT) {
-      const uint32_t k = L.pk[i], off = L.off[i], nbi = L.nb[i];
-      const uint32_t node = nbi >> 3;
-      if (off > 0 && (i > 0 ? static_cast<uint32_t>(L.nb[i - 1] >> 3) : s_prev_node) == node)
-        continue;
-      uint32_t mask = 1u << (nbi & 7u);
-      bool open = true, cut = false;
+      const uint32_t k = L.pk[i], off = L.off[i], v0 = L.nb[i];
+      const uint32_t node = node_of(p, v0);
+      if (off > 0 && (i > 0 ? node_of(p, L.nb[i - 1]) : s_prev_node) == node) continue;
+      uint64_t mask = uint64_t(1) << (v0 - G * node);
+      bool cut = false;
+      if constexpr (!WIDE) {
+        bool open = true;
 #pragma unroll
-      for (uint32_t d = 1; d < SNN_MAX_GPUS_PER_NODE; ++d) {
-        const bool in = i + d < nwin;
-        cut = cut || (open && !in);
-        const uint32_t at = min(i + d, nwin - 1);
-        const uint32_t v = L.nb[at], kv = L.pk[at];
-        open = open && in && kv == k && (v >> 3) == node;
-        if (open) mask |= 1u << (v & 7u);
+        for (uint32_t d = 1; d < NARROW_G; ++d) {
+          const bool in = i + d < nwin;
+          cut = cut || (open && !in);
+          const uint32_t at = min(i + d, nwin - 1);
+          const uint32_t v = L.nb[at], kv = L.pk[at];
+          open = open && in && kv == k && node_of(p, v) == node;
+          if (open) mask |= uint64_t(1) << (v - G * node);
+        }
+      } else {
+        for (uint32_t d = 1; d < G; ++d) {
+          if (i + d >= nwin) {
+            cut = true;
+            break;
+          }
+          const uint32_t v = L.nb[i + d];
+          if (L.pk[i + d] != k || node_of(p, v) != node) break;
+          mask |= uint64_t(1) << (v - G * node);
+        }
       }
       if (cut) {   // the run reaches the window's end: its rest from global memory
         const uint32_t len_k = L.pre[k + 1] - L.pre[k];
         for (uint32_t x = off + (nwin - i); x < len_k; ++x) {
           const uint32_t v = p.vp_part[L.j0[k] + x];
           if (node_of(p, v) != node) break;
-          mask |= 1u << (v - G * node);
+          mask |= uint64_t(1) << (v - G * node);
         }
       }
-      const uint64_t msg = (static_cast<uint64_t>(off) << 40) |
-                           (static_cast<uint64_t>(mask) << 32) | L.src[k];
       const uint32_t slot = atomicAdd(&l_total, 1u);
       const uint32_t rk = atomicAdd(&L.cnt[node], 1u);
-      L.msg[slot] = msg;
+      const uint64_t msg = (static_cast<uint64_t>(off) << 32) | L.src[k];
+      if constexpr (WIDE) {
+        L.msg[slot] = msg;
+        L.mask[slot] = mask;
+      } else {
+        L.msg[slot] = msg | (mask << 48);
+      }
       L.nr[slot] = node | (rk << 16);
       L.mk[slot] = static_cast<uint16_t>(k);
       if (node == L.own[k]) ++l1; else ++l2;
@@ -421,8 +451,9 @@ __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uin
       const uint64_t pos = L.base[node] + (nr >> 16);
       if (pos < L.end[node]) {
         const uint64_t msg = L.msg[k];
-        p.bucket[2 * pos] = msg;
-        p.bucket[2 * pos + 1] = static_cast<uint64_t>(L.j0[L.mk[k]]) + (msg >> 40);
+        const uint64_t pair = static_cast<uint64_t>(L.j0[L.mk[k]]) + ((msg >> 32) & 0xFFFFu);
+        p.bucket[2 * pos] = (msg & 0xFFFFFFFFull) | (pair << 32);
+        p.bucket[2 * pos + 1] = WIDE ? L.mask[k] : msg >> 48;
       } else {
         atomicOr(&p.st->error, ERR_BUCKET);
       }
@@ -504,7 +535,8 @@ __device__ uint32_t lookback_resolve(uint64_t* lb, uint32_t b, uint32_t agg, uin
 // then, holds the routing's arrays.
 static_assert(UPDATE_NPT % 4 == 0 && UPDATE_NPT <= 32, "fire bits of a thread fit 32 bits");
 constexpr size_t UPDATE_BIG_LDS = TILE * sizeof(int32_t) + POIS_LUT_SIZE;
-static_assert(route_lds_bytes(UPDATE_THREADS, FUSED_ROUTE_WINDOW, FUSED_MAX_NODES) <= UPDATE_BIG_LDS,
+static_assert(route_lds_bytes(UPDATE_THREADS, FUSED_ROUTE_WINDOW, FUSED_MAX_NODES, false) <=
+                  UPDATE_BIG_LDS,
               "the fused routing's arrays fit the update's LDS");
 template <bool ROUTE>
 __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
@@ -624,11 +656,25 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
       if (has[v]) atomicAdd(&s_acc[x[v].tgt], x[v].wq);
   }
   if (__syncthreads_or(over)) {
-    for (uint32_t k = grp; k < n_sub; k += ARRIVE_GROUPS)
-      for (uint32_t j = ARRIVE_LANES + gl; j < s_bcnt[k]; j += ARRIVE_LANES) {
-        const Event y = ev0[k * sub_stride + j];
-        atomicAdd(&s_acc[y.tgt], y.wq);
+    // the rest of sub-bins with more than ARRIVE_LANES events (bursts), with
+    // ARRIVE_UNROLL loads in flight per lane as above
+    for (uint32_t k = grp; k < n_sub; k += ARRIVE_GROUPS) {
+      const uint32_t c = s_bcnt[k];
+      const Event* sb = ev0 + k * sub_stride;
+      for (uint32_t j0 = ARRIVE_LANES; j0 < c; j0 += ARRIVE_LANES * ARRIVE_UNROLL) {
+        bool has[ARRIVE_UNROLL];
+        Event x[ARRIVE_UNROLL];
+#pragma unroll
+        for (int v = 0; v < ARRIVE_UNROLL; ++v) {
+          const uint32_t j = j0 + v * ARRIVE_LANES + gl;
+          has[v] = j < c;
+          x[v] = sb[has[v] ? j : 0u];
+        }
+#pragma unroll
+        for (int v = 0; v < ARRIVE_UNROLL; ++v)
+          if (has[v]) atomicAdd(&s_acc[x[v].tgt], x[v].wq);
       }
+    }
     __syncthreads();
   }
   // events that did not fit their bins are in this tile's slice of the ring
@@ -760,7 +806,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   if constexpr (ROUTE) {
     // the tile's fired neurons, UPDATE_THREADS at a time, routed into the
     // bucket set of this step
-    const RouteLds L = route_lds(s_big, UPDATE_THREADS, FUSED_ROUTE_WINDOW, p.n_nodes);
+    const RouteLds L = route_lds(s_big, UPDATE_THREADS, FUSED_ROUTE_WINDOW, p.n_nodes, false);
     uint32_t* bcnt = bucket_counts(p, t32 & 1u);
     uint64_t l1 = 0, l2 = 0;
     for (uint32_t b0 = 0; b0 < btot; b0 += UPDATE_THREADS) {
@@ -768,7 +814,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
         if (r - b0 < UPDATE_THREADS) L.src[r - b0] = id;
       });
       __syncthreads();
-      route_batch<UPDATE_THREADS, FUSED_ROUTE_UNROLL>(
+      route_batch<UPDATE_THREADS, FUSED_ROUTE_UNROLL, false>(
           p, L, min(btot - b0, static_cast<uint32_t>(UPDATE_THREADS)), bcnt, l1, l2);
     }
     uint64_t* sc = stat_copy(p, srow);
@@ -818,18 +864,19 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   }
 }
 
-static_assert(route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, ROUTE_MAX_NODES_LDS) <= 150u * 1024u,
+static_assert(route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, ROUTE_MAX_NODES_LDS, true) <= 150u * 1024u,
               "the routing kernel's arrays fit a CU's LDS");
 static_assert(ROUTE_STAGE <= 65536 && ROUTE_MAX_NODES_LDS <= 8192,
               "ranks and nodes fit their 16-bit fields");
 
 // Two-level routing as a kernel of its own: block b routes a contiguous chunk
 // of the step's fired sources, ROUTE_THREADS at a time (route_batch).
-// Dynamic LDS: route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, n_nodes).
+// Dynamic LDS: route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, n_nodes, WIDE).
+template <bool WIDE>
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   __shared__ uint64_t s_red[2 * (ROUTE_THREADS / 64)];
-  const RouteLds L = route_lds(lds_u64, ROUTE_THREADS, ROUTE_STAGE, p.n_nodes);
+  const RouteLds L = route_lds(lds_u64, ROUTE_THREADS, ROUTE_STAGE, p.n_nodes, WIDE);
   const uint32_t nF = p.st->n_fired;
   const uint32_t row = p.st->cur_srow;   // counter row
   uint32_t* bcnt = bucket_counts(p, p.st->cur_par);
@@ -841,7 +888,7 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level(KParams p) {
     const uint32_t n = min(hi - r0, static_cast<uint32_t>(ROUTE_THREADS));
     if (tid < n) L.src[tid] = p.fired[r0 + tid];
     __syncthreads();
-    route_batch<ROUTE_THREADS, ROUTE_UNROLL>(p, L, n, bcnt, l1, l2);
+    route_batch<ROUTE_THREADS, ROUTE_UNROLL, WIDE>(p, L, n, bcnt, l1, l2);
   }
   uint64_t* st = stat_copy(p, row);
   add_stats(st + SNN_STAT_MSG_L1, l1, st + SNN_STAT_MSG_L2, l2, s_red);
@@ -865,81 +912,15 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_two_level_direct(KParam
       if (j >= j1) continue;
       const uint32_t node = node_of(p, p.vp_part[j]);
       if (j != j0 && node_of(p, p.vp_part[j - 1]) == node) continue;
-      const uint64_t msg = (static_cast<uint64_t>(j - j0) << 40) |
-                           (static_cast<uint64_t>(node_mask(p, j, j1, node)) << 32) | s;
-      bucket_put(p, node, atomicAdd(bcnt + node * CNT_STRIDE, 1u), msg,
-                 static_cast<uint64_t>(j));
+      bucket_put(p, node, atomicAdd(bcnt + node * CNT_STRIDE, 1u),
+                 static_cast<uint64_t>(s) | (static_cast<uint64_t>(j) << 32),
+                 node_mask(p, j, j1, node));
       if (node == own_node) ++l1; else ++l2;
     }
   }
   __shared__ uint64_t s_red[2 * (ROUTE_THREADS / 64)];
   uint64_t* st = stat_copy(p, row);
   add_stats(st + SNN_STAT_MSG_L1, l1, st + SNN_STAT_MSG_L2, l2, s_red);
-}
-
-// Expansion at destination node n (one block per node): every set bit b of a
-// message's mask appends (source, pair index of partition G*n + b) to that
-// partition's receive list; the node's destinations are consecutive in the
-// source's list, so the pair indices follow the message's first one.  The block owns the
-// node's G partitions, so list positions come from LDS counters (no global
-// atomics) and the counts are stored at the end.  Rounds take one message per
-// thread, staged in LDS so that each partition's entries are written as runs.
-__global__ __launch_bounds__(EXPAND_THREADS) void k_expand(KParams p) {
-  constexpr uint32_t NW = EXPAND_THREADS / 64;
-  __shared__ uint64_t s_ent[EXPAND_THREADS * SNN_MAX_GPUS_PER_NODE];
-  __shared__ uint16_t s_br[EXPAND_THREADS * SNN_MAX_GPUS_PER_NODE];   // b | rank << 3
-  __shared__ uint32_t l_cnt[SNN_MAX_GPUS_PER_NODE], l_run[SNN_MAX_GPUS_PER_NODE];
-  __shared__ uint64_t l_off[SNN_MAX_GPUS_PER_NODE + 1];
-  __shared__ uint32_t l_total;
-  __shared__ uint64_t s_red[2 * NW];
-  const uint32_t n = blockIdx.x;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t row = p.st->cur_srow;   // counter row
-  const uint64_t off = p.bucket_off[n];
-  const uint64_t cap = p.bucket_off[n + 1] - off;
-  const uint64_t cnt = min(static_cast<uint64_t>(bucket_counts(p, p.st->cur_par)[n * CNT_STRIDE]), cap);
-  const uint32_t gn = min(p.G, p.P - p.G * n);             // partitions of this node
-  if (tid < SNN_MAX_GPUS_PER_NODE) l_run[tid] = 0;
-  if (tid <= gn) l_off[tid] = p.recv_off[p.G * n + tid];
-  uint64_t entries = 0;
-  for (uint64_t m0 = 0; m0 < cnt; m0 += EXPAND_THREADS) {
-    if (tid < SNN_MAX_GPUS_PER_NODE) l_cnt[tid] = 0;
-    if (tid == 0) l_total = 0;
-    __syncthreads();
-    const uint64_t m = m0 + tid;
-    if (m < cnt) {
-      const uint64_t msg = p.bucket[2 * (off + m)];
-      uint64_t pair = p.bucket[2 * (off + m) + 1];
-      const uint64_t s = msg & 0xFFFFFFFFull;
-      uint32_t mask = static_cast<uint32_t>(msg >> 32) & 0xFFu;
-      while (mask) {
-        const uint32_t b = __ffs(mask) - 1;
-        mask &= mask - 1;
-        if (b >= gn) {
-          atomicOr(&p.st->error, ERR_ROUTE);
-          continue;
-        }
-        const uint32_t k = atomicAdd(&l_total, 1u);
-        const uint32_t rk = atomicAdd(&l_cnt[b], 1u);
-        s_ent[k] = s | (pair << ENTRY_SRC_BITS);
-        s_br[k] = static_cast<uint16_t>(b | (rk << 3));
-        ++pair;
-        ++entries;
-      }
-    }
-    __syncthreads();
-    for (uint32_t k = tid; k < l_total; k += EXPAND_THREADS) {
-      const uint32_t b = s_br[k] & 7u;
-      const uint64_t pos = l_off[b] + l_run[b] + (s_br[k] >> 3);
-      if (pos < l_off[b + 1]) p.recv[pos] = s_ent[k];
-      else atomicOr(&p.st->error, ERR_RECV);
-    }
-    __syncthreads();
-    if (tid < SNN_MAX_GPUS_PER_NODE) l_run[tid] += l_cnt[tid];
-  }
-  __syncthreads();
-  if (tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
-  add_stat(stat_copy(p, row) + SNN_STAT_RECV_ENTRIES, entries, s_red);
 }
 
 // Flat (direct peer-to-peer) routing: one wave per fired source, one receive
@@ -1012,6 +993,7 @@ __device__ __forceinline__ void stage_emit(const KParams& p, const StageCtx& c, 
 // and the rest of the longer segments are concatenated by a block scan and
 // loaded as one flat sequence, GATHER_UNROLL loads in flight per thread.
 // Every thread calls it; it ends with a barrier.
+template <bool BF16>
 __device__ void stage_batch(const KParams& p, const StageCtx& c, const uint64_t* ent, uint32_t nb,
                             uint64_t& events) {
   constexpr uint32_t R = RECV_PER_THREAD;
@@ -1037,7 +1019,7 @@ __device__ void stage_batch(const KParams& p, const StageCtx& c, const uint64_t*
     if (in && ok) {
       const uint32_t wbits = static_cast<uint32_t>(rec1[v] >> 32);
       stage_emit(p, c, static_cast<uint32_t>(rec1[v]),
-                 p.bf16 ? __uint_as_float(wbits << 16) : __uint_as_float(wbits));
+                 BF16 ? __uint_as_float(wbits << 16) : __uint_as_float(wbits));
       events += seg_len;
     }
     c.s_seg[tid * R + v] = start + 1;
@@ -1062,7 +1044,7 @@ __device__ void stage_batch(const KParams& p, const StageCtx& c, const uint64_t*
       const uint32_t k = owner_of<RECV_BATCH / 2>(c.s_epre, nb, e);
       const uint64_t x = c.s_seg[k] + (e - c.s_epre[k]);
       td[v] = p.tgt_delay[x];
-      wt[v] = load_weight(p, x);
+      wt[v] = load_weight<BF16>(p, x);
     }
 #pragma unroll
     for (int v = 0; v < GATHER_UNROLL; ++v)
@@ -1074,6 +1056,7 @@ __device__ void stage_batch(const KParams& p, const StageCtx& c, const uint64_t*
 // Receive lists -> staging queues.  Block b of STAGE_BLOCKS owns a contiguous
 // range of partitions and their receive lists (expanded or flat), taken in
 // batches of RECV_BATCH entries (stage_batch).
+template <bool BF16>
 __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_flat) {
   constexpr uint32_t NW = RECV_THREADS / 64;
   constexpr uint32_t R = RECV_PER_THREAD;
@@ -1115,7 +1098,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
       const uint32_t k = owner_of<STAGE_PARTS / 2>(s_ppre, nq, e);
       ent[v] = lists[s_roff[k] + (e - s_ppre[k])];
     }
-    stage_batch(p, ctx, ent, nb, events);
+    stage_batch<BF16>(p, ctx, ent, nb, events);
   }
   if (tid < md)
     p.stage_cnt[tid * STAGE_BLOCKS + b] =
@@ -1123,19 +1106,32 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
   add_stat(stat_copy(p, row) + SNN_STAT_REMOTE_EVENTS, events, s_red);
 }
 
-// Expansion and staging in one pass (two-level routing): block b takes the
-// nodes b, b + nblocks, ...  A node's messages are loaded EXPAND_PER_THREAD
-// consecutive ones per thread; every set bit g of a mask is one receive entry
-// (source, pair index of partition G*n + g: the node's destinations are
-// consecutive in the source's list, so the pair indices follow the message's
-// first one).  The entries go into the partition's receive list (positions
-// from LDS counters: the block owns the node's partitions) and into an LDS
-// buffer, at positions from a block scan of the masks' bit counts; the
-// buffer is staged per delay (stage_batch) when it is full and at the end,
-// without reading the receive lists back.  Messages whose entries do not fit
-// the buffer's free space are taken in the next round.
-// Block b of nblocks; dyn holds EXPAND_STAGE_LDS bytes of LDS.
+__device__ __forceinline__ uint32_t popc_mask(uint32_t m) { return __popc(m); }
+__device__ __forceinline__ uint32_t popc_mask(uint64_t m) { return __popcll(m); }
+__device__ __forceinline__ uint32_t lowest_bit(uint32_t m) { return __ffs(m) - 1; }
+__device__ __forceinline__ uint32_t lowest_bit(uint64_t m) {
+  return __ffsll(static_cast<unsigned long long>(m)) - 1;
+}
+
+// Mask expansion at the destination node (the bridge's forwarding of
+// Sec. IV-B), with or without the staging of the entries (STAGE): block b
+// takes the nodes b, b + nblocks, ...  A node's messages are loaded
+// EXPAND_PER_THREAD consecutive ones per thread; every set bit g of a mask is
+// one receive entry (source, pair index of partition G*n + g: the node's
+// destinations are consecutive in the source's list, so the pair indices
+// follow the message's first one).  The entries go into the partition's
+// receive list (positions from LDS counters: the block owns the node's
+// partitions).  With STAGE they also go into an LDS buffer, at positions from
+// a block scan of the masks' bit counts, and the buffer is staged per delay
+// (stage_batch) when it is full and at the end, without reading the receive
+// lists back; messages whose entries do not fit the buffer's free space are
+// taken in the next round.
+// Block b of nblocks; with STAGE, dyn holds EXPAND_STAGE_LDS bytes of LDS.
+// WIDE: groups of more than NARROW_G partitions (masks held in 64 bits,
+// otherwise in 32).
+template <bool BF16, bool STAGE, bool WIDE>
 __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblocks, uint64_t* dyn) {
+  using MaskT = std::conditional_t<WIDE, uint64_t, uint32_t>;
   constexpr uint32_t NW = RECV_THREADS / 64;
   constexpr uint32_t R = RECV_PER_THREAD;
   constexpr uint32_t EU = EXPAND_PER_THREAD;
@@ -1160,12 +1156,14 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
   uint64_t events = 0, entries = 0;
   // stages the n buffered entries (uniform n)
   auto stage_buffer = [&](uint32_t n) {
-    for (uint32_t b0 = 0; b0 < n; b0 += RECV_BATCH) {
-      const uint32_t nb = min(n - b0, RECV_BATCH);
-      uint64_t ent[R];
+    if constexpr (STAGE) {
+      for (uint32_t b0 = 0; b0 < n; b0 += RECV_BATCH) {
+        const uint32_t nb = min(n - b0, RECV_BATCH);
+        uint64_t ent[R];
 #pragma unroll
-      for (int v = 0; v < R; ++v) ent[v] = s_ent[b0 + min(tid * R + v, nb - 1)];
-      stage_batch(p, ctx, ent, nb, events);
+        for (int v = 0; v < R; ++v) ent[v] = s_ent[b0 + min(tid * R + v, nb - 1)];
+        stage_batch<BF16>(p, ctx, ent, nb, events);
+      }
     }
   };
   uint32_t n_buf = 0;   // entries in the buffer (uniform)
@@ -1174,46 +1172,48 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
     const uint32_t cnt = static_cast<uint32_t>(
         min(static_cast<uint64_t>(bcnt[n * CNT_STRIDE]), p.bucket_off[n + 1] - off));
     const uint32_t gn = min(p.G, p.P - p.G * n);             // partitions of this node
+    const MaskT valid = gn == 8 * sizeof(MaskT) ? ~MaskT(0) : (MaskT(1) << gn) - 1;
     __syncthreads();   // the previous node is done with l_run, l_off
     if (tid < NG) l_run[tid] = 0;
     if (tid <= gn) l_off[tid] = p.recv_off[p.G * n + tid];
     for (uint32_t m0 = 0; m0 < cnt;) {
-      uint64_t w0[EU], pair[EU];
-      uint32_t mask[EU], mine = 0;
+      uint64_t w0[EU], w1[EU];
+      MaskT mask[EU];
+      uint32_t mine = 0;
 #pragma unroll
       for (int v = 0; v < EU; ++v) {
         const uint32_t m = m0 + tid * EU + v;
         const uint64_t at = 2 * (off + min(m, cnt - 1));
         w0[v] = p.bucket[at];
-        pair[v] = p.bucket[at + 1];
+        w1[v] = p.bucket[at + 1];
       }
 #pragma unroll
       for (int v = 0; v < EU; ++v) {
         const bool in = m0 + tid * EU + v < cnt;
-        const uint32_t mk = static_cast<uint32_t>(w0[v] >> 32) & 0xFFu;
-        mask[v] = in ? mk & ((1u << gn) - 1u) : 0u;
-        if (in && mask[v] != mk) atomicOr(&p.st->error, ERR_ROUTE);
-        mine += __popc(mask[v]);
+        if (in && (w1[v] & ~static_cast<uint64_t>(valid))) atomicOr(&p.st->error, ERR_ROUTE);
+        mask[v] = in ? static_cast<MaskT>(w1[v]) & valid : 0u;
+        mine += popc_mask(mask[v]);
       }
       if (tid < NG) l_cnt[tid] = 0;
       if (tid == 0) s_taken = s_added = 0;
       uint32_t total;
       uint32_t at = block_excl_scan(mine, s_wsum, &total);   // ends with the block's view of l_cnt = 0
-      const uint32_t room = EXPAND_BUF - n_buf;
+      const uint32_t room = STAGE ? EXPAND_BUF - n_buf : 0xFFFFFFFFu;
       uint32_t taken = 0, added = 0;
 #pragma unroll
       for (int v = 0; v < EU; ++v) {
-        const uint32_t pc = __popc(mask[v]);
+        const uint32_t pc = popc_mask(mask[v]);
         const bool in = m0 + tid * EU + v < cnt;
         if (in && at + pc <= room) {   // taken (the taken messages are a prefix)
           const uint64_t s = w0[v] & 0xFFFFFFFFull;
-          uint32_t mm = mask[v];
+          const uint64_t pair = w0[v] >> 32;
+          MaskT mm = mask[v];
           uint32_t k = 0;
           while (mm) {
-            const uint32_t g = __ffs(mm) - 1;
+            const uint32_t g = lowest_bit(mm);
             mm &= mm - 1;
-            const uint64_t e = s | ((pair[v] + k) << ENTRY_SRC_BITS);
-            s_ent[n_buf + at + k] = e;
+            const uint64_t e = s | ((pair + k) << ENTRY_SRC_BITS);
+            if constexpr (STAGE) s_ent[n_buf + at + k] = e;
             const uint32_t rk = atomicAdd(&l_cnt[g], 1u);
             const uint64_t pos = l_off[g] + l_run[g] + rk;
             if (pos < l_off[g + 1]) p.recv[pos] = e;
@@ -1234,7 +1234,7 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
       const uint32_t loaded = min(cnt - m0, EU * RECV_THREADS);
       if (tid < NG) l_run[tid] += l_cnt[tid];
       entries += tid == 0 ? round_added : 0u;
-      n_buf += round_added;
+      if constexpr (STAGE) n_buf += round_added;
       m0 += round_taken;
       if (round_taken < loaded) {   // the buffer is full: stage it
         stage_buffer(n_buf);
@@ -1245,11 +1245,18 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
     if (tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
   }
   stage_buffer(n_buf);
-  if (tid < md)
+  if (STAGE && tid < md)
     p.stage_cnt[tid * STAGE_BLOCKS + b] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
   uint64_t* sc = stat_copy(p, row);
   add_stats(sc + SNN_STAT_REMOTE_EVENTS, events, sc + SNN_STAT_RECV_ENTRIES, entries, s_red);
+}
+
+// Mask expansion alone (the step-by-step path): expansion blocks over the
+// nodes, the receive lists as output.
+__global__ __launch_bounds__(RECV_THREADS) void k_expand(KParams p) {
+  if (p.G > NARROW_G) expand_stage_block<false, false, true>(p, blockIdx.x, gridDim.x, nullptr);
+  else expand_stage_block<false, false, false>(p, blockIdx.x, gridDim.x, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1262,38 +1269,85 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
 // into sub-bin (slot, tile, d, w).  That sub-bin is written by this block
 // only, once per ring cycle, and read by the tile's update D - d steps later:
 // positions and counts need no atomics.
-// The runs (source segments, then queues) are taken as one flat sequence:
-// one thread per segment loads its start and length, a block scan
-// concatenates them, and the events are taken in rounds of DELIVER_ROUND,
-// GATHER_UNROLL per thread held in registers (the owner of an event is found
-// by a power-of-two search).  A round is sorted where it stands: each event's
-// rank in its tile comes from an LDS counter, a scan of the counts gives the
-// tiles' starts, the events are placed in tile order in LDS (8 bytes each),
-// and consecutive threads then write consecutive positions of one sub-bin.
-// PART selects what a block does: DELIVER_ALL; DELIVER_LOCAL (the source
-// segments only, beside the receive side) followed by DELIVER_REMOTE (the
-// queues, appended after the counts the local part published).
+// Runs (the source segments in batches of a block's width, then the QPB
+// queues) are taken as one flat sequence per batch: one thread per run loads
+// its start and length, a block scan concatenates them, and the events are
+// taken in rounds of DELIVER_ROUND, GATHER_UNROLL per thread held in
+// registers (the owner of an event is found by a power-of-two search).  A
+// round is sorted where it stands: each event's rank in its tile comes from
+// an LDS counter, a scan of the counts gives the tiles' starts, the events
+// are placed in tile order in LDS (8 bytes each), and consecutive threads
+// then write consecutive positions of one sub-bin.
+// PART: DELIVER_ALL takes the queues after the sources (one kernel per row,
+// the queues complete at launch); DELIVER_SPLIT waits between the two for
+// every staging block of the same launch to have published its queues
+// (wait_staged), so the local part overlaps the staging and the tile counts
+// stay in LDS across both parts.
 // dyn holds deliver_lds_bytes(n_tiles) bytes.
-enum DeliverPart { DELIVER_ALL, DELIVER_LOCAL, DELIVER_REMOTE };
+enum DeliverPart { DELIVER_ALL, DELIVER_SPLIT };
 constexpr uint32_t DELIVER_ROUND = GATHER_UNROLL * DELIVER_THREADS;
 static_assert(DELIVER_ROUND <= 65536, "window positions fit 16 bits");
-template <DeliverPart PART>
+
+// Polls of a device-scope wait before it gives up with ERR_TIMEOUT (every
+// wait in these kernels ends; each poll sleeps about 128 cycles).
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+// Called by every thread of a staging block when its queues and their counts
+// are written: makes them visible at device scope, then counts the block in.
+__device__ void signal_staged(const KParams& p) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(p.sync + SYNC_STAGED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until all STAGE_BLOCKS staging blocks of this launch are counted in,
+// then makes their writes visible to the block.  Every thread calls it.
+__device__ void wait_staged(const KParams& p) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(p.sync + SYNC_STAGED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           STAGE_BLOCKS) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins == SPIN_LIMIT) {
+        atomicOr(&p.st->error, ERR_TIMEOUT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Called by every thread of a delivery block of the combined launch when it
+// is done; the last of the n_deliver blocks resets the launch's counters for
+// the next launch (stream order makes the reset visible to it).
+__device__ void retire_deliver(const KParams& p, uint32_t n_deliver) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old =
+        __hip_atomic_fetch_add(p.sync + SYNC_RETIRED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == n_deliver - 1) {
+      __hip_atomic_store(p.sync + SYNC_STAGED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p.sync + SYNC_RETIRED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <DeliverPart PART, bool BF16>
 __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t* dyn) {
-  constexpr bool LOCAL = PART != DELIVER_REMOTE;
-  constexpr bool REMOTE = PART != DELIVER_LOCAL;
   constexpr uint32_t NT = DELIVER_THREADS;
   constexpr uint32_t NW = NT / 64;
   constexpr uint32_t QPB = STAGE_BLOCKS / DELIVER_BLOCKS;                 // queues per block
-  constexpr uint32_t SRC_BATCH = NT - (REMOTE ? QPB : 0);                 // sources per batch
+  static_assert(QPB <= NT, "one queue per thread");
   Event* s_sorted = reinterpret_cast<Event*>(dyn);                        // [DELIVER_ROUND]
   uint32_t* l_cnt = reinterpret_cast<uint32_t*>(s_sorted + DELIVER_ROUND);  // [n_tiles]
   uint32_t* l_run = l_cnt + p.n_tiles;                                    // [n_tiles]
   uint32_t* l_pre = l_run + p.n_tiles;                                    // [n_tiles]
-  __shared__ uint64_t s_base[NT];   // first event of each segment (synapse or queue index)
-  __shared__ uint32_t s_pre[NT];    // segment starts in the concatenation
+  __shared__ uint64_t s_base[NT];   // first event of each run (synapse or queue index)
+  __shared__ uint32_t s_pre[NT];    // run starts in the concatenation
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
-  __shared__ uint32_t s_qc[QPB];    // queue lengths
   const uint32_t tid = threadIdx.x;
 
   const uint32_t nF = p.st->n_fired;
@@ -1301,9 +1355,8 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
   if (slot >= p.D) slot -= p.D;
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t D = p.D;
-  if (REMOTE && tid < QPB) s_qc[tid] = p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS];
   for (uint32_t i = tid; i < p.n_tiles; i += NT) {
-    l_run[i] = LOCAL ? 0u : p.bin_cnt[subbin(p, slot, i, d, w)];
+    l_run[i] = 0;
     l_cnt[i] = 0;
   }
   __syncthreads();
@@ -1355,27 +1408,11 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
     __syncthreads();
   };
 
-  // segments: this block's fired sources (w + m * DELIVER_BLOCKS), batches of
-  // SRC_BATCH, then, with the last batch, its QPB queues of delay d
-  const uint32_t M = LOCAL && nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
-  const Event* q0 = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + w) * p.stage_cap;
-  for (uint32_t m0 = 0;; m0 += SRC_BATCH) {
-    const uint32_t nsrc = min(M - min(m0, M), SRC_BATCH);
-    const bool last = m0 + nsrc >= M;
-    const uint32_t nseg = nsrc + (REMOTE && last ? QPB : 0u);
-    uint32_t len = 0;
-    if (tid < nsrc) {
-      const uint32_t s = p.fired[w + (m0 + tid) * DELIVER_BLOCKS];
-      const uint64_t o = static_cast<uint64_t>(s) * D;
-      const uint32_t a = p.delay_off[o + d - 1], z = p.delay_off[o + d];
-      s_base[tid] = static_cast<uint64_t>(p.row_ptr[s]) + a;
-      len = z - a;
-      events += len;
-    }
-    if (REMOTE && last && tid >= nsrc && tid < nseg) {
-      s_base[tid] = static_cast<uint64_t>(tid - nsrc) * DELIVER_BLOCKS * p.stage_cap;
-      len = s_qc[tid - nsrc];
-    }
+  // the events of nseg runs (s_base, len per thread), QUEUE: queue runs of
+  // staged events, else synapse runs of the CSR
+  auto take_runs = [&](uint32_t nseg, uint32_t len, auto queue_tag) {
+    constexpr bool QUEUE = decltype(queue_tag)::value;
+    const Event* q0 = p.stage + (static_cast<uint64_t>(d - 1) * STAGE_BLOCKS + w) * p.stage_cap;
     uint32_t tot;
     const uint32_t ex = block_excl_scan(len, s_wsum, &tot);
     s_pre[tid] = ex;
@@ -1392,64 +1429,82 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
         const uint32_t e = r0 + min(i, n - 1);
         const uint32_t k = owner_of<NT / 2>(s_pre, nseg, e);
         const uint64_t x = s_base[k] + (e - s_pre[k]);
-        if (PART == DELIVER_LOCAL) {
-          tg[v] = p.tgt_delay[x] & 0x07FFFFFFu;
-          wq[v] = quantize_w(p, load_weight(p, x));
-        } else if (PART == DELIVER_REMOTE) {
+        if constexpr (QUEUE) {
           const Event ev = q0[x];
           tg[v] = ev.tgt;
           wq[v] = ev.wq;
-        } else if (k < nsrc) {   // both kinds of segment (one kernel per row)
-          tg[v] = p.tgt_delay[x] & 0x07FFFFFFu;
-          wq[v] = quantize_w(p, load_weight(p, x));
         } else {
-          const Event ev = q0[x];
-          tg[v] = ev.tgt;
-          wq[v] = ev.wq;
+          tg[v] = p.tgt_delay[x] & 0x07FFFFFFu;
+          wq[v] = quantize_w(p, load_weight<BF16>(p, x));
         }
       }
       sort_round(n, tg, wq, on);
     }
-    if (last) break;
     __syncthreads();   // s_pre, s_base are rewritten by the next batch
+  };
+
+  // the own-partition synapses of delay d of this block's fired sources
+  // (w + m * DELIVER_BLOCKS), NT sources per batch
+  const uint32_t M = nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
+  for (uint32_t m0 = 0; m0 < M; m0 += NT) {
+    const uint32_t nsrc = min(M - m0, NT);
+    uint32_t len = 0;
+    if (tid < nsrc) {
+      const uint32_t s = p.fired[w + (m0 + tid) * DELIVER_BLOCKS];
+      const uint64_t o = static_cast<uint64_t>(s) * D;
+      const uint32_t a = p.delay_off[o + d - 1], z = p.delay_off[o + d];
+      s_base[tid] = static_cast<uint64_t>(p.row_ptr[s]) + a;
+      len = z - a;
+      events += len;
+    }
+    take_runs(nsrc, len, std::false_type{});
+  }
+  if constexpr (PART == DELIVER_SPLIT) wait_staged(p);
+  // the staged remote synapses of delay d: queues w, w + DELIVER_BLOCKS, ...
+  {
+    uint32_t len = 0;
+    if (tid < QPB) {
+      s_base[tid] = static_cast<uint64_t>(tid) * DELIVER_BLOCKS * p.stage_cap;
+      len = p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS];
+    }
+    take_runs(QPB, len, std::true_type{});
   }
 
   // publish this block's counts for slot `slot`, every tile (zeros included)
   for (uint32_t i = tid; i < p.n_tiles; i += NT)
     p.bin_cnt[subbin(p, slot, i, d, w)] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_run[i]), p.bin_cap));
-  if (LOCAL) add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
+  add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
 }
 
+template <bool BF16>
 __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   extern __shared__ uint64_t lds_u64[];
-  deliver_block<DELIVER_ALL>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
+  deliver_block<DELIVER_ALL, BF16>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
 }
 
-// The staged remote synapses of (w, d) = (blockIdx.x, blockIdx.y + 1), after
-// k_recv_local delivered the local ones.
-__global__ __launch_bounds__(DELIVER_THREADS) void k_deliver_remote(KParams p) {
-  extern __shared__ uint64_t lds_u64[];
-  deliver_block<DELIVER_REMOTE>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
-}
-
-// Two independent jobs in one launch, so that they overlap: blocks
+// The receive side and the delivery of a step in one launch: blocks
 // [0, STAGE_BLOCKS) expand and stage the two-level messages
-// (expand_stage_block), the rest deliver the fired sources' local synapses
-// (deliver_block, local part; block STAGE_BLOCKS + i takes (w, d) =
-// (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)).  The local part needs only
-// the fired list, not the receive side.  Three blocks of 8 waves per CU (6
-// waves per SIMD, at most 80 VGPRs), so that all blocks of both jobs are
-// resident at once.
+// (expand_stage_block) and count themselves in when their queues are
+// written; the rest (block STAGE_BLOCKS + i takes (w, d) =
+// (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)) deliver the fired sources'
+// local synapses meanwhile (they need only the fired list), wait for the
+// staging blocks, and bin the staged remote synapses.  Only higher-numbered
+// blocks wait, for lower-numbered ones, which are dispatched first; three
+// blocks of 8 waves per CU (6 waves per SIMD, at most 80 VGPRs) keep all of
+// them resident at once in any case.
 static_assert(RECV_THREADS == DELIVER_THREADS, "one block size for both jobs");
+template <bool BF16, bool WIDE>
 __global__ __launch_bounds__(RECV_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
-void k_recv_local(KParams p) {
+void k_recv_deliver(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   if (blockIdx.x < STAGE_BLOCKS) {
-    expand_stage_block(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
+    expand_stage_block<BF16, true, WIDE>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
+    signal_staged(p);
   } else {
     const uint32_t i = blockIdx.x - STAGE_BLOCKS;
-    deliver_block<DELIVER_LOCAL>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
+    deliver_block<DELIVER_SPLIT, BF16>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
+    retire_deliver(p, gridDim.x - STAGE_BLOCKS);
   }
 }
 
@@ -1495,7 +1550,7 @@ static inline void mark(hipEvent_t* marks, int kind, int end, hipStream_t s) {
   if (marks) (void)hipEventRecord(marks[2 * kind + end], s);
 }
 
-bool fused_route_ok(const KParams& p) { return p.n_nodes <= FUSED_MAX_NODES; }
+bool fused_route_ok(const KParams& p) { return p.n_nodes <= FUSED_MAX_NODES && p.G <= NARROW_G; }
 
 hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks, bool route) {
   mark(marks, SNN_KERNEL_UPDATE, 0, s);
@@ -1508,7 +1563,7 @@ hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks, boo
 }
 
 static size_t route_kernel_lds_bytes(const KParams& p) {
-  return route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, p.n_nodes);
+  return route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, p.n_nodes, p.G > NARROW_G);
 }
 
 hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
@@ -1517,7 +1572,8 @@ hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* m
     if (!routed) {
       mark(marks, SNN_KERNEL_ROUTE_TWO_LEVEL, 0, s);
       if (p.n_nodes <= ROUTE_MAX_NODES_LDS)
-        hipLaunchKernelGGL(k_route_two_level, dim3(ROUTE_BLOCKS), dim3(ROUTE_THREADS),
+        hipLaunchKernelGGL(p.G > NARROW_G ? k_route_two_level<true> : k_route_two_level<false>,
+                           dim3(ROUTE_BLOCKS), dim3(ROUTE_THREADS),
                            route_kernel_lds_bytes(p), s, p);
       else
         hipLaunchKernelGGL(k_route_two_level_direct, dim3(1024), dim3(ROUTE_THREADS), 0, s, p);
@@ -1525,7 +1581,8 @@ hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* m
     }
     if (!defer_expand) {
       mark(marks, SNN_KERNEL_EXPAND, 0, s);
-      hipLaunchKernelGGL(k_expand, dim3(p.n_nodes), dim3(EXPAND_THREADS), 0, s, p);
+      hipLaunchKernelGGL(k_expand, dim3(std::min(p.n_nodes, STAGE_BLOCKS)), dim3(RECV_THREADS), 0,
+                         s, p);
       mark(marks, SNN_KERNEL_EXPAND, 1, s);
     }
   }
@@ -1548,61 +1605,70 @@ static size_t deliver_lds_bytes(uint32_t n_tiles) {
 constexpr size_t EXPAND_STAGE_LDS =
     EXPAND_BUF * sizeof(uint64_t) + RECV_BATCH * (sizeof(uint64_t) + sizeof(uint32_t));
 
-static size_t recv_local_lds_bytes(const KParams& p) {
+static size_t recv_deliver_lds_bytes(const KParams& p) {
   return std::max(EXPAND_STAGE_LDS, deliver_lds_bytes(p.n_tiles));
+}
+
+template <bool BF16>
+static void launch_deliver_t(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
+                             bool fused_expand) {
+  if (fused_expand && mode != SNN_ROUTE_FLAT) {
+    mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
+    void (*kern)(KParams) =
+        p.G > NARROW_G ? k_recv_deliver<BF16, true> : k_recv_deliver<BF16, false>;
+    hipLaunchKernelGGL(kern, dim3(STAGE_BLOCKS + DELIVER_BLOCKS * (p.D - 1)), dim3(RECV_THREADS),
+                       recv_deliver_lds_bytes(p), s, p);
+    mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
+    return;
+  }
+  mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
+  hipLaunchKernelGGL(k_recv_stage<BF16>, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p,
+                     mode == SNN_ROUTE_FLAT ? 1 : 0);
+  mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
+  mark(marks, SNN_KERNEL_DELIVER, 0, s);
+  hipLaunchKernelGGL(k_deliver<BF16>, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
+                     deliver_lds_bytes(p.n_tiles), s, p);
+  mark(marks, SNN_KERNEL_DELIVER, 1, s);
 }
 
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
                           bool fused_expand) {
-  if (fused_expand && mode != SNN_ROUTE_FLAT) {
-    mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
-    hipLaunchKernelGGL(k_recv_local, dim3(STAGE_BLOCKS + DELIVER_BLOCKS * (p.D - 1)),
-                       dim3(RECV_THREADS), recv_local_lds_bytes(p), s, p);
-    mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
-    mark(marks, SNN_KERNEL_DELIVER, 0, s);
-    hipLaunchKernelGGL(k_deliver_remote, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
-                       deliver_lds_bytes(p.n_tiles), s, p);
-    mark(marks, SNN_KERNEL_DELIVER, 1, s);
-    return hipGetLastError();
-  }
-  mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
-  hipLaunchKernelGGL(k_recv_stage, dim3(STAGE_BLOCKS), dim3(RECV_THREADS), 0, s, p,
-                     mode == SNN_ROUTE_FLAT ? 1 : 0);
-  mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
-  mark(marks, SNN_KERNEL_DELIVER, 0, s);
-  hipLaunchKernelGGL(k_deliver, dim3(DELIVER_BLOCKS, p.D - 1), dim3(DELIVER_THREADS),
-                     deliver_lds_bytes(p.n_tiles), s, p);
-  mark(marks, SNN_KERNEL_DELIVER, 1, s);
+  if (p.bf16) launch_deliver_t<true>(p, mode, s, marks, fused_expand);
+  else launch_deliver_t<false>(p, mode, s, marks, fused_expand);
   return hipGetLastError();
+}
+
+// Static plus dynamic LDS of kernel f fits the device, and f may use dyn bytes.
+static hipError_t allow_lds(const void* f, size_t dyn, int lds_max) {
+  hipFuncAttributes fa{};
+  hipError_t e = hipFuncGetAttributes(&fa, f);
+  if (e != hipSuccess) return e;
+  if (int64_t(fa.sharedSizeBytes + dyn) > lds_max) return hipErrorInvalidConfiguration;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
 }
 
 hipError_t prepare_kernels(KParams& p) {
   int dev = 0, lds_max = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  hipFuncAttributes fa{}, fr{}, fh{};
-  if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_deliver));
-  if (e == hipSuccess) e = hipFuncGetAttributes(&fr, reinterpret_cast<const void*>(&k_deliver_remote));
-  if (e == hipSuccess) e = hipFuncGetAttributes(&fh, reinterpret_cast<const void*>(&k_recv_local));
   if (e != hipSuccess) return e;
   // the deliver kernels' per-tile counters must leave room for a round
-  const size_t dl = deliver_lds_bytes(p.n_tiles), rl = recv_local_lds_bytes(p);
-  if (int64_t(fa.sharedSizeBytes + dl) > lds_max || int64_t(fr.sharedSizeBytes + dl) > lds_max ||
-      int64_t(fh.sharedSizeBytes + rl) > lds_max)
-    return hipErrorInvalidConfiguration;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_route_two_level),
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          static_cast<int>(route_kernel_lds_bytes(p)));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dl));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deliver_remote),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dl));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recv_local),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rl));
-  return e;
+  const size_t dl = deliver_lds_bytes(p.n_tiles), rl = recv_deliver_lds_bytes(p);
+  const std::pair<const void*, size_t> kernels[] = {
+      {reinterpret_cast<const void*>(&k_deliver<false>), dl},
+      {reinterpret_cast<const void*>(&k_deliver<true>), dl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<false, false>), rl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<true, false>), rl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<false, true>), rl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<true, true>), rl},
+      {reinterpret_cast<const void*>(&k_route_two_level<false>), route_kernel_lds_bytes(p)},
+      {reinterpret_cast<const void*>(&k_route_two_level<true>), route_kernel_lds_bytes(p)},
+  };
+  for (const auto& k : kernels) {
+    e = allow_lds(k.first, k.second, lds_max);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_flush(const KParams& p, hipStream_t s) {

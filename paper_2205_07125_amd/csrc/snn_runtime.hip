@@ -51,8 +51,8 @@ uint32_t n_nodes_of(const snn_params* p) {
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  uint64_t st, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat, stage_cnt,
-      stage, bin_cnt, dirty, bins, stats, pois_lut, log_off, log, total;
+  uint64_t st, sync, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat,
+      stage_cnt, stage, bin_cnt, dirty, bins, stats, pois_lut, log_off, log, total;
 };
 
 Layout layout(const snn_params* p) {
@@ -65,6 +65,7 @@ Layout layout(const snn_params* p) {
   };
   const uint64_t D = p->max_delay + 1, md = p->max_delay, tiles = tiles_of(p->n_neurons);
   L.st = take(sizeof(DevState));
+  L.sync = take(sizeof(uint32_t) * SYNC_WORDS);
   L.lookback = take(sizeof(uint64_t) * tiles);
   L.fired = take(sizeof(uint32_t) * uint64_t(p->n_neurons));
   L.bucket_cnt = take(2 * sizeof(uint32_t) * CNT_STRIDE * n_nodes_of(p));
@@ -120,7 +121,8 @@ snn_status check_params(const snn_params* p) {
   if (p->n_partitions == 0 || p->n_partitions > SNN_MAX_PARTITIONS)
     return fail(SNN_ERR_INVALID_ARG, "n_partitions=%u outside [1, 65535]", p->n_partitions);
   if (p->gpus_per_node == 0 || p->gpus_per_node > SNN_MAX_GPUS_PER_NODE)
-    return fail(SNN_ERR_INVALID_ARG, "gpus_per_node=%u outside [1, 8]", p->gpus_per_node);
+    return fail(SNN_ERR_INVALID_ARG, "gpus_per_node=%u outside [1, %u]", p->gpus_per_node,
+                SNN_MAX_GPUS_PER_NODE);
   if (p->max_delay == 0 || p->max_delay > SNN_MAX_DELAY)
     return fail(SNN_ERR_INVALID_ARG, "max_delay=%u outside [1, 15]", p->max_delay);
   if (p->n_ref > 255) return fail(SNN_ERR_INVALID_ARG, "n_ref=%u > 255", p->n_ref);
@@ -255,6 +257,7 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.ring = net->ring;
   char* ws = static_cast<char*>(workspace);
   k.st = reinterpret_cast<DevState*>(ws + L.st);
+  k.sync = reinterpret_cast<uint32_t*>(ws + L.sync);
   k.lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   k.fired = reinterpret_cast<uint32_t*>(ws + L.fired);
   k.bucket_cnt = reinterpret_cast<uint32_t*>(ws + L.bucket_cnt);
@@ -283,9 +286,11 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
     delete c;
     return fail(SNN_ERR_HIP, "create: reading vp_ptr[N], row_ptr[N]: %s", hipGetErrorString(e));
   }
-  if (tot[0] < 0 || tot[1] < 0 || tot[1] >= (int64_t(1) << 40)) {
+  if (tot[0] < 0 || tot[1] < 0 || tot[1] >= (int64_t(1) << 40) || tot[0] >= (int64_t(1) << 32)) {
     delete c;
-    return fail(SNN_ERR_INVALID_ARG, "vp_ptr[N] = %lld or row_ptr[N] = %lld out of range",
+    return fail(SNN_ERR_INVALID_ARG,
+                "vp_ptr[N] = %lld (< 2^32 required: messages carry 32-bit pair indices) or "
+                "row_ptr[N] = %lld (< 2^40) out of range",
                 (long long)tot[0], (long long)tot[1]);
   }
   k.n_pairs = uint64_t(tot[0]);
@@ -429,12 +434,13 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
   // the launches queue up behind each other as in a normal run, so no start
   // event fires on an idle queue ahead of its kernel.
   const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(h->kp);
+  // expansion, staging and delivery of a two-level step share one launch
   const bool launched[SNN_NKERNEL] = {true,
                                       mode != SNN_ROUTE_FLAT && !fused,
-                                      false,   // expansion runs inside the staging kernel
+                                      false,
                                       mode != SNN_ROUTE_TWO_LEVEL,
                                       true,
-                                      true};
+                                      mode == SNN_ROUTE_FLAT};
   std::vector<hipEvent_t> marks(size_t(2) * SNN_NKERNEL * n_steps, nullptr);
   snn_status st = SNN_OK;
   for (auto& e : marks) {
@@ -488,6 +494,8 @@ static snn_status sync_and_check(snn_handle h, DevState* out) {
   if (out) *out = st;
   if (st.error & ERR_ROUTE)
     return fail(SNN_ERR_HIP, "receive entry without a matching destination partition");
+  if (st.error & ERR_TIMEOUT)
+    return fail(SNN_ERR_HIP, "a device-side wait between blocks of one launch timed out");
   if (st.error)
     return fail(SNN_ERR_CAPACITY, "device capacity overflow (bits 0x%x: 1 bucket, 2 receive "
                 "list, 4 flat list, 8 spike log)", st.error);
@@ -623,12 +631,9 @@ snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entri
   uint64_t at = 0;
   for (uint32_t i = 0; i < nl; ++i) {
     if (!sizes[i]) continue;
-    if (which == 2)   // first word of each two-word message
-      HIP_TRY(hipMemcpy2DAsync(static_cast<char*>(entries) + at * 8, 8, base + off[i] * 16, 16, 8,
-                               sizes[i], hipMemcpyDeviceToHost, h->stream));
-    else
-      HIP_TRY(hipMemcpyAsync(static_cast<char*>(entries) + at * 8, base + off[i] * 8, sizes[i] * 8,
-                             hipMemcpyDeviceToHost, h->stream));
+    const uint64_t w = which == 2 ? 16 : 8;   // a message is two words
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(entries) + at * w, base + off[i] * w, sizes[i] * w,
+                           hipMemcpyDeviceToHost, h->stream));
     at += sizes[i];
   }
   HIP_TRY(hipStreamSynchronize(h->stream));

@@ -92,7 +92,8 @@ struct snn_setup {
 extern "C" {
 
 snn_status snn_setup_create(const snn_setup_spec* spec, const uint32_t* part_start,
-                            const double* cross_frac, snn_setup_handle* out) {
+                            const double* cross_frac, const int32_t* part_map,
+                            snn_setup_handle* out) {
   if (!spec || !out) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
   if (spec->n_neurons < 2 || spec->n_neurons > SNN_MAX_NEURONS)
@@ -100,7 +101,8 @@ snn_status snn_setup_create(const snn_setup_spec* spec, const uint32_t* part_sta
   if (spec->max_delay == 0 || spec->max_delay > SNN_MAX_DELAY)
     return fail(SNN_ERR_INVALID_ARG, "max_delay=%u outside [1, 15]", spec->max_delay);
   if (spec->gpus_per_node == 0 || spec->gpus_per_node > SNN_MAX_GPUS_PER_NODE)
-    return fail(SNN_ERR_INVALID_ARG, "gpus_per_node=%u outside [1, 8]", spec->gpus_per_node);
+    return fail(SNN_ERR_INVALID_ARG, "gpus_per_node=%u outside [1, %u]", spec->gpus_per_node,
+                SNN_MAX_GPUS_PER_NODE);
   if (spec->n_partitions == 0 || spec->n_partitions > SNN_MAX_PARTITIONS)
     return fail(SNN_ERR_INVALID_ARG, "n_partitions=%u outside [1, 65535]", spec->n_partitions);
   if (spec->weight_type != SNN_W_FP32 && spec->weight_type != SNN_W_BF16)
@@ -117,8 +119,15 @@ snn_status snn_setup_create(const snn_setup_spec* spec, const uint32_t* part_sta
   gs.w_exc = spec->w_exc;
   gs.w_inh = spec->w_inh;
   gs.w_jitter = spec->w_jitter;
+  gs.n_clusters = spec->n_clusters;
+  gs.p_in = spec->p_in;
   syn_gen* gen = syn_create(&gs, part_start, cross_frac);
   if (!gen) return fail(SNN_ERR_INVALID_ARG, "network description rejected by the generator");
+  if (part_map && syn_set_part_map(gen, part_map) != 0) {
+    syn_destroy(gen);
+    return fail(SNN_ERR_INVALID_ARG, "partition map rejected (entries in [0, n_partitions), "
+                "materialised or clustered topology only)");
+  }
 
   snn_setup* h = new (std::nothrow) snn_setup();
   if (!h) {

@@ -30,7 +30,7 @@ With every pair connected, a GPU in a group of s has s - 1 level-1
 connections.  On average it bridges (n_groups - 1) / s groups, each fanning
 out to s GPUs.  That is a mean of about s + N / s - 2 connections, which is least at s near
 sqrt(N): 88 for N = 2000, the mean the paper reports for its 2,000 GPUs
-(Sec. VI, Fig. 4).
+(Sec. V, Fig. 4).
 
 Plain numpy; nothing here runs on the GPU.  The device path groups
 partitions by node: partition p is on node p div G.  relabel() renumbers
@@ -265,7 +265,7 @@ def partition_graph(part: np.ndarray, vp_ptr: np.ndarray, vp_part: np.ndarray,
 
 def routing_report(PG: np.ndarray, WG: np.ndarray, n_groups: int, iters: int = 8,
                    seed: int = 0, balance: str = "traffic") -> dict:
-    """Algorithm 2 end to end, and what the paper measures of it (Sec. VI,
+    """Algorithm 2 end to end, and what the paper measures of it (Sec. V,
     Figs. 3(b) and 4).  Groups, bridges and TB come first.  Then, per GPU,
     the connections under flat and two-level routing, and the traffic T =
     PG * WG * WG leaving it towards other groups (level 2) under both."""
@@ -294,7 +294,7 @@ def routing_report(PG: np.ndarray, WG: np.ndarray, n_groups: int, iters: int = 8
 def _main(argv=None) -> None:
     """Connections per GPU, flat against two-level, on a seeded random PG in
     which a GPU reaches a given mean number of others.  This is the count of
-    Sec. VI, Fig. 4."""
+    Sec. V, Fig. 4."""
     import argparse
     import json
     ap = argparse.ArgumentParser(prog="python -m paper_2205_07125_amd.grouping")

@@ -1,7 +1,7 @@
 """Per-link traffic of a routed step, read from the device routing buffers:
 who sends how many receive entries (flat view) or messages (two-level view)
 to whom.  The paper's latency model waits for the GPU pair with the largest
-traffic (Sec. V) and counts connections per GPU (Sec. VI, Fig. 4); this is
+traffic (Sec. V) and counts connections per GPU (Sec. V, Fig. 4); this is
 that bookkeeping for the step in the buffers.  Host-side analysis of what the
 kernels produced; nothing here is on the simulation path."""
 from __future__ import annotations

@@ -65,9 +65,12 @@ def derived_params(wl) -> dict:
 
 
 class HostNetwork:
-    """Arrays of include/snn.h's snn_network_dev, built on the host."""
+    """Arrays of include/snn.h's snn_network_dev, built on the host.
+    part_map: explicit neuron -> partition map (the neuron-GPU mapping PM of
+    Sec. IV-A) in place of the workload's contiguous partitions."""
 
-    def __init__(self, wl, n_threads: int = 0, verbose: bool = False):
+    def __init__(self, wl, n_threads: int = 0, verbose: bool = False,
+                 part_map: np.ndarray | None = None):
         import synth  # seeded input description (partition starts, cross fractions)
         self.wl = wl
         L = _abi.lib()
@@ -77,13 +80,16 @@ class HostNetwork:
             remote_frac=wl.remote_frac, w_exc=wl.w_exc, w_inh=wl.w_inh, w_jitter=wl.w_jitter,
             gpus_per_node=wl.gpus_per_node,
             weight_type=_abi.SNN_W_BF16 if wl.weight_type == "bf16" else _abi.SNN_W_FP32,
-            n_threads=n_threads, verbose=1 if verbose else 0)
+            n_threads=n_threads, verbose=1 if verbose else 0, n_clusters=wl.n_clusters,
+            p_in=wl.p_in)
         starts = synth.partition_starts(wl)
         fracs = synth.cross_fracs(wl)
+        pm = None if part_map is None else np.ascontiguousarray(part_map, np.int32)
         h = _P()
         t0 = time.time()
         _abi.check(L.snn_setup_create(ctypes.byref(spec), None if starts is None else _ptr(starts),
-                                      None if fracs is None else _ptr(fracs), ctypes.byref(h)))
+                                      None if fracs is None else _ptr(fracs),
+                                      None if pm is None else _ptr(pm), ctypes.byref(h)))
         try:
             sizes = [ctypes.c_uint64() for _ in range(4)]
             _abi.check(L.snn_setup_sizes(h, *[ctypes.byref(s) for s in sizes]))

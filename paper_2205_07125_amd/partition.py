@@ -10,9 +10,11 @@ GPU's total weight near the mean sum(W) / N.
 The paper gives the loop of Algorithm 1 but not its rules.  This module
 reads it so:
   * Each pass starts every GPU from one seed neuron.  The first pass takes
-    them farthest-first: the heaviest neuron, then each time the neuron
-    least connected to the seeds so far, so that separate clusters each get
-    a seed.  Later passes draw N distinct neurons with a seeded generator.
+    them farthest-first: the heaviest neuron, then each time the neuron the
+    most hops away from the seeds so far, and among those the one least
+    connected to them.  Neurons with no path to a seed are the farthest, so
+    each connected component gets a seed before any gets a second.  Later
+    passes draw N distinct neurons with a seeded generator.
   * Then the GPUs take turns, in order.  A GPU whose weight is still below
     the mean takes the unassigned neuron with the largest summed connection
     probability, in either direction, to its members.  That is x_{i,t}, the
@@ -109,19 +111,27 @@ def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
 
 def spread_seeds(A: sp.csr_matrix, W: np.ndarray, n_gpus: int) -> np.ndarray:
     """Farthest-first seeds: the heaviest neuron (lowest id on ties), then
-    repeatedly the neuron with the least summed connection probability to
-    the seeds so far (lowest id on ties).  Clusters with no links between
-    them each get a seed before any cluster gets a second."""
+    repeatedly the unseeded neuron with the most hops to its nearest seed;
+    ties go to the least summed connection probability to the seeds so far,
+    then to the heaviest, then to the lowest id.  A neuron without a path to
+    any seed is infinitely far, so every connected component gets a seed
+    before any gets a second, whether its clusters are dense or sparse; inside
+    a component the summed probability separates clusters that hops cannot
+    (every pair one hop apart, but weakly linked)."""
+    from scipy.sparse.csgraph import shortest_path
+    W = np.asarray(W, np.float64)
     M = len(W)
     seeds = [int(np.argmax(W))]
+    dist = np.full(M, np.inf)
     tot = np.zeros(M)
-    taken = np.zeros(M, bool)
     for _ in range(n_gpus - 1):
         j = seeds[-1]
-        taken[j] = True
+        dist = np.minimum(dist, shortest_path(A, unweighted=True, indices=j))
         lo, hi = A.indptr[j], A.indptr[j + 1]
         tot[A.indices[lo:hi]] += A.data[lo:hi]
-        seeds.append(int(np.argmin(np.where(taken, np.inf, tot))))
+        d = dist.copy()
+        d[seeds] = -1.0
+        seeds.append(int(np.lexsort((np.arange(M), -W, tot, -d))[0]))
     return np.array(seeds, np.int64)
 
 
@@ -208,6 +218,54 @@ def plan(P, W: np.ndarray, n_gpus: int, n_groups: int, iters: int = 4, seed: int
     rep.update(PM=pm, PG=PG, WG=WG, cut_traffic=cut_traffic(P, W, pm),
                gpu_traffic=gpu_traffic(P, W, pm, n_gpus))
     return rep
+
+
+def connectivity(src: np.ndarray, tgt: np.ndarray, n_neurons: int,
+                 rate: np.ndarray | float = 1.0) -> tuple[sp.csr_matrix, np.ndarray]:
+    """Algorithm 1's inputs from a synapse list: P[i, j] = number of synapses
+    i -> j (a connection weight; only its pattern and relative size matter to
+    the greedy rule and the cut), W[i] = out-degree of i times its firing rate
+    (the data volume neuron i sends)."""
+    src = np.asarray(src, np.int64)
+    tgt = np.asarray(tgt, np.int64)
+    P = sp.csr_matrix((np.ones(len(src)), (src, tgt)), shape=(n_neurons, n_neurons))
+    P.sum_duplicates()
+    W = np.bincount(src, minlength=n_neurons).astype(np.float64) * rate
+    return P, W
+
+
+def device_map(P, W: np.ndarray, n_gpus: int, gpus_per_node: int, kind: str = "alg1",
+               iters: int = 4, seed: int = 0) -> tuple[np.ndarray, dict]:
+    """A neuron -> partition map for the device path, whose node n holds
+    partitions [n G, (n+1) G).  The neurons are mapped to GPUs by Algorithm 1
+    (kind="alg1"), by contiguous id ranges ("contiguous") or by a seeded
+    random balanced assignment ("random"); the GPUs are then grouped by
+    Algorithm 2 into groups of G and renumbered so that each group is one
+    node (grouping.relabel).  Returns (map, info) with info holding the
+    GPU-level map before renumbering, PG, WG, the groups and the cut
+    traffic."""
+    from . import grouping
+    W = np.asarray(W, np.float64)
+    M = len(W)
+    G = int(gpus_per_node)
+    if n_gpus % G:
+        raise ValueError("the GPU count must be a multiple of the group size")
+    if kind == "alg1":
+        pm = partition_neurons(P, W, n_gpus, iters, seed)
+    elif kind == "contiguous":
+        pm = (np.arange(M) * n_gpus) // M
+    elif kind == "random":
+        pm = np.random.default_rng(seed).permutation(np.arange(M) % n_gpus)
+    else:
+        raise ValueError("kind must be 'alg1', 'contiguous' or 'random'")
+    PG, WG = gpu_graph(P, W, pm, n_gpus)
+    group_of = grouping.group_gpus(PG, WG, n_gpus // G, iters, seed)
+    if np.any(np.bincount(group_of, minlength=n_gpus // G) != G):
+        raise ValueError("Algorithm 2 did not return groups of equal size")
+    new_id = grouping.relabel(group_of)
+    info = dict(gpu_map=pm, PG=PG, WG=WG, group_of=group_of, new_id=new_id,
+                cut_traffic=cut_traffic(P, W, pm), gpu_traffic=gpu_traffic(P, W, pm, n_gpus))
+    return new_id[pm].astype(np.int32), info
 
 
 def device_layout(pm: np.ndarray, group_of: np.ndarray, gpus_per_node: int) -> dict:

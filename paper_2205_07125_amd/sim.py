@@ -166,19 +166,23 @@ class Simulation:
         return sizes
 
     def read_routes(self, which: int, sources_only: bool = False):
-        """which 0 flat lists, 1 expanded lists (per partition), 2 node buckets
-        (per node); uint64 elements (see include/snn.h), or just the source ids
-        with sources_only."""
+        """which 0 flat lists, 1 expanded lists (per partition): uint64 entries;
+        2 node buckets (per node): (n, 2) uint64 messages (source | first pair
+        index << 32, partition mask); see include/snn.h.  With sources_only,
+        just the source ids."""
         L = _abi.lib()
         nl = self.wl.n_nodes if which == 2 else self.wl.n_partitions
         sizes = np.zeros(nl, np.uint64)
         n = ctypes.c_uint64()
         _abi.check(L.snn_read_routes(self.h, which, sizes.ctypes.data_as(ctypes.c_void_p), None, 0,
                                      ctypes.byref(n)))
-        ent = np.zeros(max(n.value, 1), np.uint64)
+        shape = (max(n.value, 1), 2) if which == 2 else (max(n.value, 1),)
+        ent = np.zeros(shape, np.uint64)
         _abi.check(L.snn_read_routes(self.h, which, sizes.ctypes.data_as(ctypes.c_void_p),
-                                     ent.ctypes.data_as(ctypes.c_void_p), ent.size, ctypes.byref(n)))
+                                     ent.ctypes.data_as(ctypes.c_void_p), shape[0], ctypes.byref(n)))
         if sources_only:
+            if which == 2:
+                ent = ent[:, 0]
             bits = _abi.ENTRY_SRC_BITS if which != 2 else 32
             ent = (ent & np.uint64((1 << bits) - 1)).astype(np.uint32)
         offs = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])

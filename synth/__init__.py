@@ -14,6 +14,7 @@ import numpy as np
 
 from .workloads import (  # noqa: F401  (re-exported)
     TOPO_BATCHED,
+    TOPO_CLUSTERED,
     TOPO_LOOPBACK,
     TOPO_LOOPBACK_SETS,
     TOPO_MATERIALIZED,
@@ -39,6 +40,8 @@ class _Spec(ctypes.Structure):
         ("w_exc", ctypes.c_double),
         ("w_inh", ctypes.c_double),
         ("w_jitter", ctypes.c_double),
+        ("n_clusters", ctypes.c_uint32),
+        ("p_in", ctypes.c_double),
     ]
 
 
@@ -57,6 +60,10 @@ def lib() -> ctypes.CDLL:
         L.syn_destroy.argtypes = [P]
         L.syn_edges.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, P, P, P, P, P]
         L.syn_part_map.argtypes = [P, P]
+        L.syn_set_part_map.restype = ctypes.c_int
+        L.syn_set_part_map.argtypes = [P, P]
+        L.syn_cluster_of.restype = ctypes.c_uint32
+        L.syn_cluster_of.argtypes = [P, ctypes.c_uint32]
         L.syn_initial_u.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_uint32, P]
         L.syn_lognormal_sizes.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32, P]
@@ -83,7 +90,7 @@ def partition_starts(wl: Workload) -> np.ndarray | None:
 
 
 def partition_sizes(wl: Workload) -> np.ndarray:
-    if wl.topology == TOPO_MATERIALIZED:
+    if wl.topology in (TOPO_MATERIALIZED, TOPO_CLUSTERED):
         P = wl.n_partitions
         base, rem = divmod(wl.n_neurons, P)
         return np.array([base + (1 if p < rem else 0) for p in range(P)], dtype=np.uint32)
@@ -110,18 +117,27 @@ def cross_fracs(wl: Workload) -> np.ndarray | None:
 
 
 class Generator:
-    """Handle over the native generator for one workload."""
+    """Handle over the native generator for one workload.  part_map: an
+    explicit neuron -> partition map (int32[n_neurons]) in place of the
+    workload's contiguous partitions (materialised and clustered topologies),
+    e.g. the neuron-GPU mapping a partitioning produced."""
 
-    def __init__(self, wl: Workload):
+    def __init__(self, wl: Workload, part_map: np.ndarray | None = None):
         self.wl = wl
         spec = _Spec(wl.seed, wl.n_neurons, wl.k_in, wl.max_delay, wl.n_partitions, wl.topology,
-                     wl.vp_set_size, wl.remote_frac, wl.w_exc, wl.w_inh, wl.w_jitter)
+                     wl.vp_set_size, wl.remote_frac, wl.w_exc, wl.w_inh, wl.w_jitter,
+                     wl.n_clusters, wl.p_in)
         self._starts = partition_starts(wl)
         self._fracs = cross_fracs(wl)
         h = lib().syn_create(ctypes.byref(spec), _ptr(self._starts), _ptr(self._fracs))
         if not h:
             raise ValueError(f"generator rejected workload {wl.name}")
         self.handle = ctypes.c_void_p(h)
+        if part_map is not None:
+            pm = np.ascontiguousarray(part_map, np.int32)
+            if len(pm) != wl.n_neurons or lib().syn_set_part_map(self.handle, _ptr(pm)) != 0:
+                raise ValueError("partition map rejected: one entry per neuron in "
+                                 "[0, n_partitions), materialised or clustered topology")
 
     def close(self):
         if self.handle:
@@ -150,6 +166,11 @@ class Generator:
         out = np.empty(self.wl.n_neurons, np.int32)
         lib().syn_part_map(self.handle, _ptr(out))
         return out
+
+    def clusters(self) -> np.ndarray:
+        """Cluster of every neuron (clustered topology)."""
+        f = lib().syn_cluster_of
+        return np.array([f(self.handle, i) for i in range(self.wl.n_neurons)], np.uint32)
 
     def vp_set(self, src: int) -> np.ndarray | None:
         out = np.empty(max(self.wl.vp_set_size, 1), np.uint16)

@@ -13,14 +13,22 @@ enum {
   S_W = 3,      /* weight jitter */
   S_INIT = 4,   /* initial membrane state */
   S_SET = 5,    /* per-source vp sets */
-  S_SIZE = 6    /* partition sizes */
+  S_SIZE = 6,   /* partition sizes */
+  S_CLUSTER = 7 /* cluster of a neuron */
 };
 
 struct syn_gen {
   syn_spec spec;
-  uint32_t* part_start; /* P+1 (MATERIALIZED, BATCHED) */
+  uint32_t* part_start; /* P+1 (MATERIALIZED, BATCHED, CLUSTERED) */
+  int32_t* part_map;    /* N, explicit neuron -> partition map, or NULL */
   double* cross_frac;   /* P (BATCHED) */
   uint16_t* vp_sets;    /* n_neurons * vp_set_size (LOOPBACK_SETS) */
+  /* CLUSTERED: members of each cluster, ascending, and each neuron's cluster
+     and position among its cluster's members */
+  uint32_t* cl_start;   /* n_clusters + 1 */
+  uint32_t* cl_member;  /* N */
+  uint32_t* cl_of;      /* N */
+  uint32_t* cl_pos;     /* N */
 };
 
 /* SplitMix64 output function (Steele, Lea, Flood 2014). */
@@ -61,8 +69,13 @@ syn_gen* syn_create(const syn_spec* spec, const uint32_t* part_start,
     return NULL;
   uint32_t P = spec->n_partitions;
   int need_parts = spec->topology == SYN_TOPO_MATERIALIZED ||
-                   spec->topology == SYN_TOPO_BATCHED;
-  if (spec->topology > SYN_TOPO_BATCHED) return NULL;
+                   spec->topology == SYN_TOPO_BATCHED ||
+                   spec->topology == SYN_TOPO_CLUSTERED;
+  if (spec->topology > SYN_TOPO_CLUSTERED) return NULL;
+  if (spec->topology == SYN_TOPO_CLUSTERED &&
+      (spec->n_clusters == 0 || spec->n_clusters > spec->n_neurons ||
+       !(spec->p_in >= 0.0 && spec->p_in <= 1.0)))
+    return NULL;
   if (need_parts) {
     if (!part_start || part_start[0] != 0 || part_start[P] != spec->n_neurons)
       return NULL;
@@ -86,6 +99,28 @@ syn_gen* syn_create(const syn_spec* spec, const uint32_t* part_start,
   if (spec->topology == SYN_TOPO_BATCHED) {
     g->cross_frac = (double*)malloc(sizeof(double) * P);
     memcpy(g->cross_frac, cross_frac, sizeof(double) * P);
+  }
+  if (spec->topology == SYN_TOPO_CLUSTERED) {
+    /* each neuron's cluster, then the members of each cluster (counting sort) */
+    uint32_t N = spec->n_neurons, C = spec->n_clusters;
+    g->cl_start = (uint32_t*)calloc((size_t)C + 1, sizeof(uint32_t));
+    g->cl_member = (uint32_t*)malloc(sizeof(uint32_t) * N);
+    g->cl_of = (uint32_t*)malloc(sizeof(uint32_t) * N);
+    g->cl_pos = (uint32_t*)malloc(sizeof(uint32_t) * N);
+    if (!g->cl_start || !g->cl_member || !g->cl_of || !g->cl_pos) { syn_destroy(g); return NULL; }
+    for (uint32_t i = 0; i < N; ++i) {
+      g->cl_of[i] = range32((uint32_t)(syn_hash(spec->seed, S_CLUSTER, i, 0) >> 32), C);
+      g->cl_start[g->cl_of[i] + 1]++;
+    }
+    for (uint32_t c = 0; c < C; ++c) g->cl_start[c + 1] += g->cl_start[c];
+    uint32_t* fill = (uint32_t*)calloc(C, sizeof(uint32_t));
+    if (!fill) { syn_destroy(g); return NULL; }
+    for (uint32_t i = 0; i < N; ++i) {
+      uint32_t c = g->cl_of[i];
+      g->cl_pos[i] = fill[c];
+      g->cl_member[g->cl_start[c] + fill[c]++] = i;
+    }
+    free(fill);
   }
   if (spec->topology == SYN_TOPO_LOOPBACK_SETS) {
     /* Floyd's sampling of m distinct values from [1, P-1], keyed by source. */
@@ -119,15 +154,37 @@ syn_gen* syn_create(const syn_spec* spec, const uint32_t* part_start,
 void syn_destroy(syn_gen* g) {
   if (!g) return;
   free(g->part_start);
+  free(g->part_map);
+  free(g->cl_start);
+  free(g->cl_member);
+  free(g->cl_of);
+  free(g->cl_pos);
   free(g->cross_frac);
   free(g->vp_sets);
   free(g);
 }
 
 uint32_t syn_part_of(const syn_gen* g, uint32_t x) {
+  if (g->part_map) return (uint32_t)g->part_map[x];
   if (!g->part_start) return 0;
   return find_part(g->part_start, g->spec.n_partitions, x);
 }
+
+int syn_set_part_map(syn_gen* g, const int32_t* part) {
+  if (!part || (g->spec.topology != SYN_TOPO_MATERIALIZED &&
+                g->spec.topology != SYN_TOPO_CLUSTERED))
+    return -1;
+  for (uint32_t i = 0; i < g->spec.n_neurons; ++i)
+    if (part[i] < 0 || (uint32_t)part[i] >= g->spec.n_partitions) return -1;
+  int32_t* m = (int32_t*)malloc(sizeof(int32_t) * g->spec.n_neurons);
+  if (!m) return -1;
+  memcpy(m, part, sizeof(int32_t) * g->spec.n_neurons);
+  free(g->part_map);
+  g->part_map = m;
+  return 0;
+}
+
+uint32_t syn_cluster_of(const syn_gen* g, uint32_t x) { return g->cl_of ? g->cl_of[x] : 0; }
 
 void syn_part_map(const syn_gen* g, int32_t* part) {
   uint32_t N = g->spec.n_neurons;
@@ -166,11 +223,22 @@ void syn_edge(const syn_gen* g, uint32_t tgt, uint32_t k, uint32_t* src_out,
       if (src >= tgt) src++;
     }
     vp = q;
+  } else if (s->topology == SYN_TOPO_CLUSTERED) {
+    uint32_t c = g->cl_of[tgt], c0 = g->cl_start[c], cn = g->cl_start[c + 1] - c0;
+    int inside = (double)lo1 < s->p_in * 4294967296.0 && cn > 1;
+    if (inside) {   /* uniform over the cluster's other members */
+      uint32_t r = range32(hi1, cn - 1);
+      src = g->cl_member[c0 + (r < g->cl_pos[tgt] ? r : r + 1)];
+    } else {
+      src = range32(hi1, N - 1);
+      if (src >= tgt) src++;
+    }
+    vp = syn_part_of(g, tgt);
   } else {
     src = range32(hi1, N - 1);
     if (src >= tgt) src++;
     if (s->topology == SYN_TOPO_MATERIALIZED) {
-      vp = find_part(g->part_start, s->n_partitions, tgt);
+      vp = syn_part_of(g, tgt);
     } else {
       int remote = (double)lo1 < s->remote_frac * 4294967296.0;
       if (!remote) vp = 0;

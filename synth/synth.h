@@ -47,7 +47,13 @@ enum {
   /* partitions of uneven size, all on this GPU; a target in partition q draws
      a source outside q with probability cross_frac[q] (size-weighted, i.e.
      uniform over neurons outside q), else uniform inside q; vp = q */
-  SYN_TOPO_BATCHED = 3
+  SYN_TOPO_BATCHED = 3,
+  /* all partitions on this GPU, neurons in n_clusters clusters (each neuron's
+     cluster drawn uniformly, so clusters are scattered over the ids); a target
+     draws its source inside its own cluster with probability p_in, else
+     uniform over all neurons; vp = part_of(tgt).  Connectivity with locality
+     for a partitioning to find (Algorithm 1) */
+  SYN_TOPO_CLUSTERED = 4
 };
 
 typedef struct {
@@ -61,16 +67,25 @@ typedef struct {
   double remote_frac;     /* SYN_TOPO_LOOPBACK[_SETS] only */
   double w_exc, w_inh;    /* mV */
   double w_jitter;        /* 0: none; else w *= 1 + w_jitter * (U[0,1) - 1/2) */
+  uint32_t n_clusters;    /* SYN_TOPO_CLUSTERED only */
+  double p_in;            /* SYN_TOPO_CLUSTERED only */
 } syn_spec;
 
 typedef struct syn_gen syn_gen;
 
-/* part_start: n_partitions+1 ascending neuron offsets (MATERIALIZED, BATCHED);
-   ignored (may be NULL) for the loopback topologies, where every neuron is in
-   partition 0.  cross_frac: n_partitions probabilities (BATCHED only).
-   Returns NULL on invalid input. */
+/* part_start: n_partitions+1 ascending neuron offsets (MATERIALIZED, BATCHED,
+   CLUSTERED); ignored (may be NULL) for the loopback topologies, where every
+   neuron is in partition 0.  cross_frac: n_partitions probabilities (BATCHED
+   only).  Returns NULL on invalid input. */
 syn_gen* syn_create(const syn_spec* spec, const uint32_t* part_start,
                     const double* cross_frac);
+/* An explicit neuron -> partition map (n_neurons entries in [0, n_partitions))
+   replacing the contiguous ranges of part_start: part_of() and the vp of
+   every synapse follow it (MATERIALIZED and CLUSTERED only).  Returns 0, or
+   -1 if the topology takes no map or an entry is out of range. */
+int syn_set_part_map(syn_gen* g, const int32_t* part);
+/* Cluster of a neuron (CLUSTERED; 0 otherwise). */
+uint32_t syn_cluster_of(const syn_gen* g, uint32_t neuron);
 void syn_destroy(syn_gen* g);
 
 /* One synapse, pure function of (spec, tgt, k). */

@@ -21,6 +21,7 @@ TOPO_MATERIALIZED = 0
 TOPO_LOOPBACK = 1
 TOPO_LOOPBACK_SETS = 2
 TOPO_BATCHED = 3
+TOPO_CLUSTERED = 4
 
 
 @dataclass(frozen=True)
@@ -43,6 +44,9 @@ class Workload:
     size_scale: float = 1.0
     cross_lo: float = 0.0
     cross_hi: float = 0.0
+    # clustered connectivity (TOPO_CLUSTERED)
+    n_clusters: int = 0
+    p_in: float = 0.0
     # synapses
     max_delay: int = 10
     w_exc: float = 0.5
@@ -175,6 +179,18 @@ HEAVY = _add(Workload(
 PAPER_SHARE_4K = _add(PAPER_SHARE.replace(
     name="paper_share_4k", k_in=500, n_partitions=4000, seed=12,
     description="5e6 neurons, K=500, 4,000 virtual partitions / 500 nodes"))
+
+# Clustered connectivity for the partitioning of Sec. IV-A to work on: 64k
+# neurons in 64 scattered clusters, 80 % of each neuron's 100 inputs from its
+# own cluster; 64 partitions, all materialised, in nodes of 16 (groups wider
+# than 8 GPUs: 16-bit node masks).  Partitions are contiguous id ranges unless
+# an explicit map (from Algorithm 1) is given.
+CLUSTERED = _add(Workload(
+    name="clustered", n_neurons=65_536, k_in=100, n_partitions=64, gpus_per_node=16,
+    topology=TOPO_CLUSTERED, seed=21, n_clusters=64, p_in=0.8, w_ext_mv=0.1,
+    forced=1, rate_on_hz=20.0, rate_off_hz=20.0, period_steps=1, on_steps=1,
+    description="65,536 neurons in 64 clusters (80 % of inputs inside), 64 partitions in "
+                "nodes of 16, forced 20 Hz"))
 
 WORKLOADS = dict(_W)
 

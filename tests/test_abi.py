@@ -60,7 +60,7 @@ def test_workspace_size_and_ring_stride():
 
 @pytest.mark.parametrize("field,value", [
     ("n_neurons", 0), ("n_neurons", (1 << 27) + 1), ("n_partitions", 0),
-    ("n_partitions", 65536), ("gpus_per_node", 0), ("gpus_per_node", 9), ("max_delay", 0),
+    ("n_partitions", 65536), ("gpus_per_node", 0), ("gpus_per_node", 65), ("max_delay", 0),
     ("max_delay", 16), ("n_ref", 256), ("weight_type", 2), ("flags", 2), ("log_steps", 0),
     ("input_bound", 0.0), ("input_bound", -1.0), ("input_bound", float("nan")),
     ("input_bound", float("inf")),

@@ -56,7 +56,7 @@ def _pmc_dir(tmp_path, name, counter, rows):
 
 def test_pmc_summary_scales_by_the_copy(bench, tmp_path, capsys):
     upd = "void snn::k_update<true>(snn::KParams)"
-    rl = "snn::k_recv_local(snn::KParams)"
+    rl = "snn::k_recv_deliver<false>(snn::KParams)"
     # three dispatches each: the first third is dropped, then the median
     fetch = _pmc_dir(tmp_path, "f", "FETCH_SIZE",
                      [(upd, 999), (upd, 100), (upd, 102), (rl, 5), (rl, 50), (rl, 50)])
@@ -67,12 +67,12 @@ def test_pmc_summary_scales_by_the_copy(bench, tmp_path, capsys):
     out = tmp_path / "traffic.json"
     bench.pmc_summary(fetch, write, cf, cw, 1 << 20, "demo", str(out))
     rec = json.load(open(out))["demo"]
-    assert set(rec) == {"update", "recv_local"}
+    assert set(rec) == {"update", "recv_deliver"}
     u = rec["update"]
     assert u["fetch_scale"] == 2.0 and u["write_scale"] == 1.0
     assert u["fetch_kib"] == 101.0 and u["write_kib"] == 40.0
     assert u["bytes_per_launch"] == 101.0 * 1024 * 2 + 40.0 * 1024
-    assert rec["recv_local"]["write_kib"] == 0.0
+    assert rec["recv_deliver"]["write_kib"] == 0.0
     assert u["kernel_hash"] == bench.kernel_source_hash()
     # a second workload is added beside the first
     bench.pmc_summary(fetch, write, cf, cw, 1 << 20, "other", str(out))

@@ -92,9 +92,9 @@ def test_paper_share_full_size_sampled():
     assert sum(len(b) for b in buckets) == want_msgs == cnt[T - 1, 3] + cnt[T - 1, 4]
     assert sum(len(x) for x in xrecv) == want_entries == cnt[T - 1, 6] == cnt[T - 1, 5]
     for n, b in enumerate(buckets):
-        src = (b & np.uint64(0xFFFFFFFF)).astype(np.int64)
-        mask = ((b >> np.uint64(32)) & np.uint64(0xFF)).astype(np.int64)
-        assert np.all(mask > 0)
+        src = (b[:, 0] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        mask = b[:, 1]
+        assert np.all(mask > 0) and np.all(mask < np.uint64(1 << G))
         assert np.all(part[src] // G != n) or n == 0    # loopback: own node is node 0
         assert len(np.unique(src)) == len(src)          # one message per source and node
     print("[gpu] routing invariants hold at full size", flush=True)

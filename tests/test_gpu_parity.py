@@ -20,11 +20,12 @@ STAT_MAP = [oracle.SPIKES, oracle.LOCAL_EVENTS, oracle.REMOTE_EVENTS, oracle.MSG
             oracle.MSG_L2, oracle.FLAT_MSGS, oracle.RECV_ENTRIES]
 
 
-def _pair(wl, **simkw):
-    from paper_2205_07125_amd import Simulation
-    print(f"[gpu] building {wl.name} N={wl.n_neurons} K={wl.k_in}", flush=True)
-    sim = Simulation(wl, **simkw)
-    orc = oracle.sim_for_workload(wl)
+def _pair(wl, part_map=None, **simkw):
+    from paper_2205_07125_amd import HostNetwork, Simulation
+    print(f"[gpu] building {wl.name} N={wl.n_neurons} K={wl.k_in} P={wl.n_partitions} "
+          f"G={wl.gpus_per_node}", flush=True)
+    sim = Simulation(wl, host=HostNetwork(wl, part_map=part_map), **simkw)
+    orc = oracle.sim_for_workload(wl, part_map=part_map)
     return sim, orc
 
 
@@ -63,17 +64,29 @@ def _same_routes(sim, orc, wl, where, mode=ROUTE_BOTH):
     if two:
         b_g, b_o = sim.read_routes(2), orc.buckets()
         for n in range(wl.n_nodes):
-            # device messages carry the first destination's list index above bit 40
-            g = np.sort(b_g[n] & np.uint64((1 << 40) - 1))
-            assert np.array_equal(g, np.sort(b_o[n])), f"bucket {n} at {where}"
+            # (source, mask) multisets; device messages also carry the pair
+            # index of the node's first destination above bit 32
+            src = b_g[n][:, 0] & np.uint64(0xFFFFFFFF)
+            g = sorted(zip(src.tolist(), b_g[n][:, 1].tolist()))
+            assert g == sorted(map(tuple, b_o[n].tolist())), f"bucket {n} at {where}"
+            if len(src) and host is not None:
+                # the pair index is s's first destination in node n
+                s_ = src.astype(np.int64)
+                j = (b_g[n][:, 0] >> np.uint64(32)).astype(np.int64)
+                assert np.all(j >= host.vp_ptr[s_]) and np.all(j < host.vp_ptr[s_ + 1])
+                G = wl.gpus_per_node
+                assert np.all(host.vp_part[j] // G == n)
+                first = (j == host.vp_ptr[s_]) | (host.vp_part[np.maximum(j - 1, 0)] // G != n)
+                assert np.all(first)
 
 
 def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH, fused=False,
-              fp64_bound=1e-4):
+              fp64_bound=1e-4, part_map=None):
     """fused: each step as snn_step_route + snn_deliver (two-level routing in
     the update kernel) instead of snn_step, snn_route, snn_deliver.
-    fp64_bound: largest |u - u_fp64| allowed (mV); None reports it only."""
-    sim, orc = _pair(wl, log_steps=n_steps)
+    fp64_bound: largest |u - u_fp64| allowed (mV); None reports it only.
+    part_map: explicit neuron -> partition map of the network."""
+    sim, orc = _pair(wl, part_map=part_map, log_steps=n_steps)
     stats_o = np.zeros((n_steps, 7), np.uint64)
     fired_o = []
     for t in range(n_steps):
@@ -232,21 +245,40 @@ def test_route_modes_give_identical_rasters():
     assert np.all(ka[:, 3] + ka[:, 4] <= kb[:, 5])
 
 
+def _oracle_steps(orc, n):
+    """n oracle steps -> (fired ids of each step, counters in device order)."""
+    fired, stats = [], np.zeros((n, 7), np.uint64)
+    for t in range(n):
+        orc.step()
+        fired.append(orc.fired())
+        stats[t] = orc.counters()[STAT_MAP]
+    return fired, stats
+
+
 def test_graph_replay_matches_oracle():
-    """snn_run with a captured step replayed 300 times equals the oracle."""
+    """snn_run replaying captured steps (16-step graphs, then one-step graphs
+    for the remainder) in both route modes equals the oracle: fired ids of
+    every step, all seven counters, and the state."""
     wl = synth.get_workload("tiny_active").replace(seed=7)
-    sim, orc = _pair(wl, log_steps=300)
-    sim.run(150, ROUTE_TWO_LEVEL, use_graph=True)
-    sim.sync()
-    counts_o, stats_o = orc.run(150)
-    _same_state(sim, orc, "after 150 graph steps")
-    sim.run(150, ROUTE_FLAT, use_graph=True)
-    c2, s2 = orc.run(150)
-    _same_state(sim, orc, "after 300 graph steps")
-    ids, counts = sim.read_spikes(0, 300)
-    assert np.array_equal(counts, np.concatenate([counts_o, c2]))
-    st = sim.read_counters(0, 300)
-    assert np.array_equal(st[:, :3], np.concatenate([stats_o, s2])[:, STAT_MAP][:, :3])
+    n = [150, 150, 17]               # 9 x 16 + 6 x 1, again in flat mode, then 16 + 1
+    modes = [ROUTE_TWO_LEVEL, ROUTE_FLAT, ROUTE_TWO_LEVEL]
+    sim, orc = _pair(wl, log_steps=sum(n))
+    fired, stats = [], []
+    for k, mode in zip(n, modes):
+        sim.run(k, mode, use_graph=True)
+        f, st = _oracle_steps(orc, k)
+        if mode == ROUTE_TWO_LEVEL:
+            st[:, 5] = 0              # flat entries are counted only when flat routing runs
+        else:
+            st[:, 3:5] = 0
+            st[:, 6] = 0
+        fired += f
+        stats.append(st)
+        _same_state(sim, orc, f"after {len(fired)} graph steps")
+    ids, counts = sim.read_spikes(0, len(fired))
+    assert np.array_equal(counts, np.array([len(f) for f in fired], np.uint32))
+    assert np.array_equal(ids, np.concatenate(fired).astype(np.int32))
+    assert np.array_equal(sim.read_counters(0, len(fired)), np.concatenate(stats))
 
 
 def test_graph_and_eager_agree():

@@ -1,6 +1,6 @@
 """GPU grouping, bridges and routing table (Algorithm 2, Sec. IV-B) against
 brute force on small cases, planted clusters, and the connection count that
-the paper reports for 2,000 GPUs (Sec. VI, Fig. 4).  CPU only."""
+the paper reports for 2,000 GPUs (Sec. V, Fig. 4).  CPU only."""
 import itertools
 
 import numpy as np
@@ -216,7 +216,7 @@ def test_connections_closed_form_full_exchange():
 
 
 def test_paper_connection_count_2000_gpus():
-    """2,000 GPUs where a GPU reaches 1,552 others on average (Sec. VI,
+    """2,000 GPUs where a GPU reaches 1,552 others on average (Sec. V,
     Fig. 4): groups of the size dense_group_size picks bring the mean down
     to the paper's 88."""
     N = 2000

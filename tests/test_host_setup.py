@@ -9,9 +9,9 @@ import synth
 from paper_2205_07125_amd import HostNetwork, derived_params
 
 
-def _check_network(wl, host):
+def _check_network(wl, host, part_map=None):
     """Vectorised comparison of the CSR layout with the canonical list."""
-    gen = synth.Generator(wl)
+    gen = synth.Generator(wl, part_map=part_map)
     e = gen.edges()
     part = gen.part_map().astype(np.int64)
     N, G, P = wl.n_neurons, wl.gpus_per_node, wl.n_partitions
@@ -99,6 +99,47 @@ def test_setup_matches_generator(name):
     }[name]
     host = HostNetwork(base, n_threads=4)
     _check_network(base, host)
+
+
+def _clustered_small():
+    return synth.get_workload("clustered").scaled(6000, k_in=40, n_partitions=12,
+                                                  gpus_per_node=12, n_clusters=10)
+
+
+def test_setup_clustered_with_partition_map():
+    """An explicit neuron -> partition map (scattered, as a partitioning of
+    the clustered net would give) is what the setup's rows, destination
+    lists and own-partition segments follow; wide nodes (12 partitions)."""
+    wl = _clustered_small()
+    pm = np.random.default_rng(3).integers(0, wl.n_partitions, wl.n_neurons).astype(np.int32)
+    host = HostNetwork(wl, n_threads=3, part_map=pm)
+    assert np.array_equal(host.part, pm)
+    _check_network(wl, host, part_map=pm)
+    # the default contiguous ranges too
+    _check_network(wl, HostNetwork(wl, n_threads=3))
+
+
+def test_clustered_generator_statistics():
+    """Clustered topology: no autapses, the fraction of inputs from the
+    target's own cluster is p_in plus the chance share of the rest, and the
+    clusters are scattered over the neuron ids."""
+    wl = _clustered_small().replace(p_in=0.7)
+    gen = synth.Generator(wl)
+    e = gen.edges()
+    cl = gen.clusters().astype(np.int64)
+    assert np.all(e["src"] != e["tgt"])
+    same = cl[e["src"]] == cl[e["tgt"]]
+    share = np.bincount(cl, minlength=wl.n_clusters) / wl.n_neurons
+    want = wl.p_in + (1 - wl.p_in) * float(np.sum(share ** 2))
+    m = len(same)
+    assert abs(same.mean() - want) < 5 * np.sqrt(want * (1 - want) / m)
+    # scattered: a contiguous block of ids holds many clusters
+    assert len(np.unique(cl[:500])) == wl.n_clusters
+    with pytest.raises(ValueError):
+        synth.Generator(wl, part_map=np.full(wl.n_neurons, wl.n_partitions, np.int32))
+    with pytest.raises(ValueError):
+        synth.Generator(synth.get_workload("paper_share").scaled(2000),
+                        part_map=np.zeros(2000, np.int32))
 
 
 def test_setup_independent_of_threads():

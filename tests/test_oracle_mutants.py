@@ -9,7 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_rng.py", "tests/test_oracle_lif.py",
-             "tests/test_oracle_routing.py", "tests/test_oracle_delivery.py"]
+             "tests/test_oracle_routing.py", "tests/test_oracle_delivery.py",
+             "tests/test_oracle_accuracy.py"]
 
 MUTANTS = {
     "philox_word_swap": ("uint32_t y0 = hi1 ^ x1 ^ k0;", "uint32_t y0 = hi1 ^ x3 ^ k0;"),
@@ -21,7 +22,7 @@ MUTANTS = {
     "fused_update": ("float v = f32((double)*u * (double)alpha);\n"
                      "    *u = f32((double)v + (double)I);",
                      "*u = f32((double)*u * (double)alpha + (double)I);"),
-    "mask_bit_shift": ("s->node_mask[node] |= 1u << (s->vps[j] - s->G * node);",
+    "mask_bit_shift": ("s->node_mask[node] |= (uint64_t)1 << (s->vps[j] - s->G * node);",
                        "s->node_mask[node] |= 1u << (s->vps[j] - s->G * node + 1);"),
     "own_partition": ("if (v == own) continue;", "if (v == own + 1) continue;"),
     "level_swap": ("if (node == own_node) s->stats[ORC_MSG_L1]++;",
@@ -35,6 +36,16 @@ MUTANTS = {
     "no_slot_clear": ("s->ring[(size_t)slot * s->N + i] = 0.0f;", ""),
     "fp64_weight": ("s->ring64[at] += s->e_w64[e];",
                     "s->ring64[at] += (double)(float)s->e_w64[e] * 1.0000001;"),
+    # the accuracy report
+    "acc_no_max_dv": ("if (dv > s->max_dv) s->max_dv = dv;", "(void)dv;"),
+    "acc_no_first_div": ("s->first_div = (int64_t)t;", "(void)t;"),
+    "acc_no_margin": ("if (margin < s->min_margin) s->min_margin = margin;", "(void)margin;"),
+    "acc_agree_always": ("if (agree) s->agree_steps++;", "s->agree_steps++;"),
+    "acc_dv_after_divergence": ("if (s->first_div < 0) {\n    if (!agree) {",
+                                "if (1) {\n    if (!agree && s->first_div < 0) {"),
+    "acc_max_u_reset": ("if (fabs(s->u64[i]) > s->max_abs_u) s->max_abs_u = fabs(s->u64[i]);",
+                        "if (fabs(s->u64[i]) > s->max_abs_u) s->max_abs_u = fabs(s->u64[i]);\n"
+                        "      if (s->u64[i] >= (double)s->theta) s->max_abs_u = 0;"),
 }
 
 

@@ -31,15 +31,30 @@ def test_fig2_fan_in():
     assert c[oracle.MSG_L1] == g["two_level_level1_messages"]
     assert c[oracle.MSG_L2] == g["two_level_level2_messages"]
     dnode = dst // G
-    masks = {int(m >> 32) for m in buckets[dnode]}
+    masks = {int(m[1]) for m in buckets[dnode]}
     assert masks == {g["two_level_mask"]}
-    src_nodes = {int(part[m & 0xFFFFFFFF]) // G for m in buckets[dnode]}
+    src_nodes = {int(part[m[0]]) // G for m in buckets[dnode]}
     assert len(src_nodes) == g["source_nodes_sending_to_destination_node"]
-    # after expansion inside the destination node one bridge hands partition
-    # dst its list: a single incoming connection
     assert sorted(xrecv[dst]) == sorted(flat[dst])
-    bridges = {dnode}
-    assert len(bridges) == g["connections_into_destination_after_expansion"]
+    # connections in the paper's sense, from the routed messages: which
+    # partition sends to which (the masks of the node buckets), routed by
+    # Algorithm 2's table with groups = nodes, where a source reaches another
+    # group through its own group's bridge, which forwards to the destination
+    from paper_2205_07125_amd import grouping
+    dest = np.zeros((P, P), bool)
+    for nd, b in enumerate(buckets):
+        for m in b:
+            s, mask = int(m[0]), int(m[1])
+            for bit in range(G):
+                if mask >> bit & 1:
+                    dest[part[s], G * nd + bit] = True
+    group_of = np.arange(P) // G
+    TB = grouping.routing_table(group_of, grouping.select_bridges(dest.astype(float), np.ones(P),
+                                                                  group_of))
+    hops = grouping.hop_matrix(dest, TB)
+    assert int(hops[:, dst].sum()) == g["connections_into_destination_after_expansion"]
+    # without the table (flat peer-to-peer) every source partition connects to dst
+    assert int(dest[:, dst].sum()) == g["flat_connections_into_destination"]
     for p in range(P):
         if p != dst:
             assert len(flat[p]) == 0 and len(xrecv[p]) == 0
@@ -65,7 +80,10 @@ def _check_routes(sim, edges, part, G, P):
         want_nodes += len(nodes)
         for nd in nodes:
             bits = vps[vps // G == nd] - G * nd
-            want_buckets.setdefault(int(nd), []).append((int(np.bitwise_or.reduce(1 << bits)), int(s)))
+            mask = 0
+            for bit in bits:
+                mask |= 1 << int(bit)
+            want_buckets.setdefault(int(nd), []).append((mask, int(s)))
     # I1: messages = distinct destination nodes per spike
     assert c[oracle.MSG_L1] + c[oracle.MSG_L2] == want_nodes
     assert sum(len(b) for b in buckets) == want_nodes
@@ -75,20 +93,20 @@ def _check_routes(sim, edges, part, G, P):
     assert c[oracle.FLAT_MSGS] == sum(len(v) for v in want_flat.values())
     # two-level buckets = brute force (mask, src) pairs
     for nd, b in enumerate(buckets):
-        got = sorted((int(m >> 32), int(m & 0xFFFFFFFF)) for m in b)
+        got = sorted((int(m[1]), int(m[0])) for m in b)
         assert got == sorted(want_buckets.get(nd, []))
     # I2: expansion reproduces the flat lists as multisets
     for p in range(P):
         assert sorted(xrecv[p].tolist()) == sorted(flat[p].tolist())
     # I4: entries = sum of mask popcounts
-    pop = sum(bin(int(m >> 32)).count("1") for b in buckets for m in b)
+    pop = sum(bin(int(m[1])).count("1") for b in buckets for m in b)
     assert pop == c[oracle.RECV_ENTRIES] == sum(len(x) for x in xrecv)
     # I6: masks nonzero, own-partition bit never set, only valid partitions;
     # level split by the source's own node
     l1 = 0
     for nd, b in enumerate(buckets):
         for m in b:
-            mask, s = int(m >> 32), int(m & 0xFFFFFFFF)
+            mask, s = int(m[1]), int(m[0])
             assert mask != 0 and mask < (1 << G)
             for bit in range(G):
                 if mask >> bit & 1:
@@ -103,9 +121,10 @@ def _check_routes(sim, edges, part, G, P):
 @settings(max_examples=60, deadline=None)
 @given(data=st.data())
 def test_routing_brute_force_random(data):
-    G = data.draw(st.sampled_from([1, 2, 4, 8]))
-    P = data.draw(st.integers(1, 16))
-    n = data.draw(st.integers(max(P, 2), 64))
+    # group sizes up to 64: masks of one to 64 bits, including the top bit
+    G = data.draw(st.sampled_from([1, 2, 4, 8, 16, 40, 63, 64]))
+    P = data.draw(st.integers(1, min(2 * G + 3, 140)))
+    n = data.draw(st.integers(max(P, 2), max(P, 2) + 64))
     # contiguous partitions, every partition non-empty
     cuts = sorted(data.draw(st.lists(st.integers(1, n - 1), min_size=P - 1, max_size=P - 1,
                                      unique=True))) if P > 1 else []

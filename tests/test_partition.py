@@ -182,6 +182,22 @@ def test_spread_seeds_one_per_separate_cluster():
     assert len(set(seeds.tolist())) == 7
 
 
+def test_spread_seeds_sparse_separate_clusters():
+    """Seven disjoint sparse clusters (about five in-cluster links per
+    neuron, so most neurons have no direct link to a seed): still one seed in
+    each cluster before any cluster gets a second."""
+    P, W = pt.synthetic_neurons(700, 7, 5.0, 0.0, seed=6)
+    A = pt._sym_csr(P)
+    from scipy.sparse.csgraph import connected_components
+    n_comp, comp = connected_components(A, directed=False)
+    seeds = pt.spread_seeds(A, W, n_comp)
+    assert len(set(comp[seeds].tolist())) == n_comp
+    # with more seeds than components, the extra ones go to the farthest neurons
+    more = pt.spread_seeds(A, W, n_comp + 3)
+    assert np.array_equal(more[:n_comp], seeds)
+    assert len(set(more.tolist())) == n_comp + 3
+
+
 def test_device_layout_contiguous_ranges():
     rng = np.random.default_rng(8)
     M, N, G = 200, 12, 4
