@@ -56,30 +56,58 @@ def kernel_source_hash(read=None) -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(wl_full, seconds_budget=20.0):
-    """The oracle (single-threaded C, FP64 + binary32 trajectories) on the same
-    structure at 1/100 of the neurons (same in-degree, partitions, rate)."""
-    import numpy as np
-
+def _oracle_sample(args):
+    """One oracle process: the workload's structure at n neurons with its own
+    seed, run for `seconds`; -> (events, steps, seconds)."""
+    name, n, seed, seconds = args
     import oracle
     import synth
-    n = max(wl_full.n_neurons // 100, 1000)
-    wl = wl_full.scaled(n)
+    wl = synth.get_workload(name).scaled(n)
+    wl = wl.replace(seed=wl.seed + seed)
     gen = synth.Generator(wl)
     sim = oracle.Sim(oracle.params_from_workload(wl), gen.edges(), gen.part_map(),
                      synth.initial_u(wl))
     sim.run(20)  # warm
-    steps, t0 = 0, time.perf_counter()
-    events = 0
-    while time.perf_counter() - t0 < seconds_budget:
+    steps, events, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
         c, st = sim.run(50)
         steps += 50
         events += int(st[:, oracle.LOCAL_EVENTS].sum() + st[:, oracle.REMOTE_EVENTS].sum())
-    dt = time.perf_counter() - t0
-    return dict(value=events / dt, unit="synaptic events/s", cores=1, kind="oracle",
-                sample=f"{wl_full.name} structure at {n:,} neurons (1/100), K={wl.k_in}, "
-                       f"{steps} steps, {events:,} events, {dt:.1f} s single-threaded; "
-                       f"ms/step {1e3 * dt / steps:.2f}")
+    return events, steps, time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl_full, seconds_budget=10.0):
+    """The oracle (plain C, FP64 + binary32 trajectories, one thread per
+    process) on the same structure at 1/100 of the neurons (same in-degree,
+    partitions, rate): one process alone, then one process per available
+    core at once, each on its own seeded network; value = the all-core rate."""
+    import multiprocessing as mp
+    n = max(wl_full.n_neurons // 100, 1000)
+    name = wl_full.name
+    ev1, st1, dt1 = _oracle_sample((name, n, 0, seconds_budget))
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_sample, [(name, n, i, seconds_budget) for i in range(cores)])
+    ev = sum(r[0] for r in res)
+    steps = sum(r[1] for r in res)
+    dt = max(r[2] for r in res)
+    return dict(value=ev / dt, unit="synaptic events/s", cores=cores, kind="oracle",
+                cpu_model=cpu_model(), single_thread_value=ev1 / dt1,
+                sample=f"{name} structure at {n:,} neurons (1/100), K={wl_full.k_in}: "
+                       f"{cores} processes of one thread each, {steps} steps and {ev:,} events "
+                       f"in {dt:.1f} s; one process alone {ev1 / dt1:.3g} events/s "
+                       f"({1e3 * dt1 / st1:.2f} ms/step)")
 
 
 def calibrate_copy(nbytes: int, reps: int = 5):
@@ -146,7 +174,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="paper_share")
     ap.add_argument("--mode", choices=["two_level", "flat"], default="two_level")
-    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--graph", type=int, choices=[0, 1, 2], default=2,
+                    help="0 eager launches, 1 16-step HIP graphs, 2 one HIP graph of all "
+                         "timed steps (default)")
+    ap.add_argument("--per-partition", action="store_true",
+                    help="also time the same steps with the update launched once per "
+                         "partition (materialised partitions)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shapes by timing (autotune.tune) before the timed "
+                         "region")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-steps", type=int, default=100)
     ap.add_argument("--neurons", type=int, default=0,
@@ -187,7 +223,12 @@ def main():
     t0 = time.time()
     host = HostNetwork(wl, verbose=True)
     log(f"host setup {time.time() - t0:.1f}s, {host.host_bytes() / 1e9:.1f} GB")
-    total_steps = args.warmup + args.steps + args.phase_steps
+    # steps the log must hold back to the timed region: warm-up, the run that
+    # captures the whole-run graph, the timed steps, the per-kernel timing
+    # and the per-partition comparison
+    reps = 2 if args.graph == 2 else 1
+    total_steps = (args.warmup + reps * args.steps + args.phase_steps
+                   + (args.warmup + reps * args.steps if args.per_partition else 0))
     t1 = time.time()
     sim = Simulation(wl, host=host, log_steps=total_steps,
                      log_cap=int(wl.n_neurons * max(wl.rate_on_hz, 50.0) * wl.dt_ms * 1e-3 * 4
@@ -197,22 +238,36 @@ def main():
     sim.host = None
     log(f"device upload {time.time() - t1:.1f}s")
 
-    use_graph = not args.no_graph
-    sim.run(args.warmup, mode, use_graph)
-    sim.sync()
-    torch.cuda.synchronize()
-    s = sim.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    e0.record(s)
-    sim.run(args.steps, mode, use_graph)
-    e1.record(s)
-    s.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1)
-    sim.sync()
-    cnt = sim.read_counters(args.warmup, args.steps).astype(np.float64)
+    use_graph = args.graph
+    tuned = None
+    if args.autotune:
+        from paper_2205_07125_amd import autotune
+        tuned = autotune.tune(sim, mode, log=log)
+        log(f"autotune: {tuned['tuning']} ({'cached' if tuned['cached'] else 'timed'})")
+    def timed(run):
+        """Warm-up, then (for a whole-run graph) one run that captures the
+        graph of args.steps steps, then the timed replay of those steps:
+        -> (first timed step, HIP-event ms, wall s)."""
+        run(args.warmup, 1 if use_graph else 0)
+        if use_graph == 2:
+            run(args.steps, 2)
+        sim.sync()
+        torch.cuda.synchronize()
+        t_first = sim.t
+        s = sim.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(s)
+        run(args.steps, use_graph)
+        e1.record(s)
+        s.synchronize()
+        torch.cuda.synchronize()
+        wall_s = time.perf_counter() - w0
+        sim.sync()
+        return t_first, e0.elapsed_time(e1), wall_s
+
+    t_first, ms, wall = timed(lambda n, g: sim.run(n, mode, g))
+    cnt = sim.read_counters(t_first, args.steps).astype(np.float64)
     sec = ms / 1e3
     spikes = cnt[:, 0].sum()
     events = cnt[:, 1].sum() + cnt[:, 2].sum()
@@ -238,7 +293,7 @@ def main():
                  "max_entries_per_partition": int(per_part.max()),
                  "max_msgs_per_node": int(per_node.max()),
                  "of": "the last step of the per-kernel timing"}
-    pc = sim.read_counters(args.warmup + args.steps, args.phase_steps).astype(np.float64)
+    pc = sim.read_counters(sim.t - args.phase_steps, args.phase_steps).astype(np.float64)
     log("kernels (ms): " + "  ".join(f"{k} {v:.4f}" for k, v in kt.items() if v > 0))
     N = wl.n_neurons
     bw = 2 if wl.weight_type == "bf16" else 4
@@ -332,7 +387,27 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": b, "avg_launch_ms": t_ms,
                      "timing": "HIP events on the launch stream, %d eager steps" % args.phase_steps},
+        "graph": {0: "eager launches", 1: "16-step HIP graphs",
+                  2: "one HIP graph of all %d timed steps" % args.steps}[use_graph],
     }
+    if args.per_partition:
+        # the same steps with the update launched once per partition
+        tp, ms_p, _ = timed(lambda n, g: sim.run_partitioned(n, mode, g))
+        cp = sim.read_counters(tp, args.steps).astype(np.float64)
+        ev_p = cp[:, 1].sum() + cp[:, 2].sum()
+        out["layouts"] = {
+            "one_launch": {"ms_per_step": ms / args.steps, "events_per_s": events / sec,
+                           "update_launches_per_step": 1},
+            "per_partition": {"ms_per_step": ms_p / args.steps,
+                              "events_per_s": ev_p / (ms_p / 1e3),
+                              "update_launches_per_step": int(
+                                  (np.diff(synth.partition_starts(wl)) > 0).sum()
+                                  if synth.partition_starts(wl) is not None else 1)}}
+        log(f"per-partition update launches: {ms_p / args.steps * 1e3:.1f} us/step "
+            f"against {ms / args.steps * 1e3:.1f} us/step in one launch")
+    if tuned is not None:
+        out["tuning"] = {"choice": tuned["tuning"], "cached": tuned["cached"],
+                         "candidates": len(tuned.get("timings", []))}
     sim.close()
     del sim
     torch.cuda.empty_cache()

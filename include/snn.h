@@ -112,8 +112,9 @@ enum {
 
 /* Kernel kinds of a step, in launch order (snn_kernel_times).  In a whole
    two-level step as snn_run launches it, UPDATE also routes (up to 512 nodes
-   of at most 8 partitions), and RECV_STAGE also expands the masks and bins
-   both the own-partition and the received synapses (no DELIVER launch). */
+   of at most 8 partitions), RECV_STAGE also expands the masks and, beside
+   the staging, bins the own-partition synapses, and DELIVER bins the
+   received ones. */
 enum {
   SNN_KERNEL_UPDATE = 0,           /* neuron update, threshold, compaction */
   SNN_KERNEL_ROUTE_TWO_LEVEL = 1,  /* per-node messages with partition masks */
@@ -253,11 +254,42 @@ snn_status snn_step_route(snn_handle h, int mode);
    slot (t + d) mod D when the bin is full).  Order: must follow snn_route. */
 snn_status snn_deliver(snn_handle h);
 
-/* n_steps full steps (snn_step_route(mode), snn_deliver).  use_graph != 0 captures
-   HIP graphs of 16 steps and of one step once per mode and replays them
-   (16-step replays first, then single steps for the remainder; all
-   step-dependent values live in device memory).  Order: as snn_step. */
+/* n_steps full steps (snn_step_route(mode), snn_deliver).  use_graph = 0
+   launches them directly; 1 captures HIP graphs of 16 steps and of one step
+   once per mode and replays them (16-step replays first, then single steps
+   for the remainder); 2 captures all n_steps steps as one graph (kept for
+   the next call with the same n_steps and mode) and launches it once.  All
+   step-dependent values live in device memory, so a graph replays unchanged.
+   Order: as snn_step. */
 snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph);
+
+/* snn_run with the neuron update (and the two-level routing done inside it)
+   launched once per partition, over that partition's neurons only, instead
+   of once over all of them: the layout of one launch per partition that a
+   batched kernel replaces (the uneven partitions of Sec. V's workload, each
+   of which would be one GPU's share).  Partitions must be contiguous ranges
+   of neuron ids: partition p holds [part_start[p], part_start[p+1]) (host
+   array of n_partitions + 1 entries, part_start[0] = 0,
+   part_start[n_partitions] = n_neurons; empty partitions are skipped).
+   Results are identical to snn_run's. */
+snn_status snn_run_partitioned(snn_handle h, uint32_t n_steps, int mode, int use_graph,
+                               const uint32_t* part_start);
+
+/* Launch-shape choices that leave every result unchanged; 0 in a field is
+   the library's default.  Picked per network shape by measurement (the
+   package's autotuner). */
+typedef struct {
+  uint32_t update_blocks;   /* blocks of a whole-step update launch: 0 = one per tile of
+                               neurons; fewer = persistent blocks that take tiles in turn */
+  uint32_t recv_split;      /* most receive-side blocks that share one destination node's
+                               messages (expansion and staging); 0 = as many as the
+                               256 receive-side blocks allow, 1 = one block per node */
+} snn_tuning;
+
+/* Sets / reads the handle's launch shapes.  Setting synchronises the stream
+   and drops the handle's captured graphs.  Order: between steps. */
+snn_status snn_set_tuning(snn_handle h, const snn_tuning* t);
+snn_status snn_get_tuning(snn_handle h, snn_tuning* t);
 
 /* Moves every pending binned synaptic event into the dense ring, so that the
    ring alone holds the input scheduled for the coming steps (for read-back

@@ -277,6 +277,12 @@ class Sim:
                         _p(out["ref64"]), _p(out["ring64"]))
         return out
 
+    def membrane64(self) -> np.ndarray:
+        """u of the FP64 trajectory (copy)."""
+        out = np.zeros(self.N, np.float64)
+        lib().orc_state(self.h, None, None, None, _p(out), None, None)
+        return out
+
     def accuracy(self) -> dict:
         out = np.zeros(5, np.float64)
         lib().orc_accuracy(self.h, _p(out))

@@ -34,7 +34,8 @@ SNN_NKERNEL = len(KERNEL_NAMES)
 
 EXPORTED = [
     "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route", "snn_step_route",
-    "snn_deliver", "snn_run", "snn_kernel_times", "snn_flush", "snn_sync", "snn_time",
+    "snn_deliver", "snn_run", "snn_run_partitioned", "snn_set_tuning", "snn_get_tuning",
+    "snn_kernel_times", "snn_flush", "snn_sync", "snn_time",
     "snn_bin_geometry",
     "snn_ring_events",
     "snn_read_spikes", "snn_read_routes",
@@ -64,6 +65,10 @@ class snn_network_dev(ctypes.Structure):
     _fields_ = [(n, vp) for n in (
         "row_ptr", "n_local", "delay_off", "tgt_delay", "weight", "vp_ptr", "vp_part", "vp_rec",
         "part_of_neuron", "bucket_off", "recv_off", "u", "ref", "ring")]
+
+
+class snn_tuning(ctypes.Structure):
+    _fields_ = [("update_blocks", u32), ("recv_split", u32)]
 
 
 class snn_setup_spec(ctypes.Structure):
@@ -110,6 +115,9 @@ def lib() -> ctypes.CDLL:
             "snn_step_route": (I, [vp, I]),
             "snn_deliver": (I, [vp]),
             "snn_run": (I, [vp, u32, I, I]),
+            "snn_run_partitioned": (I, [vp, u32, I, I, vp]),
+            "snn_set_tuning": (I, [vp, ctypes.POINTER(snn_tuning)]),
+            "snn_get_tuning": (I, [vp, ctypes.POINTER(snn_tuning)]),
             "snn_kernel_times": (I, [vp, u32, I, vp]),
             "snn_flush": (I, [vp]),
             "snn_sync": (I, [vp]),
@@ -178,8 +186,27 @@ def snn_deliver(h):
     check(lib().snn_deliver(h))
 
 
-def snn_run(h, n_steps: int, mode: int, use_graph: bool):
-    check(lib().snn_run(h, n_steps, mode, 1 if use_graph else 0))
+def snn_run(h, n_steps: int, mode: int, use_graph):
+    """use_graph: False / 0 eager, True / 1 16-step graphs, 2 one graph of all steps."""
+    check(lib().snn_run(h, n_steps, mode, int(use_graph)))
+
+
+def snn_run_partitioned(h, n_steps: int, mode: int, use_graph, part_start):
+    import numpy as np
+    starts = np.ascontiguousarray(part_start, np.uint32)
+    check(lib().snn_run_partitioned(h, n_steps, mode, int(use_graph),
+                                    starts.ctypes.data_as(ctypes.c_void_p)))
+
+
+def snn_set_tuning(h, update_blocks: int = 0, recv_split: int = 0):
+    t = snn_tuning(update_blocks=update_blocks, recv_split=recv_split)
+    check(lib().snn_set_tuning(h, ctypes.byref(t)))
+
+
+def snn_get_tuning(h) -> dict:
+    t = snn_tuning()
+    check(lib().snn_get_tuning(h, ctypes.byref(t)))
+    return {"update_blocks": t.update_blocks, "recv_split": t.recv_split}
 
 
 def snn_kernel_times(h, n_steps: int, mode: int):

@@ -15,16 +15,7 @@ enum : uint32_t {
   ERR_RECV = 2u,     // an expanded receive list overflowed
   ERR_FLAT = 4u,     // a flat receive list overflowed
   ERR_LOG = 8u,      // a step had more spikes than the spike log holds
-  ERR_ROUTE = 16u,   // a receive entry names a partition its source does not reach
-  ERR_TIMEOUT = 32u  // a device-scope wait gave up (a block it waited for never arrived)
-};
-
-// Words of the in-launch synchronisation area (KParams::sync), each on a
-// 64-byte line of its own; every launch that uses one leaves it at zero.
-enum : uint32_t {
-  SYNC_STAGED = 0,    // staging blocks of the combined receive launch that are done
-  SYNC_RETIRED = 16,  // delivery blocks of that launch that are done
-  SYNC_WORDS = 64
+  ERR_ROUTE = 16u    // a receive entry names a partition its source does not reach
 };
 
 // Device-resident step state.  Every step-dependent value lives here so that
@@ -47,7 +38,8 @@ struct DevState {
   uint32_t cur_par;    // parity (t mod 2) of the step in flight: its bucket counter set
   uint32_t srow;       // t mod (log_steps + 1): counter row of step t
   uint32_t cur_srow;   // counter row of the step in flight
-  uint32_t pad;
+  uint32_t part_base;  // fired ids of the step so far, while its update runs as one launch
+                       // per partition (0 between steps)
 };
 
 // Stream ids of the counter-based generator.
@@ -135,6 +127,14 @@ struct KParams {
   uint64_t log_cap;
   uint64_t bin_cap;
   uint64_t stage_cap;
+  uint32_t recv_split;   // most receive-side blocks sharing one node's bucket (0 = as many
+                         // as the blocks allow); tunable per shape
+  // what one update launch covers: tiles [tile0, tile_end), neurons [lo, hi);
+  // step_ends: the step's last update launch (advances the step state).  A
+  // whole-step launch has tile0 = 0, tile_end = n_tiles, lo = 0, hi = N.
+  uint32_t tile0, tile_end, lo, hi, step_ends;
+  uint32_t update_blocks;   // grid of a whole-step update launch (0: one block per tile;
+                            // fewer: persistent blocks taking tiles in ticket order)
   float wq_scale;      // 2^F: weight -> fixed point
   double wq_inv;       // 2^-F
   // network (caller-owned device memory)
@@ -157,6 +157,7 @@ struct KParams {
   // workspace
   DevState* st;
   uint64_t* lookback;   // [n_tiles] decoupled look-back words
+  uint32_t* tickets;    // [2] tiles handed out by a persistent update, by step parity
   uint32_t* fired;      // [N] ascending fired ids of the step in flight
   uint32_t* bucket_cnt; // [2][n_nodes * CNT_STRIDE] two sets, by step parity
   uint64_t* bucket;     // [2 * bucket_total] messages: source | pair index of the
@@ -171,7 +172,6 @@ struct KParams {
   uint32_t* dirty;      // [D * n_tiles] ring tile holds events
   Event* bins;          // [D][n_tiles][bin_cap]
   uint64_t* stats;      // [log_steps + 1][STAT_LANES][STAT_LANE_WORDS]
-  uint32_t* sync;       // [SYNC_WORDS] in-launch arrival counters
   uint64_t* log_off;    // [log_steps] first log position of each step
   uint32_t* log;        // [log_cap] spike-log ring
 };

@@ -17,11 +17,16 @@
 //                  written as runs into per-(slot, tile, delay, block) bins
 //   k_route_flat   flat routing: one receive entry per destination partition
 //
-// A whole step is two launches: k_update<true> (update, compaction and the
-// tile's own two-level routing, which overlaps the look-back) and
-// k_recv_deliver (expansion and staging, and beside them the own-partition
-// delivery, whose blocks then wait for the staging blocks and bin the staged
-// remote synapses).  The step-by-step entry points use one kernel per job
+// A whole step is three launches: k_update<true> (update, compaction and the
+// tile's own two-level routing, which overlaps the look-back), k_recv_local
+// (expansion and staging beside the own-partition delivery: two independent
+// jobs in one launch) and k_deliver_remote (the staged remote synapses,
+// appended after the counts the local part published).  Each launch boundary
+// is also where the writes of one job become visible to the next: waiting
+// inside a launch for other blocks' writes would take a device-scope release
+// and acquire per block, which on a chip of several L2 caches (one per XCD)
+// writes back or invalidates a whole L2 each time and costs far more than a
+// launch boundary.  The step-by-step entry points use one kernel per job
 // instead (k_update<false>, k_route_two_level, k_expand, k_recv_stage,
 // k_deliver).
 //
@@ -571,13 +576,22 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   const uint64_t log_head =
       (static_cast<uint64_t>(rd32(reinterpret_cast<const uint32_t*>(&st->log_head) + 1)) << 32) |
       rd32(reinterpret_cast<const uint32_t*>(&st->log_head));
+  // fired ids of the step's earlier launches (one launch per partition)
+  const uint32_t base = rd32(&st->part_base);
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t tile = blockIdx.x;
+  __shared__ uint32_t s_tile;
+  // The launch covers tiles [tile0, tile_end) and neurons [lo, hi).  Block b
+  // takes tile tile0 + b; a grid smaller than that (persistent) takes the
+  // rest in ticket order, so the look-back only ever waits for tiles already
+  // taken by running blocks.
+  uint32_t tile = p.tile0 + blockIdx.x;
+  while (true) {
   const uint32_t blk0 = tile * TILE;
 
   // Per-step counters of the routing: the bucket counters of step t + 1 (this
   // step's routing counts into the other set) and the receive-list counters.
-  if (blockIdx.x == 0) {
+  if (tile == 0) {
+    if (tid == 0) p.tickets[(t32 + 1u) & 1u] = 0u;
     uint32_t* next_bcnt = bucket_counts(p, (t32 + 1u) & 1u);
     for (uint32_t i = tid; i < p.n_nodes; i += UPDATE_THREADS) next_bcnt[i * CNT_STRIDE] = 0;
     for (uint32_t i = tid; i < p.P; i += UPDATE_THREADS) {
@@ -598,7 +612,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   // State of quad q of the thread's neurons (4 consecutive neurons).  The
   // branch on a whole tile in range is uniform, so loads carry no divergent
   // merge; past N a lane reads neuron N - 1 (never stored back, never fires).
-  const bool tile_full = blk0 + TILE <= p.N;
+  const bool tile_full = blk0 >= p.lo && blk0 + TILE <= p.hi;
   auto load_quad = [&](int q, float4& u4, uint32_t& r4) {
     const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
     if (tile_full) {
@@ -609,7 +623,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
       uint32_t r = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint32_t ik = min(i0 + k, p.N - 1);
+        const uint32_t ik = min(max(i0 + k, p.lo), p.hi - 1);
         v[k] = p.u[ik];
         r |= static_cast<uint32_t>(p.ref[ik]) << (8 * k);
       }
@@ -681,7 +695,8 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   // slot; a flagged tile reads (and clears) it with the neuron state
   float* ring_slot = p.ring + static_cast<uint64_t>(slot) * p.ring_stride;
   const bool dirty = s_dirty != 0;
-  if (dirty && tid == 0) p.dirty[slot * p.n_tiles + tile] = 0u;
+  // (cleared by the launch that holds the tile's last neuron)
+  if (dirty && tid == 0 && min(blk0 + TILE, p.N) <= p.hi) p.dirty[slot * p.n_tiles + tile] = 0u;
 
   uint32_t thr_raster = 0;
   if (p.forced) thr_raster = phase < p.raster_on ? p.raster_on_thr : p.raster_off_thr;
@@ -716,7 +731,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (dirty) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (i0 + k < p.N) {
+        if (i0 + k >= p.lo && i0 + k < p.hi) {
           syn[k] = __fadd_rn(syn[k], ring_slot[i0 + k]);
           ring_slot[i0 + k] = 0.f;
         }
@@ -746,7 +761,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
       const float un = integrating ? u_int : uu[k];
       const uint32_t rn = integrating ? 0u : rf[k] - 1u;
       bool s = p.forced ? (r2[k] < thr_raster) : (integrating && un >= p.theta);
-      s = s && (i0 + k < p.N);
+      s = s && (i0 + k >= p.lo && i0 + k < p.hi);
       uu[k] = s ? p.u_reset : un;
       rf[k] = s ? p.n_ref : rn;
       fire_bits |= static_cast<uint32_t>(s) << (4 * q + k);
@@ -761,7 +776,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (i0 + k < p.N) {
+        if (i0 + k >= p.lo && i0 + k < p.hi) {
           p.u[i0 + k] = uu[k];
           p.ref[i0 + k] = static_cast<uint8_t>(rf[k]);
         }
@@ -781,7 +796,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     const uint32_t incl = wave_incl_scan(c);
     if (lane < NQ * NW) s_qoff[lane / NW][lane % NW] = incl - c;
     const uint32_t block_tot = __shfl(incl, 63, 64);
-    lookback_publish(p.lookback, blockIdx.x, block_tot, tag);
+    lookback_publish(p.lookback, tile - p.tile0, block_tot, tag);
     if (lane == 0) s_btot = block_tot;
   }
   __syncthreads();
@@ -822,13 +837,13 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   }
 
   if (wave == 0) {
-    const uint32_t excl = lookback_resolve(p.lookback, blockIdx.x, btot, tag);
+    const uint32_t excl = lookback_resolve(p.lookback, tile - p.tile0, btot, tag);
     if (lane == 0) s_excl = excl;
   }
   __syncthreads();
   const uint32_t excl = s_excl;
   for_each_fired([&](uint32_t r, uint32_t id) {
-    const uint32_t pos = excl + r;
+    const uint32_t pos = base + excl + r;
     p.fired[pos] = id;
     // a step with more spikes than the log holds is flagged by the last
     // block (ERR_LOG); its ids past the capacity are not logged
@@ -839,29 +854,44 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     }
   });
 
-  // The last block holds the step total once its look-back is done; every
-  // other block has read t and log_total by then (they published first).
-  if (blockIdx.x == gridDim.x - 1 && tid == 0) {
+  // The launch's last tile holds the launch total once its look-back is done;
+  // every other block has read the state by then (they published first).
+  // It hands the next launch its look-back tag, and the step's last launch
+  // advances the step state.
+  if (tile == p.tile_end - 1 && tid == 0) {
     DevState* w = p.st;
-    const uint32_t n = s_excl + s_btot;
-    const uint64_t log_base = w->log_total;
-    w->n_fired = n;
-    p.stats[static_cast<uint64_t>(srow) * STAT_ROW_WORDS + SNN_STAT_SPIKES] = n;
-    p.log_off[row] = log_base;
-    if (p.log_cap && n > p.log_cap) atomicOr(&w->error, ERR_LOG);
-    w->log_total = log_base + n;
-    if (p.log_cap) w->log_head = (w->log_head + n) % p.log_cap;
-    w->cur_slot = slot;
-    w->cur_row = row;
-    w->cur_par = t32 & 1u;
-    w->cur_srow = srow;
-    w->srow = srow + 1 == p.log_steps + 1 ? 0u : srow + 1;
-    w->slot = slot + 1 == p.D ? 0u : slot + 1;
-    w->row = row + 1 == p.log_steps ? 0u : row + 1;
-    w->phase = phase + 1 == p.raster_period ? 0u : phase + 1;
+    const uint32_t n = base + s_excl + s_btot;
     w->tag = tag == 0x3FFFFFFFu ? 0u : tag;          // next tag - 1 = this tag
-    w->t = w->t + 1;
+    if (!p.step_ends) {
+      w->part_base = n;
+    } else {
+      const uint64_t log_base = w->log_total;
+      w->part_base = 0;
+      w->n_fired = n;
+      p.stats[static_cast<uint64_t>(srow) * STAT_ROW_WORDS + SNN_STAT_SPIKES] = n;
+      p.log_off[row] = log_base;
+      if (p.log_cap && n > p.log_cap) atomicOr(&w->error, ERR_LOG);
+      w->log_total = log_base + n;
+      if (p.log_cap) w->log_head = (w->log_head + n) % p.log_cap;
+      w->cur_slot = slot;
+      w->cur_row = row;
+      w->cur_par = t32 & 1u;
+      w->cur_srow = srow;
+      w->srow = srow + 1 == p.log_steps + 1 ? 0u : srow + 1;
+      w->slot = slot + 1 == p.D ? 0u : slot + 1;
+      w->row = row + 1 == p.log_steps ? 0u : row + 1;
+      w->phase = phase + 1 == p.raster_period ? 0u : phase + 1;
+      w->t = w->t + 1;
+    }
   }
+  if (gridDim.x >= p.tile_end - p.tile0) break;    // one tile per block
+  __syncthreads();
+  if (tid == 0) s_tile = p.tile0 + gridDim.x + atomicAdd(p.tickets + (t32 & 1u), 1u);
+  __syncthreads();
+  tile = s_tile;
+  if (tile >= p.tile_end) break;
+  __syncthreads();
+  }   // tiles
 }
 
 static_assert(route_lds_bytes(ROUTE_THREADS, ROUTE_STAGE, ROUTE_MAX_NODES_LDS, true) <= 150u * 1024u,
@@ -1114,21 +1144,32 @@ __device__ __forceinline__ uint32_t lowest_bit(uint64_t m) {
 }
 
 // Mask expansion at the destination node (the bridge's forwarding of
-// Sec. IV-B), with or without the staging of the entries (STAGE): block b
-// takes the nodes b, b + nblocks, ...  A node's messages are loaded
-// EXPAND_PER_THREAD consecutive ones per thread; every set bit g of a mask is
-// one receive entry (source, pair index of partition G*n + g: the node's
-// destinations are consecutive in the source's list, so the pair indices
-// follow the message's first one).  The entries go into the partition's
-// receive list (positions from LDS counters: the block owns the node's
-// partitions).  With STAGE they also go into an LDS buffer, at positions from
-// a block scan of the masks' bit counts, and the buffer is staged per delay
-// (stage_batch) when it is full and at the end, without reading the receive
-// lists back; messages whose entries do not fit the buffer's free space are
-// taken in the next round.
+// Sec. IV-B), with or without the staging of the entries (STAGE).  A node's
+// messages are split among S = split_of(n_nodes, nblocks) consecutive blocks
+// (S = 1 when there are at least as many nodes as blocks: block b then takes
+// the nodes b, b + nblocks, ...), so that a shape with few nodes still puts
+// every block to work.  A block's messages are loaded EXPAND_PER_THREAD
+// consecutive ones per thread; every set bit g of a mask is one receive entry
+// (source, pair index of partition G*n + g: the node's destinations are
+// consecutive in the source's list, so the pair indices follow the message's
+// first one).  Receive-list positions: with S = 1 the block owns the node's
+// partitions and counts in LDS; with S > 1 each round's entries are first
+// buffered with their partition and rank, then one global atomic per
+// partition reserves the round's run in that list.  With STAGE the entries
+// also go into an LDS buffer, at positions from a block scan of the masks'
+// bit counts, and the buffer is staged per delay (stage_batch) when it is
+// full and at the end, without reading the receive lists back; messages
+// whose entries do not fit the buffer's free space are taken in the next
+// round.
 // Block b of nblocks; with STAGE, dyn holds EXPAND_STAGE_LDS bytes of LDS.
 // WIDE: groups of more than NARROW_G partitions (masks held in 64 bits,
 // otherwise in 32).
+__device__ __forceinline__ uint32_t split_of(const KParams& p, uint32_t nblocks) {
+  if (p.n_nodes >= nblocks) return 1u;
+  const uint32_t s = nblocks / p.n_nodes;
+  return p.recv_split ? min(s, p.recv_split) : s;
+}
+
 template <bool BF16, bool STAGE, bool WIDE>
 __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblocks, uint64_t* dyn) {
   using MaskT = std::conditional_t<WIDE, uint64_t, uint32_t>;
@@ -1139,11 +1180,15 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
   uint64_t* s_ent = dyn;                                                   // [EXPAND_BUF]
   uint64_t* s_seg = s_ent + EXPAND_BUF;                                    // [RECV_BATCH]
   uint32_t* s_epre = reinterpret_cast<uint32_t*>(s_seg + RECV_BATCH);      // [RECV_BATCH]
+  // shared nodes: partition | rank << 8 of each buffered entry of the round,
+  // in s_epre (free until the buffer is staged)
+  uint32_t* s_gr = s_epre;
+  static_assert(RECV_BATCH >= EXPAND_BUF, "the round's ranks fit the staging scratch");
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint64_t s_red[2 * NW];
   __shared__ uint32_t l_pos[SNN_MAX_DELAY];
   __shared__ uint32_t l_cnt[NG], l_run[NG];
-  __shared__ uint64_t l_off[NG + 1];
+  __shared__ uint64_t l_off[NG + 1], l_base[NG];
   __shared__ uint32_t s_taken, s_added;
   const uint32_t tid = threadIdx.x;
   const uint32_t md = p.D - 1;
@@ -1166,17 +1211,25 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
       }
     }
   };
+  // S blocks per node: block b takes part b mod S of node b / S, then, with
+  // S = 1, every nblocks-th node
+  const uint32_t S = STAGE ? split_of(p, nblocks) : 1u;
+  const bool shared = S > 1;
+  const uint32_t n_step = shared ? p.n_nodes : nblocks;   // shared: one node per block
   uint32_t n_buf = 0;   // entries in the buffer (uniform)
-  for (uint32_t n = b; n < p.n_nodes; n += nblocks) {
+  for (uint32_t n = b / S; n < p.n_nodes; n += n_step) {
     const uint64_t off = p.bucket_off[n];
-    const uint32_t cnt = static_cast<uint32_t>(
+    const uint32_t cnt_n = static_cast<uint32_t>(
         min(static_cast<uint64_t>(bcnt[n * CNT_STRIDE]), p.bucket_off[n + 1] - off));
+    const uint32_t part = b % S;
+    const uint32_t m_lo = static_cast<uint32_t>(static_cast<uint64_t>(cnt_n) * part / S);
+    const uint32_t cnt = static_cast<uint32_t>(static_cast<uint64_t>(cnt_n) * (part + 1) / S);
     const uint32_t gn = min(p.G, p.P - p.G * n);             // partitions of this node
     const MaskT valid = gn == 8 * sizeof(MaskT) ? ~MaskT(0) : (MaskT(1) << gn) - 1;
     __syncthreads();   // the previous node is done with l_run, l_off
     if (tid < NG) l_run[tid] = 0;
     if (tid <= gn) l_off[tid] = p.recv_off[p.G * n + tid];
-    for (uint32_t m0 = 0; m0 < cnt;) {
+    for (uint32_t m0 = m_lo; m0 < cnt;) {
       uint64_t w0[EU], w1[EU];
       MaskT mask[EU];
       uint32_t mine = 0;
@@ -1215,9 +1268,13 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
             const uint64_t e = s | ((pair + k) << ENTRY_SRC_BITS);
             if constexpr (STAGE) s_ent[n_buf + at + k] = e;
             const uint32_t rk = atomicAdd(&l_cnt[g], 1u);
-            const uint64_t pos = l_off[g] + l_run[g] + rk;
-            if (pos < l_off[g + 1]) p.recv[pos] = e;
-            else atomicOr(&p.st->error, ERR_RECV);
+            if (shared) {
+              s_gr[n_buf + at + k] = g | (rk << 8);
+            } else {
+              const uint64_t pos = l_off[g] + l_run[g] + rk;
+              if (pos < l_off[g + 1]) p.recv[pos] = e;
+              else atomicOr(&p.st->error, ERR_RECV);
+            }
             ++k;
           }
           ++taken;
@@ -1232,17 +1289,33 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
       __syncthreads();
       const uint32_t round_taken = s_taken, round_added = s_added;
       const uint32_t loaded = min(cnt - m0, EU * RECV_THREADS);
-      if (tid < NG) l_run[tid] += l_cnt[tid];
+      if (shared) {
+        // reserve the round's run in each partition's list, then write the
+        // buffered entries there
+        if (tid < gn && l_cnt[tid])
+          l_base[tid] = atomicAdd(p.recv_cnt + (p.G * n + tid) * CNT_STRIDE, l_cnt[tid]);
+        __syncthreads();
+        for (uint32_t i = tid; i < round_added; i += RECV_THREADS) {
+          const uint32_t gr = s_gr[n_buf + i];
+          const uint32_t g = gr & 0xFFu;
+          const uint64_t pos = l_off[g] + l_base[g] + (gr >> 8);
+          if (pos < l_off[g + 1]) p.recv[pos] = s_ent[n_buf + i];
+          else atomicOr(&p.st->error, ERR_RECV);
+        }
+      } else if (tid < NG) {
+        l_run[tid] += l_cnt[tid];
+      }
       entries += tid == 0 ? round_added : 0u;
       if constexpr (STAGE) n_buf += round_added;
       m0 += round_taken;
       if (round_taken < loaded) {   // the buffer is full: stage it
+        __syncthreads();
         stage_buffer(n_buf);
         n_buf = 0;
       }
       __syncthreads();
     }
-    if (tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
+    if (!shared && tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
   }
   stage_buffer(n_buf);
   if (STAGE && tid < md)
@@ -1279,60 +1352,13 @@ __global__ __launch_bounds__(RECV_THREADS) void k_expand(KParams p) {
 // are placed in tile order in LDS (8 bytes each), and consecutive threads
 // then write consecutive positions of one sub-bin.
 // PART: DELIVER_ALL takes the queues after the sources (one kernel per row,
-// the queues complete at launch); DELIVER_SPLIT waits between the two for
-// every staging block of the same launch to have published its queues
-// (wait_staged), so the local part overlaps the staging and the tile counts
-// stay in LDS across both parts.
+// the queues complete at launch); DELIVER_LOCAL takes the sources only (beside
+// the receive side, which is still filling the queues) and DELIVER_REMOTE the
+// queues only, appended after the counts DELIVER_LOCAL published.
 // dyn holds deliver_lds_bytes(n_tiles) bytes.
-enum DeliverPart { DELIVER_ALL, DELIVER_SPLIT };
+enum DeliverPart { DELIVER_ALL, DELIVER_LOCAL, DELIVER_REMOTE };
 constexpr uint32_t DELIVER_ROUND = GATHER_UNROLL * DELIVER_THREADS;
 static_assert(DELIVER_ROUND <= 65536, "window positions fit 16 bits");
-
-// Polls of a device-scope wait before it gives up with ERR_TIMEOUT (every
-// wait in these kernels ends; each poll sleeps about 128 cycles).
-constexpr uint32_t SPIN_LIMIT = 1u << 22;
-
-// Called by every thread of a staging block when its queues and their counts
-// are written: makes them visible at device scope, then counts the block in.
-__device__ void signal_staged(const KParams& p) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_fetch_add(p.sync + SYNC_STAGED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Waits until all STAGE_BLOCKS staging blocks of this launch are counted in,
-// then makes their writes visible to the block.  Every thread calls it.
-__device__ void wait_staged(const KParams& p) {
-  if (threadIdx.x == 0) {
-    uint32_t spins = 0;
-    while (__hip_atomic_load(p.sync + SYNC_STAGED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-           STAGE_BLOCKS) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins == SPIN_LIMIT) {
-        atomicOr(&p.st->error, ERR_TIMEOUT);
-        break;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-}
-
-// Called by every thread of a delivery block of the combined launch when it
-// is done; the last of the n_deliver blocks resets the launch's counters for
-// the next launch (stream order makes the reset visible to it).
-__device__ void retire_deliver(const KParams& p, uint32_t n_deliver) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t old =
-        __hip_atomic_fetch_add(p.sync + SYNC_RETIRED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == n_deliver - 1) {
-      __hip_atomic_store(p.sync + SYNC_STAGED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(p.sync + SYNC_RETIRED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
 
 template <DeliverPart PART, bool BF16>
 __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t* dyn) {
@@ -1355,8 +1381,10 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
   if (slot >= p.D) slot -= p.D;
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t D = p.D;
+  constexpr bool LOCAL = PART != DELIVER_REMOTE;
+  constexpr bool REMOTE = PART != DELIVER_LOCAL;
   for (uint32_t i = tid; i < p.n_tiles; i += NT) {
-    l_run[i] = 0;
+    l_run[i] = LOCAL ? 0u : p.bin_cnt[subbin(p, slot, i, d, w)];
     l_cnt[i] = 0;
   }
   __syncthreads();
@@ -1445,7 +1473,7 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
 
   // the own-partition synapses of delay d of this block's fired sources
   // (w + m * DELIVER_BLOCKS), NT sources per batch
-  const uint32_t M = nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
+  const uint32_t M = LOCAL && nF > w ? (nF - w + DELIVER_BLOCKS - 1) / DELIVER_BLOCKS : 0;
   for (uint32_t m0 = 0; m0 < M; m0 += NT) {
     const uint32_t nsrc = min(M - m0, NT);
     uint32_t len = 0;
@@ -1459,9 +1487,8 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
     }
     take_runs(nsrc, len, std::false_type{});
   }
-  if constexpr (PART == DELIVER_SPLIT) wait_staged(p);
   // the staged remote synapses of delay d: queues w, w + DELIVER_BLOCKS, ...
-  {
+  if constexpr (REMOTE) {
     uint32_t len = 0;
     if (tid < QPB) {
       s_base[tid] = static_cast<uint64_t>(tid) * DELIVER_BLOCKS * p.stage_cap;
@@ -1474,7 +1501,7 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
   for (uint32_t i = tid; i < p.n_tiles; i += NT)
     p.bin_cnt[subbin(p, slot, i, d, w)] =
         static_cast<uint32_t>(min(static_cast<uint64_t>(l_run[i]), p.bin_cap));
-  add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
+  if constexpr (LOCAL) add_stat(stat_copy(p, row) + SNN_STAT_LOCAL_EVENTS, events, s_red);
 }
 
 template <bool BF16>
@@ -1483,28 +1510,32 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver(KParams p) {
   deliver_block<DELIVER_ALL, BF16>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
 }
 
-// The receive side and the delivery of a step in one launch: blocks
+// The staged remote synapses of (w, d) = (blockIdx.x, blockIdx.y + 1), after
+// k_recv_local delivered the local ones.
+template <bool BF16>
+__global__ __launch_bounds__(DELIVER_THREADS) void k_deliver_remote(KParams p) {
+  extern __shared__ uint64_t lds_u64[];
+  deliver_block<DELIVER_REMOTE, BF16>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
+}
+
+// Two independent jobs in one launch, so that they overlap: blocks
 // [0, STAGE_BLOCKS) expand and stage the two-level messages
-// (expand_stage_block) and count themselves in when their queues are
-// written; the rest (block STAGE_BLOCKS + i takes (w, d) =
-// (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)) deliver the fired sources'
-// local synapses meanwhile (they need only the fired list), wait for the
-// staging blocks, and bin the staged remote synapses.  Only higher-numbered
-// blocks wait, for lower-numbered ones, which are dispatched first; three
-// blocks of 8 waves per CU (6 waves per SIMD, at most 80 VGPRs) keep all of
-// them resident at once in any case.
+// (expand_stage_block), the rest deliver the fired sources' local synapses
+// (deliver_block, local part; block STAGE_BLOCKS + i takes (w, d) =
+// (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)).  The local part needs only
+// the fired list, not the receive side.  Three blocks of 8 waves per CU (6
+// waves per SIMD, at most 80 VGPRs), so that all blocks of both jobs are
+// resident at once.
 static_assert(RECV_THREADS == DELIVER_THREADS, "one block size for both jobs");
 template <bool BF16, bool WIDE>
 __global__ __launch_bounds__(RECV_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
-void k_recv_deliver(KParams p) {
+void k_recv_local(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   if (blockIdx.x < STAGE_BLOCKS) {
     expand_stage_block<BF16, true, WIDE>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
-    signal_staged(p);
   } else {
     const uint32_t i = blockIdx.x - STAGE_BLOCKS;
-    deliver_block<DELIVER_SPLIT, BF16>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
-    retire_deliver(p, gridDim.x - STAGE_BLOCKS);
+    deliver_block<DELIVER_LOCAL, BF16>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
   }
 }
 
@@ -1554,10 +1585,13 @@ bool fused_route_ok(const KParams& p) { return p.n_nodes <= FUSED_MAX_NODES && p
 
 hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks, bool route) {
   mark(marks, SNN_KERNEL_UPDATE, 0, s);
+  const uint32_t tiles = p.tile_end - p.tile0;
+  const uint32_t grid = p.update_blocks && p.tile0 == 0 && p.tile_end == p.n_tiles
+                            ? std::min(p.update_blocks, tiles) : tiles;
   if (route && fused_route_ok(p))
-    hipLaunchKernelGGL(k_update<true>, dim3(p.n_tiles), dim3(UPDATE_THREADS), 0, s, p);
+    hipLaunchKernelGGL(k_update<true>, dim3(grid), dim3(UPDATE_THREADS), 0, s, p);
   else
-    hipLaunchKernelGGL(k_update<false>, dim3(p.n_tiles), dim3(UPDATE_THREADS), 0, s, p);
+    hipLaunchKernelGGL(k_update<false>, dim3(grid), dim3(UPDATE_THREADS), 0, s, p);
   mark(marks, SNN_KERNEL_UPDATE, 1, s);
   return hipGetLastError();
 }
@@ -1605,7 +1639,7 @@ static size_t deliver_lds_bytes(uint32_t n_tiles) {
 constexpr size_t EXPAND_STAGE_LDS =
     EXPAND_BUF * sizeof(uint64_t) + RECV_BATCH * (sizeof(uint64_t) + sizeof(uint32_t));
 
-static size_t recv_deliver_lds_bytes(const KParams& p) {
+static size_t recv_local_lds_bytes(const KParams& p) {
   return std::max(EXPAND_STAGE_LDS, deliver_lds_bytes(p.n_tiles));
 }
 
@@ -1615,10 +1649,14 @@ static void launch_deliver_t(const KParams& p, int mode, hipStream_t s, hipEvent
   if (fused_expand && mode != SNN_ROUTE_FLAT) {
     mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
     void (*kern)(KParams) =
-        p.G > NARROW_G ? k_recv_deliver<BF16, true> : k_recv_deliver<BF16, false>;
+        p.G > NARROW_G ? k_recv_local<BF16, true> : k_recv_local<BF16, false>;
     hipLaunchKernelGGL(kern, dim3(STAGE_BLOCKS + DELIVER_BLOCKS * (p.D - 1)), dim3(RECV_THREADS),
-                       recv_deliver_lds_bytes(p), s, p);
+                       recv_local_lds_bytes(p), s, p);
     mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
+    mark(marks, SNN_KERNEL_DELIVER, 0, s);
+    hipLaunchKernelGGL(k_deliver_remote<BF16>, dim3(DELIVER_BLOCKS, p.D - 1),
+                       dim3(DELIVER_THREADS), deliver_lds_bytes(p.n_tiles), s, p);
+    mark(marks, SNN_KERNEL_DELIVER, 1, s);
     return;
   }
   mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
@@ -1653,14 +1691,16 @@ hipError_t prepare_kernels(KParams& p) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
   // the deliver kernels' per-tile counters must leave room for a round
-  const size_t dl = deliver_lds_bytes(p.n_tiles), rl = recv_deliver_lds_bytes(p);
+  const size_t dl = deliver_lds_bytes(p.n_tiles), rl = recv_local_lds_bytes(p);
   const std::pair<const void*, size_t> kernels[] = {
       {reinterpret_cast<const void*>(&k_deliver<false>), dl},
       {reinterpret_cast<const void*>(&k_deliver<true>), dl},
-      {reinterpret_cast<const void*>(&k_recv_deliver<false, false>), rl},
-      {reinterpret_cast<const void*>(&k_recv_deliver<true, false>), rl},
-      {reinterpret_cast<const void*>(&k_recv_deliver<false, true>), rl},
-      {reinterpret_cast<const void*>(&k_recv_deliver<true, true>), rl},
+      {reinterpret_cast<const void*>(&k_deliver_remote<false>), dl},
+      {reinterpret_cast<const void*>(&k_deliver_remote<true>), dl},
+      {reinterpret_cast<const void*>(&k_recv_local<false, false>), rl},
+      {reinterpret_cast<const void*>(&k_recv_local<true, false>), rl},
+      {reinterpret_cast<const void*>(&k_recv_local<false, true>), rl},
+      {reinterpret_cast<const void*>(&k_recv_local<true, true>), rl},
       {reinterpret_cast<const void*>(&k_route_two_level<false>), route_kernel_lds_bytes(p)},
       {reinterpret_cast<const void*>(&k_route_two_level<true>), route_kernel_lds_bytes(p)},
   };

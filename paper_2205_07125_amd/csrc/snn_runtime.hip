@@ -51,7 +51,7 @@ uint32_t n_nodes_of(const snn_params* p) {
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  uint64_t st, sync, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat,
+  uint64_t st, tickets, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat,
       stage_cnt, stage, bin_cnt, dirty, bins, stats, pois_lut, log_off, log, total;
 };
 
@@ -65,7 +65,7 @@ Layout layout(const snn_params* p) {
   };
   const uint64_t D = p->max_delay + 1, md = p->max_delay, tiles = tiles_of(p->n_neurons);
   L.st = take(sizeof(DevState));
-  L.sync = take(sizeof(uint32_t) * SYNC_WORDS);
+  L.tickets = take(sizeof(uint32_t) * 2);
   L.lookback = take(sizeof(uint64_t) * tiles);
   L.fired = take(sizeof(uint32_t) * uint64_t(p->n_neurons));
   L.bucket_cnt = take(2 * sizeof(uint32_t) * CNT_STRIDE * n_nodes_of(p));
@@ -91,8 +91,7 @@ Layout layout(const snn_params* p) {
 // Poisson inversion lookup (layout in snn_internal.h): for the draws of entry
 // b, [lo, hi], k = #{j : thr[j] <= r} is fixed when no threshold lies in
 // (lo, hi]; one threshold there is resolved by one comparison in the kernel.
-void build_pois_lut(const uint32_t* thr, std::vector<uint8_t>& lut) {
-  lut.assign(POIS_LUT_SIZE, 0);
+void build_pois_lut(const uint32_t* thr, uint8_t* lut) {
   for (uint32_t b = 0; b < POIS_LUT_SIZE; ++b) {
     const uint64_t lo = uint64_t(b) << POIS_LUT_SHIFT;
     const uint64_t hi = lo + (uint64_t(1) << POIS_LUT_SHIFT) - 1;
@@ -159,8 +158,13 @@ struct snn_ctx {
   bool expand_deferred;  // snn_step_route left the mask expansion to snn_deliver
   uint64_t t_host;    // steps enqueued
   uint64_t routed_t;  // step whose routes are in the buffers (+1), 0 = none
-  hipGraphExec_t graph[3][2];   // per route mode: one step, GRAPH_STEPS steps
-  std::vector<uint8_t> pois_lut;  // host copy of the lookup uploaded at create
+  // captured steps, per layout (0: one update launch per step, 1: one per
+  // partition) and route mode: one step, GRAPH_STEPS steps
+  hipGraphExec_t graph[2][3][2];
+  hipGraphExec_t whole;         // all steps of one snn_run call (use_graph = 2)
+  uint32_t whole_key[3];        // its steps, mode, layout
+  std::vector<uint32_t> part_start;   // partition starts of the per-partition layout
+  uint8_t pois_lut[POIS_LUT_SIZE];  // host copy of the lookup uploaded at create
 };
 
 // Steps captured in the long graph: replaying several steps per launch spreads
@@ -181,12 +185,9 @@ snn_status snn_workspace_size(const snn_params* params, size_t* bytes) {
   return SNN_OK;
 }
 
-snn_status snn_create(const snn_params* params, const snn_network_dev* net, void* workspace,
-                      size_t workspace_bytes, void* stream, snn_handle* out) {
-  if (!out) return fail(SNN_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  snn_status s = check_params(params);
-  if (s != SNN_OK) return s;
+namespace {
+
+snn_status check_net(const snn_network_dev* net) {
   if (!net) return fail(SNN_ERR_INVALID_ARG, "net is NULL");
   const void* req[] = {net->row_ptr, net->n_local, net->delay_off, net->tgt_delay, net->weight,
                        net->vp_ptr, net->vp_part, net->vp_rec, net->part_of_neuron,
@@ -199,14 +200,13 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   if ((reinterpret_cast<uintptr_t>(net->u) & 15) || (reinterpret_cast<uintptr_t>(net->ring) & 15) ||
       (reinterpret_cast<uintptr_t>(net->ref) & 3))
     return fail(SNN_ERR_INVALID_ARG, "u and ring must be 16-byte aligned, ref 4-byte aligned");
-  const Layout L = layout(params);
-  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
-    return fail(SNN_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
-  if (workspace_bytes < L.total)
-    return fail(SNN_ERR_INVALID_ARG, "workspace has %zu bytes, needs %llu", workspace_bytes,
-                (unsigned long long)L.total);
+  return SNN_OK;
+}
 
-  snn_ctx* c = new snn_ctx();
+// Fills c for params / net with its workspace at ws (layout L) and clears
+// the workspace's counters on the stream.
+snn_status init_ctx(snn_ctx* c, const snn_params* params, const snn_network_dev* net, char* ws,
+                    const Layout& L, void* stream) {
   c->prm = *params;
   c->net = *net;
   c->stream = static_cast<hipStream_t>(stream);
@@ -219,6 +219,11 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.D = params->max_delay + 1;
   k.n_nodes = n_nodes_of(params);
   k.n_tiles = tiles_of(params->n_neurons);
+  k.tile0 = 0;
+  k.tile_end = k.n_tiles;
+  k.lo = 0;
+  k.hi = k.N;
+  k.step_ends = 1;
   k.n_ref = params->n_ref;
   k.ring_stride = snn_ring_stride(params->n_neurons);
   k.alpha = params->alpha;
@@ -255,10 +260,9 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   k.u = net->u;
   k.ref = net->ref;
   k.ring = net->ring;
-  char* ws = static_cast<char*>(workspace);
   k.st = reinterpret_cast<DevState*>(ws + L.st);
-  k.sync = reinterpret_cast<uint32_t*>(ws + L.sync);
   k.lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  k.tickets = reinterpret_cast<uint32_t*>(ws + L.tickets);
   k.fired = reinterpret_cast<uint32_t*>(ws + L.fired);
   k.bucket_cnt = reinterpret_cast<uint32_t*>(ws + L.bucket_cnt);
   k.bucket = reinterpret_cast<uint64_t*>(ws + L.bucket);
@@ -282,36 +286,52 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
   hipError_t e = hipMemcpy(&tot[0], net->vp_ptr + params->n_neurons, 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess)
     e = hipMemcpy(&tot[1], net->row_ptr + params->n_neurons, 8, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) {
-    delete c;
+  if (e != hipSuccess)
     return fail(SNN_ERR_HIP, "create: reading vp_ptr[N], row_ptr[N]: %s", hipGetErrorString(e));
-  }
-  if (tot[0] < 0 || tot[1] < 0 || tot[1] >= (int64_t(1) << 40) || tot[0] >= (int64_t(1) << 32)) {
-    delete c;
+  if (tot[0] < 0 || tot[1] < 0 || tot[1] >= (int64_t(1) << 40) || tot[0] >= (int64_t(1) << 32))
     return fail(SNN_ERR_INVALID_ARG,
                 "vp_ptr[N] = %lld (< 2^32 required: messages carry 32-bit pair indices) or "
                 "row_ptr[N] = %lld (< 2^40) out of range",
                 (long long)tot[0], (long long)tot[1]);
-  }
   k.n_pairs = uint64_t(tot[0]);
   k.nnz = uint64_t(tot[1]);
   e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
   build_pois_lut(params->poisson_thr, c->pois_lut);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + L.pois_lut, c->pois_lut.data(), POIS_LUT_SIZE, hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(ws + L.pois_lut, c->pois_lut, POIS_LUT_SIZE, hipMemcpyHostToDevice,
                        c->stream);
   if (e == hipSuccess) {
     e = prepare_kernels(k);
-    if (e == hipErrorInvalidConfiguration) {
-      delete c;
+    if (e == hipErrorInvalidConfiguration)
       return fail(SNN_ERR_UNSUPPORTED,
                   "create: %u tiles of neurons leave no deliver window in the device's LDS "
                   "(about 8e7 neurons at most)", k.n_tiles);
-    }
   }
-  if (e != hipSuccess) {
+  if (e != hipSuccess) return fail(SNN_ERR_HIP, "create: %s", hipGetErrorString(e));
+  return SNN_OK;
+}
+
+}  // namespace
+
+snn_status snn_create(const snn_params* params, const snn_network_dev* net, void* workspace,
+                      size_t workspace_bytes, void* stream, snn_handle* out) {
+  if (!out) return fail(SNN_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  snn_status s = check_params(params);
+  if (s != SNN_OK) return s;
+  s = check_net(net);
+  if (s != SNN_OK) return s;
+  const Layout L = layout(params);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(SNN_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(SNN_ERR_INVALID_ARG, "workspace has %zu bytes, needs %llu", workspace_bytes,
+                (unsigned long long)L.total);
+  snn_ctx* c = new snn_ctx();
+  s = init_ctx(c, params, net, static_cast<char*>(workspace), L, stream);
+  if (s != SNN_OK) {
     delete c;
-    return fail(SNN_ERR_HIP, "create: %s", hipGetErrorString(e));
+    return s;
   }
   *out = c;
   return SNN_OK;
@@ -362,6 +382,38 @@ static hipError_t launch_step(const KParams& kp, int mode, hipStream_t s, hipEve
   return e;
 }
 
+// The same step with the neuron update (and its routing) launched once per
+// partition, over that partition's neurons [start[p], start[p+1]) only: the
+// launches of a step append their fired ids in partition order, and the last
+// one advances the step.  The receive side is one launch set as above.
+static hipError_t launch_step_partitioned(const KParams& kp, int mode, hipStream_t s,
+                                          const std::vector<uint32_t>& start) {
+  const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(kp);
+  const uint32_t P = static_cast<uint32_t>(start.size()) - 1;
+  uint32_t last = P;
+  for (uint32_t p = 0; p < P; ++p)
+    if (start[p + 1] > start[p]) last = p;
+  hipError_t e = hipSuccess;
+  for (uint32_t p = 0; p < P && e == hipSuccess; ++p) {
+    if (start[p + 1] == start[p]) continue;
+    KParams q = kp;
+    q.lo = start[p];
+    q.hi = start[p + 1];
+    q.tile0 = q.lo / TILE;
+    q.tile_end = (q.hi - 1) / TILE + 1;
+    q.step_ends = p == last ? 1u : 0u;
+    e = launch_update(q, s, nullptr, fused);
+  }
+  if (e == hipSuccess) e = launch_route(kp, mode, s, nullptr, fused, true);
+  if (e == hipSuccess) e = launch_deliver(kp, mode, s, nullptr, true);
+  return e;
+}
+
+static hipError_t launch_step_as(snn_handle h, int layout, int mode) {
+  return layout ? launch_step_partitioned(h->kp, mode, h->stream, h->part_start)
+                : launch_step(h->kp, mode, h->stream, nullptr);
+}
+
 snn_status snn_deliver(snn_handle h) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
   if (h->phase != 2) return fail(SNN_ERR_BAD_STATE, "snn_deliver must follow snn_route");
@@ -372,54 +424,132 @@ snn_status snn_deliver(snn_handle h) {
   return SNN_OK;
 }
 
-// Captures (once) a graph of one step (which = 0) or GRAPH_STEPS steps
-// (which = 1) in route mode `mode`.
-static snn_status ensure_graph(snn_handle h, int mode, int which) {
-  if (h->graph[mode][which]) return SNN_OK;
-  const uint32_t steps = which ? GRAPH_STEPS : 1u;
+// Captures n steps of the given layout and mode into one executable graph.
+static snn_status capture_steps(snn_handle h, int layout, int mode, uint32_t steps,
+                                hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (uint32_t i = 0; i < steps && e == hipSuccess; ++i) e = launch_step(h->kp, mode, h->stream, nullptr);
+  for (uint32_t i = 0; i < steps && e == hipSuccess; ++i) e = launch_step_as(h, layout, mode);
   hipError_t ec = hipStreamEndCapture(h->stream, &g);
   if (e != hipSuccess || ec != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
     return fail(SNN_ERR_HIP, "graph capture failed: %s",
                 hipGetErrorString(e != hipSuccess ? e : ec));
   }
-  hipError_t ei = hipGraphInstantiate(&h->graph[mode][which], g, nullptr, nullptr, 0);
+  hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) {
-    h->graph[mode][which] = nullptr;
+    *out = nullptr;
     return fail(SNN_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
   }
   return SNN_OK;
 }
 
-snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
-  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+// Every captured graph holds the kernel parameters of its capture: dropped
+// when they change.
+static void drop_graphs(snn_handle h) {
+  for (auto& gl : h->graph)
+    for (auto& gm : gl)
+      for (auto& g : gm)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+  if (h->whole) (void)hipGraphExecDestroy(h->whole);
+  h->whole = nullptr;
+}
+
+static snn_status run_steps(snn_handle h, uint32_t n_steps, int mode, int use_graph, int layout) {
   if (mode < SNN_ROUTE_TWO_LEVEL || mode > SNN_ROUTE_BOTH)
     return fail(SNN_ERR_INVALID_ARG, "route mode %d", mode);
+  if (use_graph < 0 || use_graph > 2) return fail(SNN_ERR_INVALID_ARG, "use_graph %d", use_graph);
   if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_run called in the middle of a step");
   if (n_steps == 0) return SNN_OK;
   if (!use_graph) {
-    for (uint32_t i = 0; i < n_steps; ++i) HIP_TRY(launch_step(h->kp, mode, h->stream, nullptr));
+    for (uint32_t i = 0; i < n_steps; ++i) HIP_TRY(launch_step_as(h, layout, mode));
+  } else if (use_graph == 2) {
+    const uint32_t key[3] = {n_steps, uint32_t(mode), uint32_t(layout)};
+    if (h->whole && std::memcmp(key, h->whole_key, sizeof(key)) != 0) {
+      (void)hipGraphExecDestroy(h->whole);
+      h->whole = nullptr;
+    }
+    if (!h->whole) {
+      snn_status st = capture_steps(h, layout, mode, n_steps, &h->whole);
+      if (st != SNN_OK) return st;
+      std::memcpy(h->whole_key, key, sizeof(key));
+    }
+    HIP_TRY(hipGraphLaunch(h->whole, h->stream));
   } else {
     const uint32_t n_long = n_steps / GRAPH_STEPS, n_short = n_steps % GRAPH_STEPS;
-    if (n_long) {
-      snn_status st = ensure_graph(h, mode, 1);
-      if (st != SNN_OK) return st;
-      for (uint32_t i = 0; i < n_long; ++i) HIP_TRY(hipGraphLaunch(h->graph[mode][1], h->stream));
-    }
-    if (n_short) {
-      snn_status st = ensure_graph(h, mode, 0);
-      if (st != SNN_OK) return st;
-      for (uint32_t i = 0; i < n_short; ++i) HIP_TRY(hipGraphLaunch(h->graph[mode][0], h->stream));
+    for (int which = 1; which >= 0; --which) {
+      const uint32_t reps = which ? n_long : n_short;
+      if (!reps) continue;
+      hipGraphExec_t& g = h->graph[layout][mode][which];
+      if (!g) {
+        snn_status st = capture_steps(h, layout, mode, which ? GRAPH_STEPS : 1u, &g);
+        if (st != SNN_OK) return st;
+      }
+      for (uint32_t i = 0; i < reps; ++i) HIP_TRY(hipGraphLaunch(g, h->stream));
     }
   }
   h->route_mode = mode;
   h->t_host += n_steps;
   h->routed_t = h->t_host;
+  return SNN_OK;
+}
+
+snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
+  if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
+  return run_steps(h, n_steps, mode, use_graph, 0);
+}
+
+snn_status snn_run_partitioned(snn_handle h, uint32_t n_steps, int mode, int use_graph,
+                               const uint32_t* part_start) {
+  if (!h || !part_start) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  const uint32_t P = h->kp.P;
+  if (part_start[0] != 0 || part_start[P] != h->kp.N)
+    return fail(SNN_ERR_INVALID_ARG, "part_start must run from 0 to n_neurons (%u)", h->kp.N);
+  for (uint32_t p = 0; p < P; ++p)
+    if (part_start[p + 1] < part_start[p])
+      return fail(SNN_ERR_INVALID_ARG, "part_start decreases at partition %u", p);
+  if (h->part_start.size() != P + 1 ||
+      !std::equal(h->part_start.begin(), h->part_start.end(), part_start)) {
+    for (auto& gm : h->graph[1])
+      for (auto& g : gm)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+    if (h->whole && h->whole_key[2] == 1) {
+      (void)hipGraphExecDestroy(h->whole);
+      h->whole = nullptr;
+    }
+    h->part_start.assign(part_start, part_start + P + 1);
+  }
+  return run_steps(h, n_steps, mode, use_graph, 1);
+}
+
+snn_status snn_set_tuning(snn_handle h, const snn_tuning* t) {
+  if (!h || !t) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_set_tuning called in the middle of a step");
+  if (t->update_blocks > h->kp.n_tiles)
+    return fail(SNN_ERR_INVALID_ARG, "update_blocks %u > %u tiles", t->update_blocks, h->kp.n_tiles);
+  if (t->recv_split > STAGE_BLOCKS)
+    return fail(SNN_ERR_INVALID_ARG, "recv_split %u > %u", t->recv_split, STAGE_BLOCKS);
+  if (h->kp.update_blocks != t->update_blocks || h->kp.recv_split != t->recv_split) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->kp.update_blocks = t->update_blocks;
+    h->kp.recv_split = t->recv_split;
+  }
+  return SNN_OK;
+}
+
+snn_status snn_get_tuning(snn_handle h, snn_tuning* t) {
+  if (!h || !t) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  t->update_blocks = h->kp.update_blocks;
+  t->recv_split = h->kp.recv_split;
   return SNN_OK;
 }
 
@@ -434,13 +564,13 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
   // the launches queue up behind each other as in a normal run, so no start
   // event fires on an idle queue ahead of its kernel.
   const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(h->kp);
-  // expansion, staging and delivery of a two-level step share one launch
+  // expansion and staging of a two-level step share the receive-side launch
   const bool launched[SNN_NKERNEL] = {true,
                                       mode != SNN_ROUTE_FLAT && !fused,
                                       false,
                                       mode != SNN_ROUTE_TWO_LEVEL,
                                       true,
-                                      mode == SNN_ROUTE_FLAT};
+                                      true};
   std::vector<hipEvent_t> marks(size_t(2) * SNN_NKERNEL * n_steps, nullptr);
   snn_status st = SNN_OK;
   for (auto& e : marks) {
@@ -494,8 +624,6 @@ static snn_status sync_and_check(snn_handle h, DevState* out) {
   if (out) *out = st;
   if (st.error & ERR_ROUTE)
     return fail(SNN_ERR_HIP, "receive entry without a matching destination partition");
-  if (st.error & ERR_TIMEOUT)
-    return fail(SNN_ERR_HIP, "a device-side wait between blocks of one launch timed out");
   if (st.error)
     return fail(SNN_ERR_CAPACITY, "device capacity overflow (bits 0x%x: 1 bucket, 2 receive "
                 "list, 4 flat list, 8 spike log)", st.error);
@@ -645,9 +773,7 @@ snn_status snn_destroy(snn_handle h) {
   snn_status s = SNN_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) s = fail(SNN_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-  for (auto& gm : h->graph)
-    for (auto& g : gm)
-      if (g) (void)hipGraphExecDestroy(g);
+  drop_graphs(h);
   delete h;
   return s;
 }

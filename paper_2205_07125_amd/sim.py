@@ -83,8 +83,7 @@ class Simulation:
             stage_cap=stage_cap)
         self.ws_bytes = _abi.snn_workspace_size(self.params)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        self.ws_ptr = (base + 255) & ~255
+        self.ws_ptr = (self.workspace.data_ptr() + 255) & ~255
         self.net = _abi.snn_network_dev(
             row_ptr=self.t_row_ptr.data_ptr(), n_local=self.t_n_local.data_ptr(),
             delay_off=self.t_delay_off.data_ptr(),
@@ -119,8 +118,25 @@ class Simulation:
         self.route(mode)
         self.deliver()
 
-    def run(self, n_steps: int, mode=_abi.SNN_ROUTE_TWO_LEVEL, use_graph: bool = True):
+    def run(self, n_steps: int, mode=_abi.SNN_ROUTE_TWO_LEVEL, use_graph=True):
+        """use_graph: False eager, True 16-step graphs, 2 one graph of all n_steps."""
         _abi.snn_run(self.h, n_steps, mode, use_graph)
+
+    def run_partitioned(self, n_steps: int, mode=_abi.SNN_ROUTE_TWO_LEVEL, use_graph=True):
+        """snn_run_partitioned: the update launched once per partition (the
+        workload's partitions must be contiguous ranges)."""
+        import synth
+        starts = synth.partition_starts(self.wl)
+        if starts is None:     # loopback shapes: every neuron is in partition 0
+            starts = np.full(self.wl.n_partitions + 1, self.wl.n_neurons, np.uint32)
+            starts[0] = 0
+        _abi.snn_run_partitioned(self.h, n_steps, mode, use_graph, starts)
+
+    def set_tuning(self, update_blocks: int = 0, recv_split: int = 0):
+        _abi.snn_set_tuning(self.h, update_blocks, recv_split)
+
+    def tuning(self) -> dict:
+        return _abi.snn_get_tuning(self.h)
 
     def sync(self):
         _abi.snn_sync(self.h)
@@ -193,6 +209,12 @@ class Simulation:
         _abi.check(_abi.lib().snn_read_counters(self.h, first_step, n_steps,
                                                 out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def membrane(self) -> np.ndarray:
+        """u as a host array, after the stream's work; nothing else is read or
+        moved, so the simulation continues exactly as it would have."""
+        self.sync()
+        return self.u.cpu().numpy()
 
     def state(self) -> dict:
         """u, ref and the ring (D x N) as host arrays.  Pending binned events
