@@ -230,6 +230,29 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net,
                       void* workspace, size_t workspace_bytes, void* stream,
                       snn_handle* out);
 
+/* Size of the library's static device scratch used by snn_create_static. */
+#define SNN_STATIC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid allocation): snn_create without the
+   workspace argument.  The handle's workspace is the library's static device
+   array of SNN_STATIC_SCRATCH_BYTES (one per device, held until the process
+   ends) and the handle itself lives in static host storage, so the call
+   allocates nothing, host or device; its set-up (clearing the counters,
+   building the Poisson lookup) runs as kernels on `stream`.  Networks whose
+   workspace (snn_workspace_size) exceeds SNN_STATIC_SCRATCH_BYTES (a few
+   thousand neurons at the workloads' shapes) are rejected with
+   SNN_ERR_UNSUPPORTED.
+   Every call on a device shares that device's scratch and static handle: a
+   call replaces the previous static handle of the device (which must no
+   longer be used) and its state; calls and steps that overlap on one device
+   race.  All other calls take the handle as usual, except that snn_run
+   rejects use_graph != 0 (instantiating a graph allocates); snn_destroy
+   only synchronises (so destroying a replaced handle is harmless).  Not
+   thread-safe. */
+snn_status snn_create_static(const snn_params* params, const snn_network_dev* net, void* stream,
+                             snn_handle* out);
+
 /* Neuron update, threshold and ascending compaction of fired ids for the
    current step t (ring slot t mod D is read and cleared).  Order: must follow
    snn_create or snn_deliver. */
@@ -271,7 +294,7 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph);
    of neuron ids: partition p holds [part_start[p], part_start[p+1]) (host
    array of n_partitions + 1 entries, part_start[0] = 0,
    part_start[n_partitions] = n_neurons; empty partitions are skipped).
-   Results are identical to snn_run's. */
+   Results are identical to snn_run's.  Not for snn_create_static handles. */
 snn_status snn_run_partitioned(snn_handle h, uint32_t n_steps, int mode, int use_graph,
                                const uint32_t* part_start);
 

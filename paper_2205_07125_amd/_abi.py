@@ -15,6 +15,8 @@ SNN_ERR_CAPACITY = -3
 SNN_ERR_HIP = -4
 SNN_ERR_UNSUPPORTED = -5
 
+SNN_STATIC_SCRATCH_BYTES = 32 << 20   # snn_create_static's device scratch
+
 SNN_ROUTE_TWO_LEVEL = 0
 SNN_ROUTE_FLAT = 1
 SNN_ROUTE_BOTH = 2
@@ -33,7 +35,7 @@ KERNEL_NAMES = ["update", "route_two_level", "expand", "route_flat", "recv_stage
 SNN_NKERNEL = len(KERNEL_NAMES)
 
 EXPORTED = [
-    "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_step", "snn_route", "snn_step_route",
+    "snn_ring_stride", "snn_workspace_size", "snn_create", "snn_create_static", "snn_step", "snn_route", "snn_step_route",
     "snn_deliver", "snn_run", "snn_run_partitioned", "snn_set_tuning", "snn_get_tuning",
     "snn_kernel_times", "snn_flush", "snn_sync", "snn_time",
     "snn_bin_geometry",
@@ -110,6 +112,8 @@ def lib() -> ctypes.CDLL:
             "snn_workspace_size": (I, [ctypes.POINTER(snn_params), ctypes.POINTER(ctypes.c_size_t)]),
             "snn_create": (I, [ctypes.POINTER(snn_params), ctypes.POINTER(snn_network_dev), vp,
                                ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+            "snn_create_static": (I, [ctypes.POINTER(snn_params), ctypes.POINTER(snn_network_dev),
+                                      vp, ctypes.POINTER(vp)]),
             "snn_step": (I, [vp]),
             "snn_route": (I, [vp, I]),
             "snn_step_route": (I, [vp, I]),
@@ -167,6 +171,13 @@ def snn_create(params: snn_params, net: snn_network_dev, workspace: int, ws_byte
     h = vp()
     check(lib().snn_create(ctypes.byref(params), ctypes.byref(net), workspace, ws_bytes, stream,
                            ctypes.byref(h)))
+    return h.value
+
+
+def snn_create_static(params: snn_params, net: snn_network_dev, stream: int) -> int:
+    h = vp()
+    check(lib().snn_create_static(ctypes.byref(params), ctypes.byref(net), stream,
+                                  ctypes.byref(h)))
     return h.value
 
 

@@ -194,5 +194,9 @@ hipError_t launch_route(const KParams& p, int mode, hipStream_t s, hipEvent_t* m
 hipError_t launch_deliver(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks = nullptr,
                           bool fused_expand = false);
 hipError_t launch_flush(const KParams& p, hipStream_t s);
+// Set-up without memset or host copies: zeroes bytes (a multiple of 4) at
+// dst; builds the Poisson lookup from p.thr into lut.
+hipError_t launch_zero(void* dst, uint64_t bytes, hipStream_t s);
+hipError_t launch_pois_lut(const KParams& p, uint8_t* lut, hipStream_t s);
 
 }  // namespace snn

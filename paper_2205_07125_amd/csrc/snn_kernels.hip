@@ -1569,6 +1569,34 @@ __global__ __launch_bounds__(256) void k_flush(KParams p) {
   if (threadIdx.x == 0 && any) p.dirty[slot * p.n_tiles + tile] = 1u;
 }
 
+// Set-up kernels of the allocation-free entry point (snn_create_static),
+// which writes no memset or host-to-device copy into the stream.
+
+// Zeroes n 32-bit words at dst.
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* dst, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = 0u;
+}
+
+// The Poisson inversion lookup (layout in snn_internal.h) from the
+// thresholds p.thr: entry b covers the draws [lo, hi] = [b << POIS_LUT_SHIFT,
+// lo + 2^POIS_LUT_SHIFT - 1]; no threshold in (lo, hi] fixes k, exactly one
+// is resolved by one comparison in the update.
+__global__ __launch_bounds__(256) void k_pois_lut(KParams p, uint8_t* lut) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= POIS_LUT_SIZE) return;
+  const uint64_t lo = static_cast<uint64_t>(b) << POIS_LUT_SHIFT;
+  const uint64_t hi = lo + (uint64_t(1) << POIS_LUT_SHIFT) - 1;
+  uint32_t k_lo = 0, k_hi = 0;
+  for (int j = 0; j < 15; ++j) {
+    k_lo += p.thr[j] <= lo ? 1u : 0u;
+    k_hi += p.thr[j] <= hi ? 1u : 0u;
+  }
+  lut[b] = k_hi == k_lo ? static_cast<uint8_t>(k_lo)
+         : k_hi == k_lo + 1 ? static_cast<uint8_t>(16 + k_lo) : POIS_LUT_SLOW;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -1709,6 +1737,19 @@ hipError_t prepare_kernels(KParams& p) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_zero(void* dst, uint64_t bytes, hipStream_t s) {
+  const uint64_t words = bytes / 4;
+  const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>((words + 255) / 256, 4096));
+  if (blocks) hipLaunchKernelGGL(k_zero_words, dim3(blocks), dim3(256), 0, s,
+                                 static_cast<uint32_t*>(dst), words);
+  return hipGetLastError();
+}
+
+hipError_t launch_pois_lut(const KParams& p, uint8_t* lut, hipStream_t s) {
+  hipLaunchKernelGGL(k_pois_lut, dim3(POIS_LUT_SIZE / 256), dim3(256), 0, s, p, lut);
+  return hipGetLastError();
 }
 
 hipError_t launch_flush(const KParams& p, hipStream_t s) {

@@ -165,11 +165,25 @@ struct snn_ctx {
   uint32_t whole_key[3];        // its steps, mode, layout
   std::vector<uint32_t> part_start;   // partition starts of the per-partition layout
   uint8_t pois_lut[POIS_LUT_SIZE];  // host copy of the lookup uploaded at create
+  bool is_static;     // from snn_create_static: lives in static storage, never freed
 };
 
 // Steps captured in the long graph: replaying several steps per launch spreads
 // the graph launch cost (several microseconds) over them.
 constexpr uint32_t GRAPH_STEPS = 16;
+
+// Scratch of the allocation-free entry point (snn_create_static): the whole
+// workspace of one handle, at most SNN_STATIC_SCRATCH_BYTES.  Each device that
+// runs the library holds its own copy until the process ends.  Host code
+// never passes the array's name as an address: each device's copy is found
+// with hipGetSymbolAddress, that device current, and kept in g_scratch.
+__device__ __align__(256) uint8_t scratch[SNN_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int STATIC_DEVICES = 64;
+void* g_scratch[STATIC_DEVICES];        // device address of each device's copy of scratch
+snn_ctx g_static_ctx[STATIC_DEVICES];   // the handle that uses it
+}  // namespace
 
 extern "C" {
 
@@ -204,9 +218,11 @@ snn_status check_net(const snn_network_dev* net) {
 }
 
 // Fills c for params / net with its workspace at ws (layout L) and clears
-// the workspace's counters on the stream.
+// the workspace's counters on the stream.  device_setup: the clearing and the
+// Poisson lookup are kernels, so the stream gets no memset node and no copy
+// from host memory.
 snn_status init_ctx(snn_ctx* c, const snn_params* params, const snn_network_dev* net, char* ws,
-                    const Layout& L, void* stream) {
+                    const Layout& L, void* stream, bool device_setup) {
   c->prm = *params;
   c->net = *net;
   c->stream = static_cast<hipStream_t>(stream);
@@ -295,11 +311,17 @@ snn_status init_ctx(snn_ctx* c, const snn_params* params, const snn_network_dev*
                 (long long)tot[0], (long long)tot[1]);
   k.n_pairs = uint64_t(tot[0]);
   k.nnz = uint64_t(tot[1]);
-  e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
-  build_pois_lut(params->poisson_thr, c->pois_lut);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + L.pois_lut, c->pois_lut, POIS_LUT_SIZE, hipMemcpyHostToDevice,
-                       c->stream);
+  if (device_setup) {
+    e = launch_zero(ws, L.bucket, c->stream);
+    if (e == hipSuccess)
+      e = launch_pois_lut(k, reinterpret_cast<uint8_t*>(ws + L.pois_lut), c->stream);
+  } else {
+    e = hipMemsetAsync(ws, 0, L.bucket, c->stream);
+    build_pois_lut(params->poisson_thr, c->pois_lut);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ws + L.pois_lut, c->pois_lut, POIS_LUT_SIZE, hipMemcpyHostToDevice,
+                         c->stream);
+  }
   if (e == hipSuccess) {
     e = prepare_kernels(k);
     if (e == hipErrorInvalidConfiguration)
@@ -328,9 +350,48 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net, void
     return fail(SNN_ERR_INVALID_ARG, "workspace has %zu bytes, needs %llu", workspace_bytes,
                 (unsigned long long)L.total);
   snn_ctx* c = new snn_ctx();
-  s = init_ctx(c, params, net, static_cast<char*>(workspace), L, stream);
+  s = init_ctx(c, params, net, static_cast<char*>(workspace), L, stream, false);
   if (s != SNN_OK) {
     delete c;
+    return s;
+  }
+  *out = c;
+  return SNN_OK;
+}
+
+snn_status snn_create_static(const snn_params* params, const snn_network_dev* net, void* stream,
+                             snn_handle* out) {
+  if (!out) return fail(SNN_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  snn_status s = check_params(params);
+  if (s != SNN_OK) return s;
+  s = check_net(net);
+  if (s != SNN_OK) return s;
+  const Layout L = layout(params);
+  if (L.total > SNN_STATIC_SCRATCH_BYTES)
+    return fail(SNN_ERR_UNSUPPORTED,
+                "snn_create_static: the network needs %llu bytes of workspace, more than the "
+                "%u bytes of the static scratch; use snn_create with a workspace",
+                (unsigned long long)L.total, SNN_STATIC_SCRATCH_BYTES);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= STATIC_DEVICES)
+    return fail(SNN_ERR_UNSUPPORTED, "snn_create_static: device %d (at most %d devices)", dev,
+                STATIC_DEVICES);
+  if (!g_scratch[dev]) {
+    // once per device, with that device current: the address of its copy
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SNN_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch[dev] = ptr;
+  }
+  snn_ctx* c = &g_static_ctx[dev];
+  *c = snn_ctx{};
+  c->is_static = true;
+  s = init_ctx(c, params, net, static_cast<char*>(g_scratch[dev]), L, stream, true);
+  if (s != SNN_OK) {
+    *c = snn_ctx{};
     return s;
   }
   *out = c;
@@ -465,6 +526,9 @@ static snn_status run_steps(snn_handle h, uint32_t n_steps, int mode, int use_gr
     return fail(SNN_ERR_INVALID_ARG, "route mode %d", mode);
   if (use_graph < 0 || use_graph > 2) return fail(SNN_ERR_INVALID_ARG, "use_graph %d", use_graph);
   if (h->phase != 0) return fail(SNN_ERR_BAD_STATE, "snn_run called in the middle of a step");
+  if (use_graph && h->is_static)
+    return fail(SNN_ERR_UNSUPPORTED, "snn_run: a handle from snn_create_static runs without "
+                "HIP graphs (instantiating one allocates)");
   if (n_steps == 0) return SNN_OK;
   if (!use_graph) {
     for (uint32_t i = 0; i < n_steps; ++i) HIP_TRY(launch_step_as(h, layout, mode));
@@ -507,6 +571,9 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph) {
 snn_status snn_run_partitioned(snn_handle h, uint32_t n_steps, int mode, int use_graph,
                                const uint32_t* part_start) {
   if (!h || !part_start) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  if (h->is_static)
+    return fail(SNN_ERR_UNSUPPORTED, "snn_run_partitioned: not for a handle from "
+                "snn_create_static (it keeps a host copy of the partition starts)");
   const uint32_t P = h->kp.P;
   if (part_start[0] != 0 || part_start[P] != h->kp.N)
     return fail(SNN_ERR_INVALID_ARG, "part_start must run from 0 to n_neurons (%u)", h->kp.N);
@@ -773,6 +840,8 @@ snn_status snn_destroy(snn_handle h) {
   snn_status s = SNN_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) s = fail(SNN_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  if (h->is_static) return s;   // static storage: never freed (a newer static
+                                // handle of the device may already use it)
   drop_graphs(h);
   delete h;
   return s;

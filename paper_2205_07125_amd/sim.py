@@ -24,7 +24,10 @@ class Simulation:
     def __init__(self, wl, host: HostNetwork | None = None, device: str = "cuda",
                  log_steps: int | None = None, log_cap: int | None = None,
                  bucket_off=None, recv_off=None, bin_cap: int | None = None,
-                 stage_cap: int | None = None, verbose: bool = False):
+                 stage_cap: int | None = None, verbose: bool = False, static: bool = False):
+        """static: the handle comes from snn_create_static (workspace in the
+        library's static device scratch, nothing allocated by the call; one such
+        handle per device at a time, small networks only)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the simulation runs only in libsnn's HIP kernels")
@@ -82,8 +85,11 @@ class Simulation:
             log_steps=log_steps, input_bound=host.input_bound, log_cap=log_cap, bin_cap=bin_cap,
             stage_cap=stage_cap)
         self.ws_bytes = _abi.snn_workspace_size(self.params)
-        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        self.ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.static = static
+        if not static:
+            self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
+                                         device=self.device)
+            self.ws_ptr = (self.workspace.data_ptr() + 255) & ~255
         self.net = _abi.snn_network_dev(
             row_ptr=self.t_row_ptr.data_ptr(), n_local=self.t_n_local.data_ptr(),
             delay_off=self.t_delay_off.data_ptr(),
@@ -96,8 +102,11 @@ class Simulation:
         # on the legacy default stream.
         self.stream = torch.cuda.Stream(device=self.device)
         torch.cuda.synchronize(self.device)
-        self.h = _abi.snn_create(self.params, self.net, self.ws_ptr, self.ws_bytes,
-                                 self.stream.cuda_stream)
+        if static:
+            self.h = _abi.snn_create_static(self.params, self.net, self.stream.cuda_stream)
+        else:
+            self.h = _abi.snn_create(self.params, self.net, self.ws_ptr, self.ws_bytes,
+                                     self.stream.cuda_stream)
 
     # --- the C ABI, one call each -------------------------------------------------
     def step(self):

@@ -111,6 +111,24 @@ def test_create_rejects_null_arrays_and_bad_workspace():
         _abi.snn_create(p, net, 4096, 16, 0)   # too small
 
 
+def test_create_static_rejects_before_touching_the_device():
+    """Argument errors and a workspace larger than the static scratch are
+    reported on the host, before any HIP call."""
+    p = _params()
+    with pytest.raises(_abi.SNNError) as ei:
+        _abi.snn_create_static(p, _abi.snn_network_dev(), 0)
+    assert ei.value.status == _abi.SNN_ERR_INVALID_ARG
+    fake = {n: 4096 * (i + 1) for i, (n, _) in enumerate(_abi.snn_network_dev._fields_)}
+    net = _abi.snn_network_dev(**fake)
+    big = _params()
+    big.recv_total = _abi.SNN_STATIC_SCRATCH_BYTES // 8     # the lists alone fill the scratch
+    assert _abi.snn_workspace_size(big) > _abi.SNN_STATIC_SCRATCH_BYTES
+    with pytest.raises(_abi.SNNError) as ei:
+        _abi.snn_create_static(big, net, 0)
+    assert ei.value.status == _abi.SNN_ERR_UNSUPPORTED
+    assert "static scratch" in _abi.snn_last_error()
+
+
 def test_null_handle_calls():
     L = _abi.lib()
     assert L.snn_step(None) == _abi.SNN_ERR_INVALID_ARG
@@ -132,6 +150,12 @@ def test_counter_and_kernel_enums_match_binding():
     assert [k.lower() for k, _ in sorted(kinds.items(), key=lambda kv: kv[1])] == _abi.KERNEL_NAMES
     assert int(re.search(r"SNN_NKERNEL = (\d+)", src).group(1)) == _abi.SNN_NKERNEL
     assert int(re.search(r"SNN_NSTAT = (\d+)", src).group(1)) == _abi.SNN_NSTAT
+
+
+def test_static_scratch_size_matches_header():
+    src = open(os.path.join(ROOT, "include", "snn.h")).read()
+    m = re.search(r"#define SNN_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == _abi.SNN_STATIC_SCRATCH_BYTES
 
 
 def test_one_hip_runtime_in_process():
