@@ -65,7 +65,15 @@ def gpu_traffic(P, W: np.ndarray, pm: np.ndarray, n_gpus: int) -> np.ndarray:
 def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
                 A: sp.csr_matrix | None = None) -> np.ndarray:
     """One pass of Algorithm 1's loop from the given seed neurons (one per
-    GPU, distinct).  Returns PM[M] in [0, n_gpus)."""
+    GPU, distinct).  Returns PM[M] in [0, n_gpus).
+
+    Each GPU keeps its frontier sparse: the summed probability to its members
+    of only the free neurons adjacent to them, in a max-heap (stale entries
+    are skipped when popped).  A GPU whose frontier is empty takes the
+    lowest-id free neuron, which is what a dense argmax over all-zero sums
+    would pick, so the maps equal those of the dense form while memory stays
+    O(synapses + M) instead of O(n_gpus * M)."""
+    import heapq
     W = np.asarray(W, np.float64)
     M = len(W)
     if not 1 <= n_gpus <= M:
@@ -77,17 +85,34 @@ def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
     target = W.sum() / n_gpus
     pm = np.full(M, -1, np.int64)
     load = np.zeros(n_gpus)
-    # summed probability from each GPU's members to each neuron; -inf once placed
-    aff = np.zeros((n_gpus, M))
+    aff = [dict() for _ in range(n_gpus)]   # free neuron -> summed probability to members
+    heaps = [[] for _ in range(n_gpus)]     # (-sum, neuron), possibly stale
     free = np.ones(M, bool)
+    lowest_free = 0
 
     def place(i, j):
         pm[j] = i
         free[j] = False
         load[i] += W[j]
         lo, hi = A.indptr[j], A.indptr[j + 1]
-        aff[i, A.indices[lo:hi]] += A.data[lo:hi]
-        aff[:, j] = -np.inf
+        ai, hp = aff[i], heaps[i]
+        for k, a in zip(A.indices[lo:hi].tolist(), A.data[lo:hi].tolist()):
+            if free[k]:
+                v = ai.get(k, 0.0) + a
+                ai[k] = v
+                heapq.heappush(hp, (-v, k))
+
+    def best(i):
+        nonlocal lowest_free
+        ai, hp = aff[i], heaps[i]
+        while hp:
+            v, k = hp[0]
+            if free[k] and ai.get(k) == -v:
+                return k
+            heapq.heappop(hp)
+        while not free[lowest_free]:
+            lowest_free += 1
+        return lowest_free
 
     for i, j in enumerate(seeds):
         place(i, int(j))
@@ -99,7 +124,7 @@ def greedy_pass(P, W: np.ndarray, n_gpus: int, seeds: np.ndarray,
                 break
             if load[i] >= target:
                 continue
-            place(i, int(np.argmax(aff[i])))
+            place(i, best(i))
             n_free -= 1
             moved = True
         if not moved:

@@ -217,3 +217,75 @@ def test_device_layout_contiguous_ranges():
         assert np.all(np.diff(nid[ids]) == 1)
     with pytest.raises(ValueError):
         pt.device_layout(pm, np.array([0] * 5 + [1] * 7), G)
+
+
+def _dense_greedy_pass(P, W, n_gpus, seeds):
+    """The pass with a dense GPUs x neurons affinity array and argmax (lowest
+    id among ties): the plain form the sparse frontier must reproduce."""
+    A = pt._sym_csr(P)
+    W = np.asarray(W, np.float64)
+    M = len(W)
+    target = W.sum() / n_gpus
+    pm = np.full(M, -1, np.int64)
+    load = np.zeros(n_gpus)
+    aff = np.zeros((n_gpus, M))
+    free = np.ones(M, bool)
+
+    def place(i, j):
+        pm[j] = i
+        free[j] = False
+        load[i] += W[j]
+        lo, hi = A.indptr[j], A.indptr[j + 1]
+        aff[i, A.indices[lo:hi]] += A.data[lo:hi]
+        aff[:, j] = -np.inf
+
+    for i, j in enumerate(seeds):
+        place(i, int(j))
+    n_free = M - n_gpus
+    while n_free:
+        moved = False
+        for i in range(n_gpus):
+            if not n_free:
+                break
+            if load[i] >= target:
+                continue
+            place(i, int(np.argmax(aff[i])))
+            n_free -= 1
+            moved = True
+        if not moved:
+            break
+    for j in np.where(free)[0][np.argsort(-W[free], kind="stable")]:
+        place(int(np.argmin(load)), int(j))
+    return pm
+
+
+@pytest.mark.parametrize("M,N,density,seed", [(40, 3, 0.1, 0), (120, 7, 0.03, 1),
+                                              (300, 16, 0.01, 2), (200, 5, 0.0, 3)])
+def test_sparse_frontier_equals_dense_argmax(M, N, density, seed):
+    """The heap frontier picks what the dense argmax picks, ties and
+    neurons without links to a GPU's members (lowest free id) included."""
+    P, W = _rand_p(M, density, seed)
+    rng = np.random.default_rng(seed + 10)
+    seeds = rng.choice(M, N, replace=False)
+    assert np.array_equal(pt.greedy_pass(sp.csr_matrix(P), W, N, seeds),
+                          _dense_greedy_pass(P, W, N, seeds))
+
+
+def test_pass_memory_stays_sparse():
+    """100,000 neurons on 1,000 GPUs (a dense GPUs x neurons array would take
+    800 MB): the pass allocates O(synapses + neurons)."""
+    import tracemalloc
+    M, N, deg = 100_000, 1_000, 8
+    rng = np.random.default_rng(5)
+    rows = np.repeat(np.arange(M), deg)
+    cols = rng.integers(0, M, M * deg)
+    P = sp.csr_matrix((rng.random(M * deg), (rows, cols)), shape=(M, M))
+    W = np.ones(M)
+    A = pt._sym_csr(P)
+    seeds = rng.choice(M, N, replace=False)
+    tracemalloc.start()
+    pm = pt.greedy_pass(P, W, N, seeds, A=A)
+    peak = tracemalloc.get_traced_memory()[1]
+    tracemalloc.stop()
+    assert peak < 200e6
+    assert np.all(pm >= 0) and np.bincount(pm, minlength=N).max() <= M // N + 1
