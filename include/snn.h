@@ -28,10 +28,11 @@
  *                scheduled for step t + d (d = the synapse's delay) and summed
  *                into the target's input when that step's update runs
  *
- * Scheduled input lives in per-(step mod D, tile of neurons) bins, with a
- * dense delay ring ring[(max_delay+1)][n] as the overflow path for bins that
- * are full; snn_flush moves all binned input into the ring, after which the
- * ring alone holds the input of the coming steps.
+ * Scheduled input lives in per-(step mod D, tile of neurons) bins of
+ * fixed-point events, with a dense fixed-point overflow ring in the
+ * workspace for bins that are full; both are summed exactly.  snn_flush
+ * writes the input scheduled for the coming steps into the caller's dense
+ * ring ring[(max_delay+1)][n] as binary32, without changing either.
  *
  * Neuron model (the paper only names LIF as a model class, Table I):
  * current-based leaky integrate-and-fire with delta synapses, state
@@ -112,9 +113,10 @@ enum {
 
 /* Kernel kinds of a step, in launch order (snn_kernel_times).  In a whole
    two-level step as snn_run launches it, UPDATE also routes (up to 512 nodes
-   of at most 8 partitions), RECV_STAGE also expands the masks and, beside
-   the staging, bins the own-partition synapses, and DELIVER bins the
-   received ones. */
+   of at most 8 partitions) and RECV_STAGE also expands the masks and bins
+   the own-partition synapses; DELIVER bins the received ones (with
+   snn_tuning.recv_merged, RECV_STAGE does that too and there is no DELIVER
+   launch). */
 enum {
   SNN_KERNEL_UPDATE = 0,           /* neuron update, threshold, compaction */
   SNN_KERNEL_ROUTE_TWO_LEVEL = 1,  /* per-node messages with partition masks */
@@ -209,9 +211,9 @@ typedef struct {
                                       recv_off[p+1] - recv_off[p] entries */
   float* u;                        /* [N] membrane state, relative to rest (read/write) */
   uint8_t* ref;                    /* [N] refractory steps left (read/write) */
-  float* ring;                     /* [(max_delay+1) * ring_stride] delay ring, slot-major,
-                                      ring_stride = snn_ring_stride(N); zero-initialised by
-                                      the caller (read/write) */
+  float* ring;                     /* [(max_delay+1) * ring_stride] slot-major read-back of
+                                      the scheduled input, ring_stride = snn_ring_stride(N):
+                                      written by snn_flush only */
 } snn_network_dev;
 
 /* Slot stride of the delay ring: n_neurons rounded up to a multiple of 256. */
@@ -307,6 +309,10 @@ typedef struct {
   uint32_t recv_split;      /* most receive-side blocks that share one destination node's
                                messages (expansion and staging); 0 = as many as the
                                256 receive-side blocks allow, 1 = one block per node */
+  uint32_t recv_merged;     /* 0: the receive side of a whole step is two launches
+                               (expansion and staging beside the own-partition delivery,
+                               then the received synapses); 1: one launch, whose
+                               delivery blocks wait for its staging blocks */
 } snn_tuning;
 
 /* Sets / reads the handle's launch shapes.  Setting synchronises the stream
@@ -314,9 +320,12 @@ typedef struct {
 snn_status snn_set_tuning(snn_handle h, const snn_tuning* t);
 snn_status snn_get_tuning(snn_handle h, snn_tuning* t);
 
-/* Moves every pending binned synaptic event into the dense ring, so that the
-   ring alone holds the input scheduled for the coming steps (for read-back
-   of the state; the simulation continues unchanged).  Order: between steps. */
+/* Writes the input scheduled for each of the coming steps into `ring`: for
+   slot s and neuron i, the sum of the pending events for i at the step that
+   consumes slot s, rounded to binary32 exactly as the update will round it
+   (their fixed-point sum, see input_bound).  Reads only: the bins, the
+   overflow ring and every later step are unchanged, whatever the weights.
+   Order: between steps. */
 snn_status snn_flush(snn_handle h);
 
 /* Blocks until the handle's work is done; reports sticky device errors. */

@@ -70,7 +70,7 @@ class snn_network_dev(ctypes.Structure):
 
 
 class snn_tuning(ctypes.Structure):
-    _fields_ = [("update_blocks", u32), ("recv_split", u32)]
+    _fields_ = [("update_blocks", u32), ("recv_split", u32), ("recv_merged", u32)]
 
 
 class snn_setup_spec(ctypes.Structure):
@@ -209,15 +209,16 @@ def snn_run_partitioned(h, n_steps: int, mode: int, use_graph, part_start):
                                     starts.ctypes.data_as(ctypes.c_void_p)))
 
 
-def snn_set_tuning(h, update_blocks: int = 0, recv_split: int = 0):
-    t = snn_tuning(update_blocks=update_blocks, recv_split=recv_split)
+def snn_set_tuning(h, update_blocks: int = 0, recv_split: int = 0, recv_merged: int = 0):
+    t = snn_tuning(update_blocks=update_blocks, recv_split=recv_split, recv_merged=recv_merged)
     check(lib().snn_set_tuning(h, ctypes.byref(t)))
 
 
 def snn_get_tuning(h) -> dict:
     t = snn_tuning()
     check(lib().snn_get_tuning(h, ctypes.byref(t)))
-    return {"update_blocks": t.update_blocks, "recv_split": t.recv_split}
+    return {"update_blocks": t.update_blocks, "recv_split": t.recv_split,
+            "recv_merged": t.recv_merged}
 
 
 def snn_kernel_times(h, n_steps: int, mode: int):

@@ -1,6 +1,7 @@
 """Launch-shape autotuner: picks, per network shape, the snn_tuning values
-(persistent update blocks, receive-side blocks per destination node) that
-run whole steps fastest on this GPU, and caches the choice.
+(persistent update blocks, receive-side blocks per destination node, the
+receive side as one launch or two) that run whole steps fastest on this GPU,
+and caches the choice.
 
 None of the choices changes a result (the GPU tests check each against the
 default), so the tuner only times: for every candidate it replays whole
@@ -39,7 +40,8 @@ def shape_key(sim) -> str:
 def candidates(sim, cu_count: int | None = None) -> list[dict]:
     """update_blocks: one block per tile, or persistent grids of 1, 2 and 3
     blocks per CU where that is fewer than the tiles; recv_split: one block
-    per destination node up to as many as the 256 receive-side blocks allow."""
+    per destination node up to as many as the 256 receive-side blocks allow;
+    recv_merged: both forms of the receive side."""
     import torch
     wl = sim.wl
     tiles = (wl.n_neurons + 8191) // 8192
@@ -50,7 +52,8 @@ def candidates(sim, cu_count: int | None = None) -> list[dict]:
     rs = [0]
     if nodes < 256:
         rs += [s for s in (1, 2, 4, 8, 16, 32, 64) if s < 256 // nodes]
-    return [{"update_blocks": u, "recv_split": r} for u in ub for r in rs]
+    return [{"update_blocks": u, "recv_split": r, "recv_merged": m}
+            for u in ub for r in rs for m in (0, 1)]
 
 
 def time_candidate(sim, cand: dict, steps: int, warmup: int, mode: int) -> float:

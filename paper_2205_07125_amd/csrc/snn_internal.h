@@ -15,7 +15,17 @@ enum : uint32_t {
   ERR_RECV = 2u,     // an expanded receive list overflowed
   ERR_FLAT = 4u,     // a flat receive list overflowed
   ERR_LOG = 8u,      // a step had more spikes than the spike log holds
-  ERR_ROUTE = 16u    // a receive entry names a partition its source does not reach
+  ERR_ROUTE = 16u,   // a receive entry names a partition its source does not reach
+  ERR_TIMEOUT = 32u  // a wait between blocks of one launch gave up (a block it waited for
+                     // never arrived)
+};
+
+// Words of the in-launch synchronisation area (KParams::sync), each on a
+// 64-byte line of its own; every launch that uses one leaves it at zero.
+enum : uint32_t {
+  SYNC_STAGED = 0,    // staging blocks of the receive launch that are done
+  SYNC_RETIRED = 16,  // delivery blocks of that launch that are done
+  SYNC_WORDS = 64
 };
 
 // Device-resident step state.  Every step-dependent value lives here so that
@@ -135,6 +145,7 @@ struct KParams {
   uint32_t tile0, tile_end, lo, hi, step_ends;
   uint32_t update_blocks;   // grid of a whole-step update launch (0: one block per tile;
                             // fewer: persistent blocks taking tiles in ticket order)
+  uint32_t recv_merged;     // receive side of a whole step in one launch (1) or two (0)
   float wq_scale;      // 2^F: weight -> fixed point
   double wq_inv;       // 2^-F
   // network (caller-owned device memory)
@@ -153,11 +164,14 @@ struct KParams {
   uint64_t nnz;               // row_ptr[N]: synapses (bounds checks)
   float* u;
   uint8_t* ref;
-  float* ring;
+  float* ring;               // read-back view of the pending input (snn_flush)
   // workspace
+  int32_t* ovf;         // [D][ring_stride] overflow ring: fixed-point input of events that
+                        // did not fit their bin or staging queue
   DevState* st;
   uint64_t* lookback;   // [n_tiles] decoupled look-back words
   uint32_t* tickets;    // [2] tiles handed out by a persistent update, by step parity
+  uint32_t* sync;       // [SYNC_WORDS] in-launch arrival counters
   uint32_t* fired;      // [N] ascending fired ids of the step in flight
   uint32_t* bucket_cnt; // [2][n_nodes * CNT_STRIDE] two sets, by step parity
   uint64_t* bucket;     // [2 * bucket_total] messages: source | pair index of the

@@ -17,18 +17,20 @@
 //                  written as runs into per-(slot, tile, delay, block) bins
 //   k_route_flat   flat routing: one receive entry per destination partition
 //
-// A whole step is three launches: k_update<true> (update, compaction and the
-// tile's own two-level routing, which overlaps the look-back), k_recv_local
-// (expansion and staging beside the own-partition delivery: two independent
-// jobs in one launch) and k_deliver_remote (the staged remote synapses,
-// appended after the counts the local part published).  Each launch boundary
-// is also where the writes of one job become visible to the next: waiting
-// inside a launch for other blocks' writes would take a device-scope release
-// and acquire per block, which on a chip of several L2 caches (one per XCD)
-// writes back or invalidates a whole L2 each time and costs far more than a
-// launch boundary.  The step-by-step entry points use one kernel per job
-// instead (k_update<false>, k_route_two_level, k_expand, k_recv_stage,
-// k_deliver).
+// A whole step is two or three launches: k_update<true> (update, compaction
+// and the tile's own two-level routing, which overlaps the look-back), then
+// the receive side in one of two forms (snn_tuning.recv_merged):
+//   k_recv_local + k_deliver_remote: expansion and staging beside the
+//     own-partition delivery, then the staged remote synapses in a launch of
+//     their own, appended after the counts the local part published;
+//   k_recv_deliver: the same in one launch, the delivery blocks waiting for
+//     the staging blocks and then binning the staged remote synapses too; the
+//     queues pass between the blocks through device-coherent loads and
+//     stores (the sc1 form of global access, which goes past the
+//     non-coherent per-XCD L2 caches), since a device-scope release and
+//     acquire per block would write back or invalidate a whole L2 each time.
+// The step-by-step entry points use one kernel per job instead
+// (k_update<false>, k_route_two_level, k_expand, k_recv_stage, k_deliver).
 //
 // Global atomics run at roughly 20 G/s on random addresses and serialise on
 // hot counters, so every scatter goes through LDS first: reservations are one
@@ -107,6 +109,22 @@ __device__ __forceinline__ float load_weight(const KParams& p, uint64_t e) {
   }
 }
 
+// Device-coherent access for data handed between blocks of one launch: the
+// access goes to the coherence point instead of a possibly stale line of the
+// XCD's own L2, so no cache-wide write-back or invalidation is needed.
+__device__ __forceinline__ void store_coherent(uint64_t* a, uint64_t v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent(uint32_t* a, uint32_t v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_coherent(const uint64_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_coherent(const uint32_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Adds the block's sum of two per-thread counters into two global u64s with
 // one atomic each per block (atomics on one address serialise, so a block
 // sums first).  Every thread of the block calls it; s_red holds 2 * waves.
@@ -183,10 +201,11 @@ __device__ __forceinline__ float dequantize_w(const KParams& p, int32_t q) {
   return static_cast<float>(static_cast<double>(q) * p.wq_inv);
 }
 
-// An event that does not fit its bin goes to the dense ring; the tile is
-// flagged so the update kernel reads that slice of the ring.
+// An event that does not fit its bin goes to the dense overflow ring, which
+// holds fixed-point sums (integer atomics: exact in any order, like the
+// update's own sums); the tile is flagged so the update reads that slice.
 __device__ void ring_fallback(const KParams& p, uint32_t slot, uint32_t tgt, int32_t wq) {
-  unsafeAtomicAdd(p.ring + slot * p.ring_stride + tgt, dequantize_w(p, wq));
+  atomicAdd(p.ovf + slot * p.ring_stride + tgt, wq);
   p.dirty[slot * p.n_tiles + (tgt >> TILE_SHIFT)] = 1u;
   atomicAdd(reinterpret_cast<unsigned long long*>(&p.st->ring_events), 1ull);
 }
@@ -543,7 +562,11 @@ constexpr size_t UPDATE_BIG_LDS = TILE * sizeof(int32_t) + POIS_LUT_SIZE;
 static_assert(route_lds_bytes(UPDATE_THREADS, FUSED_ROUTE_WINDOW, FUSED_MAX_NODES, false) <=
                   UPDATE_BIG_LDS,
               "the fused routing's arrays fit the update's LDS");
-template <bool ROUTE>
+// PERSIST: a grid smaller than the launch's tiles, whose blocks take further
+// tiles by ticket (a separate instantiation: the loop carried across tiles
+// costs registers, 106 VGPRs against 73, so two blocks per CU instead of
+// three).
+template <bool ROUTE, bool PERSIST>
 __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   constexpr int NQ = UPDATE_NPT / 4;
   constexpr int NW = UPDATE_THREADS / 64;
@@ -602,6 +625,11 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     const uint32_t next_srow = srow + 1 == p.log_steps + 1 ? 0u : srow + 1;
     if (tid < STAT_ROW_WORDS) p.stats[static_cast<uint64_t>(next_srow) * STAT_ROW_WORDS + tid] = 0;
   }
+  // the tile's sub-bin counts (one coalesced load), issued first so that
+  // their latency overlaps the set-up below
+  const uint32_t md = p.D - 1;
+  const uint32_t n_sub = md * DELIVER_BLOCKS;
+  const uint32_t bc_raw = tid < n_sub ? p.bin_cnt[subbin(p, slot, tile, 1, 0) + tid] : 0u;
   for (uint32_t i = tid; i < TILE; i += UPDATE_THREADS) s_acc[i] = 0;
   if (tid == 0) s_dirty = p.dirty[slot * p.n_tiles + tile];
   for (uint32_t i = tid; i < POIS_LUT_SIZE / 16; i += UPDATE_THREADS)
@@ -644,10 +672,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   // A lane without an event re-reads event 0 of the tile's first sub-bin (a
   // valid address) and skips the add, so the loads carry no branch and issue
   // together.  Events past ARRIVE_LANES in a sub-bin (rare) take a second loop.
-  const uint32_t md = p.D - 1;
-  const uint32_t n_sub = md * DELIVER_BLOCKS;
-  if (tid < n_sub)
-    s_bcnt[tid] = min(p.bin_cnt[subbin(p, slot, tile, 1, 0) + tid], static_cast<uint32_t>(p.bin_cap));
+  if (tid < n_sub) s_bcnt[tid] = min(bc_raw, static_cast<uint32_t>(p.bin_cap));
   __syncthreads();
   // sub-bin dw of this tile starts at ev0 + dw * sub_stride
   const Event* ev0 = p.bins + bin_data(p, slot, tile, 0);
@@ -691,9 +716,10 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     }
     __syncthreads();
   }
-  // events that did not fit their bins are in this tile's slice of the ring
-  // slot; a flagged tile reads (and clears) it with the neuron state
-  float* ring_slot = p.ring + static_cast<uint64_t>(slot) * p.ring_stride;
+  // events that did not fit their bins are in this tile's slice of the
+  // overflow ring slot; a flagged tile adds (and clears) it with the neuron
+  // state, before the sum is rounded
+  int32_t* ovf_slot = p.ovf + static_cast<uint64_t>(slot) * p.ring_stride;
   const bool dirty = s_dirty != 0;
   // (cleared by the launch that holds the tile's last neuron)
   if (dirty && tid == 0 && min(blk0 + TILE, p.N) <= p.hi) p.dirty[slot * p.n_tiles + tile] = 0u;
@@ -718,24 +744,24 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (p.forced) rnd2 = philox4x32_10(i0 >> 2, t32, STREAM_RASTER, 0u, p.seed_lo, p.seed_hi);
     const uint32_t r1[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
     const uint32_t r2[4] = {rnd2.x, rnd2.y, rnd2.z, rnd2.w};
-    // arriving input: the exact fixed-point sum rounded once to binary32
-    // (rounding the integer and then scaling by the power of two 2^-F gives
-    // the same value: the scaling is exact), plus the ring slice of a
-    // flagged tile
+    // arriving input: the exact fixed-point sum (bins, plus the overflow
+    // ring slice of a flagged tile) rounded once to binary32 (rounding the
+    // integer and then scaling by the power of two 2^-F gives the same
+    // value: the scaling is exact)
     const int4 acc4 = *reinterpret_cast<const int4*>(&s_acc[l0]);
-    const int32_t acc[4] = {acc4.x, acc4.y, acc4.z, acc4.w};
-    const float wq_inv = static_cast<float>(p.wq_inv);
-    float syn[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) syn[k] = __fmul_rn(static_cast<float>(acc[k]), wq_inv);
+    int32_t acc[4] = {acc4.x, acc4.y, acc4.z, acc4.w};
     if (dirty) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (i0 + k >= p.lo && i0 + k < p.hi) {
-          syn[k] = __fadd_rn(syn[k], ring_slot[i0 + k]);
-          ring_slot[i0 + k] = 0.f;
+          acc[k] += ovf_slot[i0 + k];
+          ovf_slot[i0 + k] = 0;
         }
     }
+    const float wq_inv = static_cast<float>(p.wq_inv);
+    float syn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) syn[k] = __fmul_rn(static_cast<float>(acc[k]), wq_inv);
     float uu[4] = {u4.x, u4.y, u4.z, u4.w};
     uint32_t rf[4];
 #pragma unroll
@@ -884,7 +910,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
       w->t = w->t + 1;
     }
   }
-  if (gridDim.x >= p.tile_end - p.tile0) break;    // one tile per block
+  if constexpr (!PERSIST) break;                    // one tile per block
   __syncthreads();
   if (tid == 0) s_tile = p.tile0 + gridDim.x + atomicAdd(p.tickets + (t32 & 1u), 1u);
   __syncthreads();
@@ -991,6 +1017,7 @@ struct StageCtx {
   uint64_t* s_seg;     // [RECV_BATCH] second synapse of each entry's segment
   uint32_t* s_epre;    // [RECV_BATCH] remaining synapses: starts in the concatenation
   uint32_t* s_wsum;    // [RECV_THREADS / 64]
+  bool coherent;       // the queues are read by other blocks of the same launch
 };
 
 // One synapse (tgt_delay, weight) into the queue of its delay (position from
@@ -1006,7 +1033,12 @@ __device__ __forceinline__ void stage_emit(const KParams& p, const StageCtx& c, 
   const Event ev{td & 0x07FFFFFFu, quantize_w(p, w)};
   const uint32_t pos = atomicAdd(&c.l_pos[d1], 1u);
   if (pos < p.stage_cap) {
-    c.queue[d1 * c.qstride + pos] = ev;
+    Event* q = c.queue + d1 * c.qstride + pos;
+    if (c.coherent)
+      store_coherent(reinterpret_cast<uint64_t*>(q),
+                     ev.tgt | (static_cast<uint64_t>(static_cast<uint32_t>(ev.wq)) << 32));
+    else
+      *q = ev;
   } else {
     uint32_t slot = c.slot0 + d1 + 1;
     if (slot >= p.D) slot -= p.D;
@@ -1117,7 +1149,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
   __syncthreads();
   const StageCtx ctx{p.stage + static_cast<uint64_t>(b) * p.stage_cap,
                      static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap, p.st->cur_slot, l_pos,
-                     s_seg, s_epre, s_wsum};
+                     s_seg, s_epre, s_wsum, false};
   uint64_t events = 0;
   for (uint32_t b0 = 0; b0 < n_ent; b0 += RECV_BATCH) {
     const uint32_t nb = min(n_ent - b0, RECV_BATCH);
@@ -1170,7 +1202,7 @@ __device__ __forceinline__ uint32_t split_of(const KParams& p, uint32_t nblocks)
   return p.recv_split ? min(s, p.recv_split) : s;
 }
 
-template <bool BF16, bool STAGE, bool WIDE>
+template <bool BF16, bool STAGE, bool WIDE, bool COHERENT>
 __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblocks, uint64_t* dyn) {
   using MaskT = std::conditional_t<WIDE, uint64_t, uint32_t>;
   constexpr uint32_t NW = RECV_THREADS / 64;
@@ -1197,7 +1229,7 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
   if (tid < SNN_MAX_DELAY) l_pos[tid] = 0;
   const StageCtx ctx{p.stage + static_cast<uint64_t>(b) * p.stage_cap,
                      static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap, p.st->cur_slot, l_pos,
-                     s_seg, s_epre, s_wsum};
+                     s_seg, s_epre, s_wsum, COHERENT};
   uint64_t events = 0, entries = 0;
   // stages the n buffered entries (uniform n)
   auto stage_buffer = [&](uint32_t n) {
@@ -1217,14 +1249,20 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
   const bool shared = S > 1;
   const uint32_t n_step = shared ? p.n_nodes : nblocks;   // shared: one node per block
   uint32_t n_buf = 0;   // entries in the buffer (uniform)
-  for (uint32_t n = b / S; n < p.n_nodes; n += n_step) {
+  // block-uniform values are kept in scalar registers (readfirstlane): held
+  // across the round loop in vector registers they would be spilled
+  auto uni = [](uint32_t v) { return __builtin_amdgcn_readfirstlane(v); };
+  const uint32_t node0 = uni(b / S), part = uni(b - node0 * S);
+  for (uint32_t n = node0; n < p.n_nodes; n += n_step) {
     const uint64_t off = p.bucket_off[n];
-    const uint32_t cnt_n = static_cast<uint32_t>(
-        min(static_cast<uint64_t>(bcnt[n * CNT_STRIDE]), p.bucket_off[n + 1] - off));
-    const uint32_t part = b % S;
-    const uint32_t m_lo = static_cast<uint32_t>(static_cast<uint64_t>(cnt_n) * part / S);
-    const uint32_t cnt = static_cast<uint32_t>(static_cast<uint64_t>(cnt_n) * (part + 1) / S);
-    const uint32_t gn = min(p.G, p.P - p.G * n);             // partitions of this node
+    const uint32_t cnt_n = uni(static_cast<uint32_t>(
+        min(static_cast<uint64_t>(bcnt[n * CNT_STRIDE]), p.bucket_off[n + 1] - off)));
+    // this block's share of the node's messages [m_lo, cnt): S near-equal
+    // parts (32-bit arithmetic only: a 64-bit division here spills registers)
+    const uint32_t q = uni(cnt_n / S), r = uni(cnt_n - q * S);
+    const uint32_t m_lo = uni(q * part + min(part, r));
+    const uint32_t cnt = uni(m_lo + q + (part < r ? 1u : 0u));
+    const uint32_t gn = uni(min(p.G, p.P - p.G * n));        // partitions of this node
     const MaskT valid = gn == 8 * sizeof(MaskT) ? ~MaskT(0) : (MaskT(1) << gn) - 1;
     __syncthreads();   // the previous node is done with l_run, l_off
     if (tid < NG) l_run[tid] = 0;
@@ -1318,9 +1356,11 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
     if (!shared && tid < gn) p.recv_cnt[(p.G * n + tid) * CNT_STRIDE] = l_run[tid];
   }
   stage_buffer(n_buf);
-  if (STAGE && tid < md)
-    p.stage_cnt[tid * STAGE_BLOCKS + b] =
-        static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
+  if (STAGE && tid < md) {
+    const uint32_t c = static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
+    if (COHERENT) store_coherent(p.stage_cnt + tid * STAGE_BLOCKS + b, c);
+    else p.stage_cnt[tid * STAGE_BLOCKS + b] = c;
+  }
   uint64_t* sc = stat_copy(p, row);
   add_stats(sc + SNN_STAT_REMOTE_EVENTS, events, sc + SNN_STAT_RECV_ENTRIES, entries, s_red);
 }
@@ -1328,8 +1368,8 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
 // Mask expansion alone (the step-by-step path): expansion blocks over the
 // nodes, the receive lists as output.
 __global__ __launch_bounds__(RECV_THREADS) void k_expand(KParams p) {
-  if (p.G > NARROW_G) expand_stage_block<false, false, true>(p, blockIdx.x, gridDim.x, nullptr);
-  else expand_stage_block<false, false, false>(p, blockIdx.x, gridDim.x, nullptr);
+  if (p.G > NARROW_G) expand_stage_block<false, false, true, false>(p, blockIdx.x, gridDim.x, nullptr);
+  else expand_stage_block<false, false, false, false>(p, blockIdx.x, gridDim.x, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1352,13 +1392,62 @@ __global__ __launch_bounds__(RECV_THREADS) void k_expand(KParams p) {
 // are placed in tile order in LDS (8 bytes each), and consecutive threads
 // then write consecutive positions of one sub-bin.
 // PART: DELIVER_ALL takes the queues after the sources (one kernel per row,
-// the queues complete at launch); DELIVER_LOCAL takes the sources only (beside
-// the receive side, which is still filling the queues) and DELIVER_REMOTE the
-// queues only, appended after the counts DELIVER_LOCAL published.
+// the queues complete at launch); DELIVER_LOCAL takes the sources only
+// (beside the staging, which is still filling the queues) and
+// DELIVER_REMOTE the queues only, appended after the counts DELIVER_LOCAL
+// published; DELIVER_SPLIT takes the sources, waits for every staging block
+// of the same launch to have published its queues (wait_staged), then takes
+// the queues with device-coherent loads, appending to the same runs.
 // dyn holds deliver_lds_bytes(n_tiles) bytes.
-enum DeliverPart { DELIVER_ALL, DELIVER_LOCAL, DELIVER_REMOTE };
+enum DeliverPart { DELIVER_ALL, DELIVER_LOCAL, DELIVER_REMOTE, DELIVER_SPLIT };
 constexpr uint32_t DELIVER_ROUND = GATHER_UNROLL * DELIVER_THREADS;
 static_assert(DELIVER_ROUND <= 65536, "window positions fit 16 bits");
+
+// Polls of a wait between blocks of one launch before it gives up with
+// ERR_TIMEOUT (each poll sleeps about 128 cycles): every wait ends.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+// Called by every thread of a staging block once its queues and their
+// counts are stored (device-coherently): waits for its own stores to
+// complete, then the block counts itself in.
+__device__ void signal_staged(const KParams& p) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(p.sync + SYNC_STAGED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until all STAGE_BLOCKS staging blocks of this launch are counted in.
+// Every thread calls it.
+__device__ void wait_staged(const KParams& p) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(p.sync + SYNC_STAGED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           STAGE_BLOCKS) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins == SPIN_LIMIT) {
+        atomicOr(&p.st->error, ERR_TIMEOUT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Called by every thread of a delivery block of the combined launch when it
+// is done; the last of the n_deliver blocks clears the launch's counters for
+// the next launch (the launch boundary makes that visible to it).
+__device__ void retire_deliver(const KParams& p, uint32_t n_deliver) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old =
+        __hip_atomic_fetch_add(p.sync + SYNC_RETIRED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == n_deliver - 1) {
+      __hip_atomic_store(p.sync + SYNC_STAGED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p.sync + SYNC_RETIRED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
 
 template <DeliverPart PART, bool BF16>
 __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t* dyn) {
@@ -1381,6 +1470,7 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
   if (slot >= p.D) slot -= p.D;
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t D = p.D;
+  constexpr bool COHERENT = PART == DELIVER_SPLIT;   // queues staged by this launch
   constexpr bool LOCAL = PART != DELIVER_REMOTE;
   constexpr bool REMOTE = PART != DELIVER_LOCAL;
   for (uint32_t i = tid; i < p.n_tiles; i += NT) {
@@ -1458,9 +1548,15 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
         const uint32_t k = owner_of<NT / 2>(s_pre, nseg, e);
         const uint64_t x = s_base[k] + (e - s_pre[k]);
         if constexpr (QUEUE) {
-          const Event ev = q0[x];
-          tg[v] = ev.tgt;
-          wq[v] = ev.wq;
+          if constexpr (COHERENT) {
+            const uint64_t ev = load_coherent(reinterpret_cast<const uint64_t*>(q0 + x));
+            tg[v] = static_cast<uint32_t>(ev);
+            wq[v] = static_cast<int32_t>(static_cast<uint32_t>(ev >> 32));
+          } else {
+            const Event ev = q0[x];
+            tg[v] = ev.tgt;
+            wq[v] = ev.wq;
+          }
         } else {
           tg[v] = p.tgt_delay[x] & 0x07FFFFFFu;
           wq[v] = quantize_w(p, load_weight<BF16>(p, x));
@@ -1487,12 +1583,14 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
     }
     take_runs(nsrc, len, std::false_type{});
   }
+  if constexpr (COHERENT) wait_staged(p);
   // the staged remote synapses of delay d: queues w, w + DELIVER_BLOCKS, ...
   if constexpr (REMOTE) {
     uint32_t len = 0;
     if (tid < QPB) {
       s_base[tid] = static_cast<uint64_t>(tid) * DELIVER_BLOCKS * p.stage_cap;
-      len = p.stage_cnt[(d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS];
+      const uint32_t* c = p.stage_cnt + (d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS;
+      len = COHERENT ? load_coherent(c) : *c;
     }
     take_runs(QPB, len, std::true_type{});
   }
@@ -1518,55 +1616,77 @@ __global__ __launch_bounds__(DELIVER_THREADS) void k_deliver_remote(KParams p) {
   deliver_block<DELIVER_REMOTE, BF16>(p, blockIdx.x, blockIdx.y + 1, lds_u64);
 }
 
-// Two independent jobs in one launch, so that they overlap: blocks
-// [0, STAGE_BLOCKS) expand and stage the two-level messages
-// (expand_stage_block), the rest deliver the fired sources' local synapses
-// (deliver_block, local part; block STAGE_BLOCKS + i takes (w, d) =
-// (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)).  The local part needs only
-// the fired list, not the receive side.  Three blocks of 8 waves per CU (6
-// waves per SIMD, at most 80 VGPRs), so that all blocks of both jobs are
-// resident at once.
-static_assert(RECV_THREADS == DELIVER_THREADS, "one block size for both jobs");
+// Expansion and staging beside the own-partition delivery: two independent
+// jobs in one launch, so that they overlap (block layout as k_recv_deliver);
+// the staged queues are binned by k_deliver_remote after it.
 template <bool BF16, bool WIDE>
 __global__ __launch_bounds__(RECV_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
 void k_recv_local(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   if (blockIdx.x < STAGE_BLOCKS) {
-    expand_stage_block<BF16, true, WIDE>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
+    expand_stage_block<BF16, true, WIDE, false>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
   } else {
     const uint32_t i = blockIdx.x - STAGE_BLOCKS;
     deliver_block<DELIVER_LOCAL, BF16>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
   }
 }
 
-// Moves every pending binned event into the dense ring (for read-back) and
-// empties those bins.  Grid: x = tile, y = slot.  Bins are not cleared when
-// consumed, so only some are pending: slot s is consumed k steps from now
+// The receive side and the delivery of a step in one launch: blocks
+// [0, STAGE_BLOCKS) expand and stage the two-level messages
+// (expand_stage_block) and count themselves in when their queues are
+// stored; the rest (block STAGE_BLOCKS + i takes (w, d) =
+// (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)) deliver the fired sources'
+// local synapses meanwhile (they need only the fired list), wait for the
+// staging blocks, and bin the staged remote synapses.  Only higher-numbered
+// blocks wait, for lower-numbered ones, which are dispatched first.  Three
+// blocks of 8 waves per CU (6 waves per SIMD, at most 80 VGPRs).
+static_assert(RECV_THREADS == DELIVER_THREADS, "one block size for both jobs");
+template <bool BF16, bool WIDE>
+__global__ __launch_bounds__(RECV_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
+void k_recv_deliver(KParams p) {
+  extern __shared__ uint64_t lds_u64[];
+  if (blockIdx.x < STAGE_BLOCKS) {
+    expand_stage_block<BF16, true, WIDE, true>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
+    signal_staged(p);
+  } else {
+    const uint32_t i = blockIdx.x - STAGE_BLOCKS;
+    deliver_block<DELIVER_SPLIT, BF16>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
+    retire_deliver(p, gridDim.x - STAGE_BLOCKS);
+  }
+}
+
+// Writes the input scheduled for the coming steps into the dense ring p.ring
+// (binary32, slot-major): for every slot and neuron, the pending fixed-point
+// events of its bins plus its overflow-ring sum, rounded as the update will
+// round them.  Nothing is moved or cleared, so the simulation continues
+// unchanged.  Grid: x = tile, y = slot.  Bins are not cleared when consumed,
+// so only some are pending: slot s is consumed k steps from now
 // (k = (s - next slot) mod D), and its bin of delay d has been written for
 // that step only if d > k (it is written at step s - d); the others still
 // hold input already consumed.
 __global__ __launch_bounds__(256) void k_flush(KParams p) {
+  __shared__ int32_t s_acc[TILE];
   const uint32_t tile = blockIdx.x, slot = blockIdx.y;
   const uint32_t next = p.st->slot;
   const uint32_t ahead = slot >= next ? slot - next : slot + p.D - next;
   const uint32_t md = p.D - 1;
-  __shared__ uint32_t any;
-  if (threadIdx.x == 0) any = 0;
+  const uint32_t blk0 = tile << TILE_SHIFT;
+  const uint32_t nt = min(TILE, p.N - blk0);
+  const uint64_t row = static_cast<uint64_t>(slot) * p.ring_stride + blk0;
+  for (uint32_t i = threadIdx.x; i < TILE; i += 256) s_acc[i] = i < nt ? p.ovf[row + i] : 0;
   __syncthreads();
   for (uint32_t d = ahead + 1; d <= md; ++d) {
     for (uint32_t w = 0; w < DELIVER_BLOCKS; ++w) {
-      const uint64_t sb = subbin(p, slot, tile, d, w);
-      const uint32_t c = min(p.bin_cnt[sb], static_cast<uint32_t>(p.bin_cap));
+      const uint32_t c = min(p.bin_cnt[subbin(p, slot, tile, d, w)],
+                             static_cast<uint32_t>(p.bin_cap));
       const Event* ev = p.bins + bin_data(p, slot, tile, (d - 1) * DELIVER_BLOCKS + w);
-      for (uint32_t e = threadIdx.x; e < c; e += 256)
-        unsafeAtomicAdd(p.ring + slot * p.ring_stride + (tile << TILE_SHIFT) + ev[e].tgt,
-                        dequantize_w(p, ev[e].wq));
-      if (c && threadIdx.x == 0) any = 1;
-      __syncthreads();
-      if (threadIdx.x == 0) p.bin_cnt[sb] = 0;
+      for (uint32_t e = threadIdx.x; e < c; e += 256) atomicAdd(&s_acc[ev[e].tgt], ev[e].wq);
     }
   }
-  if (threadIdx.x == 0 && any) p.dirty[slot * p.n_tiles + tile] = 1u;
+  __syncthreads();
+  const float wq_inv = static_cast<float>(p.wq_inv);
+  for (uint32_t i = threadIdx.x; i < nt; i += 256)
+    p.ring[row + i] = __fmul_rn(static_cast<float>(s_acc[i]), wq_inv);
 }
 
 // Set-up kernels of the allocation-free entry point (snn_create_static),
@@ -1614,12 +1734,13 @@ bool fused_route_ok(const KParams& p) { return p.n_nodes <= FUSED_MAX_NODES && p
 hipError_t launch_update(const KParams& p, hipStream_t s, hipEvent_t* marks, bool route) {
   mark(marks, SNN_KERNEL_UPDATE, 0, s);
   const uint32_t tiles = p.tile_end - p.tile0;
-  const uint32_t grid = p.update_blocks && p.tile0 == 0 && p.tile_end == p.n_tiles
-                            ? std::min(p.update_blocks, tiles) : tiles;
-  if (route && fused_route_ok(p))
-    hipLaunchKernelGGL(k_update<true>, dim3(grid), dim3(UPDATE_THREADS), 0, s, p);
-  else
-    hipLaunchKernelGGL(k_update<false>, dim3(grid), dim3(UPDATE_THREADS), 0, s, p);
+  const bool persist = p.update_blocks && p.update_blocks < tiles && p.tile0 == 0 &&
+                       p.tile_end == p.n_tiles;
+  const uint32_t grid = persist ? p.update_blocks : tiles;
+  const bool r = route && fused_route_ok(p);
+  void (*kern)(KParams) = persist ? (r ? k_update<true, true> : k_update<false, true>)
+                                  : (r ? k_update<true, false> : k_update<false, false>);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(UPDATE_THREADS), 0, s, p);
   mark(marks, SNN_KERNEL_UPDATE, 1, s);
   return hipGetLastError();
 }
@@ -1667,7 +1788,7 @@ static size_t deliver_lds_bytes(uint32_t n_tiles) {
 constexpr size_t EXPAND_STAGE_LDS =
     EXPAND_BUF * sizeof(uint64_t) + RECV_BATCH * (sizeof(uint64_t) + sizeof(uint32_t));
 
-static size_t recv_local_lds_bytes(const KParams& p) {
+static size_t recv_deliver_lds_bytes(const KParams& p) {
   return std::max(EXPAND_STAGE_LDS, deliver_lds_bytes(p.n_tiles));
 }
 
@@ -1675,11 +1796,17 @@ template <bool BF16>
 static void launch_deliver_t(const KParams& p, int mode, hipStream_t s, hipEvent_t* marks,
                              bool fused_expand) {
   if (fused_expand && mode != SNN_ROUTE_FLAT) {
+    const dim3 grid(STAGE_BLOCKS + DELIVER_BLOCKS * (p.D - 1));
     mark(marks, SNN_KERNEL_RECV_STAGE, 0, s);
-    void (*kern)(KParams) =
-        p.G > NARROW_G ? k_recv_local<BF16, true> : k_recv_local<BF16, false>;
-    hipLaunchKernelGGL(kern, dim3(STAGE_BLOCKS + DELIVER_BLOCKS * (p.D - 1)), dim3(RECV_THREADS),
-                       recv_local_lds_bytes(p), s, p);
+    if (p.recv_merged) {
+      void (*kern)(KParams) =
+          p.G > NARROW_G ? k_recv_deliver<BF16, true> : k_recv_deliver<BF16, false>;
+      hipLaunchKernelGGL(kern, grid, dim3(RECV_THREADS), recv_deliver_lds_bytes(p), s, p);
+      mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
+      return;
+    }
+    void (*kern)(KParams) = p.G > NARROW_G ? k_recv_local<BF16, true> : k_recv_local<BF16, false>;
+    hipLaunchKernelGGL(kern, grid, dim3(RECV_THREADS), recv_deliver_lds_bytes(p), s, p);
     mark(marks, SNN_KERNEL_RECV_STAGE, 1, s);
     mark(marks, SNN_KERNEL_DELIVER, 0, s);
     hipLaunchKernelGGL(k_deliver_remote<BF16>, dim3(DELIVER_BLOCKS, p.D - 1),
@@ -1719,7 +1846,7 @@ hipError_t prepare_kernels(KParams& p) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
   // the deliver kernels' per-tile counters must leave room for a round
-  const size_t dl = deliver_lds_bytes(p.n_tiles), rl = recv_local_lds_bytes(p);
+  const size_t dl = deliver_lds_bytes(p.n_tiles), rl = recv_deliver_lds_bytes(p);
   const std::pair<const void*, size_t> kernels[] = {
       {reinterpret_cast<const void*>(&k_deliver<false>), dl},
       {reinterpret_cast<const void*>(&k_deliver<true>), dl},
@@ -1729,6 +1856,10 @@ hipError_t prepare_kernels(KParams& p) {
       {reinterpret_cast<const void*>(&k_recv_local<true, false>), rl},
       {reinterpret_cast<const void*>(&k_recv_local<false, true>), rl},
       {reinterpret_cast<const void*>(&k_recv_local<true, true>), rl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<false, false>), rl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<true, false>), rl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<false, true>), rl},
+      {reinterpret_cast<const void*>(&k_recv_deliver<true, true>), rl},
       {reinterpret_cast<const void*>(&k_route_two_level<false>), route_kernel_lds_bytes(p)},
       {reinterpret_cast<const void*>(&k_route_two_level<true>), route_kernel_lds_bytes(p)},
   };

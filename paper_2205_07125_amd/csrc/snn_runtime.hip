@@ -51,7 +51,7 @@ uint32_t n_nodes_of(const snn_params* p) {
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  uint64_t st, tickets, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat,
+  uint64_t st, tickets, sync, ovf, lookback, fired, bucket_cnt, bucket, recv_cnt, recv, flat_cnt, flat,
       stage_cnt, stage, bin_cnt, dirty, bins, stats, pois_lut, log_off, log, total;
 };
 
@@ -66,6 +66,8 @@ Layout layout(const snn_params* p) {
   const uint64_t D = p->max_delay + 1, md = p->max_delay, tiles = tiles_of(p->n_neurons);
   L.st = take(sizeof(DevState));
   L.tickets = take(sizeof(uint32_t) * 2);
+  L.sync = take(sizeof(uint32_t) * SYNC_WORDS);
+  L.ovf = take(sizeof(int32_t) * D * snn_ring_stride(p->n_neurons));
   L.lookback = take(sizeof(uint64_t) * tiles);
   L.fired = take(sizeof(uint32_t) * uint64_t(p->n_neurons));
   L.bucket_cnt = take(2 * sizeof(uint32_t) * CNT_STRIDE * n_nodes_of(p));
@@ -279,6 +281,8 @@ snn_status init_ctx(snn_ctx* c, const snn_params* params, const snn_network_dev*
   k.st = reinterpret_cast<DevState*>(ws + L.st);
   k.lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   k.tickets = reinterpret_cast<uint32_t*>(ws + L.tickets);
+  k.sync = reinterpret_cast<uint32_t*>(ws + L.sync);
+  k.ovf = reinterpret_cast<int32_t*>(ws + L.ovf);
   k.fired = reinterpret_cast<uint32_t*>(ws + L.fired);
   k.bucket_cnt = reinterpret_cast<uint32_t*>(ws + L.bucket_cnt);
   k.bucket = reinterpret_cast<uint64_t*>(ws + L.bucket);
@@ -604,11 +608,14 @@ snn_status snn_set_tuning(snn_handle h, const snn_tuning* t) {
     return fail(SNN_ERR_INVALID_ARG, "update_blocks %u > %u tiles", t->update_blocks, h->kp.n_tiles);
   if (t->recv_split > STAGE_BLOCKS)
     return fail(SNN_ERR_INVALID_ARG, "recv_split %u > %u", t->recv_split, STAGE_BLOCKS);
-  if (h->kp.update_blocks != t->update_blocks || h->kp.recv_split != t->recv_split) {
+  if (t->recv_merged > 1) return fail(SNN_ERR_INVALID_ARG, "recv_merged %u", t->recv_merged);
+  if (h->kp.update_blocks != t->update_blocks || h->kp.recv_split != t->recv_split ||
+      h->kp.recv_merged != t->recv_merged) {
     HIP_TRY(hipStreamSynchronize(h->stream));
     drop_graphs(h);
     h->kp.update_blocks = t->update_blocks;
     h->kp.recv_split = t->recv_split;
+    h->kp.recv_merged = t->recv_merged;
   }
   return SNN_OK;
 }
@@ -617,6 +624,7 @@ snn_status snn_get_tuning(snn_handle h, snn_tuning* t) {
   if (!h || !t) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
   t->update_blocks = h->kp.update_blocks;
   t->recv_split = h->kp.recv_split;
+  t->recv_merged = h->kp.recv_merged;
   return SNN_OK;
 }
 
@@ -631,13 +639,14 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
   // the launches queue up behind each other as in a normal run, so no start
   // event fires on an idle queue ahead of its kernel.
   const bool fused = mode != SNN_ROUTE_FLAT && fused_route_ok(h->kp);
-  // expansion and staging of a two-level step share the receive-side launch
+  // expansion and staging of a two-level step share the receive-side launch,
+  // and so does the remote delivery when that side is one launch
   const bool launched[SNN_NKERNEL] = {true,
                                       mode != SNN_ROUTE_FLAT && !fused,
                                       false,
                                       mode != SNN_ROUTE_TWO_LEVEL,
                                       true,
-                                      true};
+                                      mode == SNN_ROUTE_FLAT || !h->kp.recv_merged};
   std::vector<hipEvent_t> marks(size_t(2) * SNN_NKERNEL * n_steps, nullptr);
   snn_status st = SNN_OK;
   for (auto& e : marks) {
@@ -691,6 +700,8 @@ static snn_status sync_and_check(snn_handle h, DevState* out) {
   if (out) *out = st;
   if (st.error & ERR_ROUTE)
     return fail(SNN_ERR_HIP, "receive entry without a matching destination partition");
+  if (st.error & ERR_TIMEOUT)
+    return fail(SNN_ERR_HIP, "a wait between blocks of one launch timed out");
   if (st.error)
     return fail(SNN_ERR_CAPACITY, "device capacity overflow (bits 0x%x: 1 bucket, 2 receive "
                 "list, 4 flat list, 8 spike log)", st.error);

@@ -141,8 +141,8 @@ class Simulation:
             starts[0] = 0
         _abi.snn_run_partitioned(self.h, n_steps, mode, use_graph, starts)
 
-    def set_tuning(self, update_blocks: int = 0, recv_split: int = 0):
-        _abi.snn_set_tuning(self.h, update_blocks, recv_split)
+    def set_tuning(self, update_blocks: int = 0, recv_split: int = 0, recv_merged: int = 0):
+        _abi.snn_set_tuning(self.h, update_blocks, recv_split, recv_merged)
 
     def tuning(self) -> dict:
         return _abi.snn_get_tuning(self.h)
@@ -226,9 +226,9 @@ class Simulation:
         return self.u.cpu().numpy()
 
     def state(self) -> dict:
-        """u, ref and the ring (D x N) as host arrays.  Pending binned events
-        are first moved into the ring (snn_flush), so the ring holds all input
-        scheduled for the coming steps."""
+        """u, ref and the ring (D x N) as host arrays: snn_flush writes the
+        input scheduled for the coming steps into the ring first (reading
+        only; later steps are unchanged)."""
         self.flush()
         self.sync()
         D, N = self.wl.max_delay + 1, self.wl.n_neurons

@@ -100,11 +100,14 @@ def test_empty_steps():
     assert all(len(x) == 0 for x in sim.read_routes(1))
 
 
+@pytest.mark.parametrize("jitter", [0.0, 0.2])
 @pytest.mark.parametrize("bin_cap,stage_cap", [(0, 0), (2, 1)])
-def test_dense_ring_fallback_is_exact(bin_cap, stage_cap):
+def test_dense_ring_fallback_is_exact(bin_cap, stage_cap, jitter):
     """With no (or tiny) bin and staging capacity every event takes the dense
-    ring path; the result is the same as with the bins."""
-    wl = synth.get_workload("tiny_active")
+    overflow path; the result is the same as with the bins, bit for bit, also
+    with non-dyadic (jittered) weights: both paths sum the same fixed-point
+    weights exactly."""
+    wl = synth.get_workload("tiny_active").replace(w_jitter=jitter)
     a = Simulation(wl, log_steps=150)
     b = Simulation(wl, log_steps=150, bin_cap=bin_cap, stage_cap=stage_cap)
     a.run(150, _abi.SNN_ROUTE_TWO_LEVEL, use_graph=False)
@@ -116,3 +119,22 @@ def test_dense_ring_fallback_is_exact(bin_cap, stage_cap):
     ia, _ = a.read_spikes(0, 150)
     ib, _ = b.read_spikes(0, 150)
     assert np.array_equal(ia, ib)
+
+
+def test_state_reads_leave_the_run_unchanged():
+    """Reading the state (snn_flush) between steps only reads: with jittered
+    (non-dyadic) weights a run read every 7 steps equals one never read."""
+    wl = synth.get_workload("tiny_active").replace(w_jitter=0.2)
+    a = Simulation(wl, log_steps=120)
+    b = Simulation(wl, log_steps=120)
+    for t in range(120):
+        a.full_step(_abi.SNN_ROUTE_TWO_LEVEL)
+        b.full_step(_abi.SNN_ROUTE_TWO_LEVEL)
+        if t % 7 == 3:
+            a.state()
+    ia, ca = a.read_spikes(0, 120)
+    ib, cb = b.read_spikes(0, 120)
+    assert ca.sum() > 0 and np.array_equal(ca, cb) and np.array_equal(ia, ib)
+    sa, sb = a.state(), b.state()
+    for k in ("u", "ref", "ring"):
+        assert np.array_equal(sa[k].view(np.uint8), sb[k].view(np.uint8)), k

@@ -6,7 +6,7 @@ batched form chooses between give identical results.
 * persistent update blocks (fewer blocks than tiles, tiles taken in turn)
   against one block per tile;
 * the receive side with several blocks sharing one destination node's
-  messages against one block per node;
+  messages against one block per node, and as one launch against two;
 * one HIP graph of all steps against 16-step graphs and eager launches;
 
 and the per-partition layout against the oracle.  Routing buffers are
@@ -113,6 +113,43 @@ def test_recv_split_matches(name, split):
     a.run(n, TWO_LEVEL, use_graph=False)
     b.run(n, TWO_LEVEL, use_graph=False)
     _same(a, b, wl, n, f"recv_split {split}")
+
+
+@pytest.mark.parametrize("name", ["tiny_active", "batched", "paper_share"])
+def test_recv_merged_matches(name):
+    """The receive side as one launch (delivery blocks wait for the staging
+    blocks and read their queues device-coherently) against two launches."""
+    wl = _wl(name)
+    n = 60
+    a, b = _sims(wl, n, recv_merged=1)
+    b.set_tuning(recv_merged=1)
+    a.run(n, TWO_LEVEL, use_graph=False)
+    b.run(n, TWO_LEVEL, use_graph=True)
+    _same(a, b, wl, n, "one receive launch")
+
+
+def test_recv_merged_matches_oracle():
+    """One receive launch, step by step against the oracle (64 uneven
+    partitions, several blocks per destination node)."""
+    from paper_2205_07125_amd import HostNetwork, Simulation
+    wl = _wl("batched")
+    n = 40
+    sim = Simulation(wl, host=HostNetwork(wl), log_steps=n)
+    sim.set_tuning(recv_merged=1)
+    orc = oracle.sim_for_workload(wl)
+    fired, stats = [], np.zeros((n, 7), np.uint64)
+    for t in range(n):
+        sim.run(1, TWO_LEVEL, use_graph=False)
+        orc.step()
+        fired.append(orc.fired())
+        stats[t] = orc.counters()[STAT_MAP]
+    stats[:, 5] = 0
+    ids, counts = sim.read_spikes(0, n)
+    assert np.array_equal(ids, np.concatenate(fired).astype(np.int32))
+    assert np.array_equal(sim.read_counters(0, n), stats)
+    g, o = sim.state(), orc.state()
+    assert np.array_equal(g["u"].view(np.uint32), o["u"].view(np.uint32))
+    assert np.array_equal(g["ring"].view(np.uint32), o["ring"].view(np.uint32))
 
 
 def test_whole_run_graph():
