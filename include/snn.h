@@ -224,7 +224,11 @@ uint64_t snn_ring_stride(uint32_t n_neurons);
    bucket_total, recv_total, log_steps and log_cap. */
 snn_status snn_workspace_size(const snn_params* params, size_t* bytes);
 
-/* Validates params and array pointers, carves the workspace, zeroes its
+/* One GPU's share of the network after the model has been generated and
+   dispersed over the GPUs (the two set-up stages of Sec. I, Fig. 1), with
+   the neuron-GPU mapping of Sec. IV-A fixing which partition each neuron and
+   each synapse's target belongs to.
+   Validates params and array pointers, carves the workspace, zeroes its
    counters on `stream` and returns a handle at step t = 0.  `stream` is a
    hipStream_t (NULL = the default stream).  Does not allocate device
    memory. */
@@ -255,12 +259,16 @@ snn_status snn_create(const snn_params* params, const snn_network_dev* net,
 snn_status snn_create_static(const snn_params* params, const snn_network_dev* net, void* stream,
                              snn_handle* out);
 
-/* Neuron update, threshold and ascending compaction of fired ids for the
-   current step t (ring slot t mod D is read and cleared).  Order: must follow
+/* The computation half of a simulation step (Sec. I: data processing on the
+   GPUs; the LIF model class of Table I): neuron update, threshold and
+   ascending compaction of fired ids for the current step t (ring slot t mod D
+   is read and cleared).  Order: must follow
    snn_create or snn_deliver. */
 snn_status snn_step(snn_handle h);
 
-/* Routes the spikes of the current step (mode SNN_ROUTE_*).  Order: must
+/* Routes the spikes of the current step (mode SNN_ROUTE_*): the two-level
+   messages of Sec. IV-B (one per destination group, Fig. 2(b)), the direct
+   per-destination messages of Fig. 2(a), or both.  Order: must
    follow snn_step. */
 snn_status snn_route(snn_handle h, int mode);
 
@@ -274,8 +282,10 @@ snn_status snn_route(snn_handle h, int mode);
    Order: as snn_step; snn_deliver follows. */
 snn_status snn_step_route(snn_handle h, int mode);
 
-/* Delivers the current step's synaptic events (own partition and receive
-   lists): each is scheduled for step t + d in its tile's bin (or the ring
+/* The receiving half of the exchange (Sec. I: data exchange among GPUs; Sec.
+   IV-B: a group's messages reach each destination GPU of the group, whose
+   synapses of the source then take the spike): delivers the current step's
+   synaptic events (own partition and receive lists); each is scheduled for step t + d in its tile's bin (or the ring
    slot (t + d) mod D when the bin is full).  Order: must follow snn_route. */
 snn_status snn_deliver(snn_handle h);
 
@@ -355,7 +365,9 @@ void snn_bin_geometry(uint32_t* tile_neurons, uint32_t* deliver_blocks, uint32_t
 /* Steps completed so far (host-side count of enqueued steps). */
 uint64_t snn_time(snn_handle h);
 
-/* Fired ids of steps [first_step, first_step + n_steps), which must be among
+/* The spikes each step exchanges (Sec. I), whose counts per destination
+   make up the per-GPU traffic of Fig. 3(a) (Sec. V).
+   Fired ids of steps [first_step, first_step + n_steps), which must be among
    the last log_steps steps; ids ascending within a step, concatenated.
    per_step_counts[n_steps] (may be NULL); ids may be NULL to query *n_ids.
    Fails with SNN_ERR_CAPACITY if more than cap ids or if the spike log
@@ -382,7 +394,9 @@ snn_status snn_read_spikes(snn_handle h, uint64_t first_step, uint32_t n_steps,
 snn_status snn_read_routes(snn_handle h, int which, uint64_t* sizes, void* entries,
                            uint64_t cap, uint64_t* n_entries);
 
-/* Counters of steps [first_step, first_step + n_steps) (the last log_steps
+/* Per-step counts behind Sec. V's comparisons (spikes, events, level-1 and
+   level-2 messages against the direct messages of Fig. 4's two routings):
+   counters of steps [first_step, first_step + n_steps) (the last log_steps
    steps), out[n_steps][SNN_NSTAT].  Synchronises. */
 snn_status snn_read_counters(snn_handle h, uint64_t first_step, uint32_t n_steps,
                              uint64_t* out);

@@ -106,6 +106,32 @@ snn_status snn_setup_fill_routes(snn_setup_handle h, const uint32_t* tgt_delay,
 
 void snn_setup_destroy(snn_setup_handle h);
 
+/* Physical constants of the neuron model and its drive (the paper names only
+   the model class, LIF, in Table I; the values are the workload's). */
+typedef struct {
+  double dt_ms;         /* step length */
+  double tau_m_ms;      /* membrane time constant */
+  double theta_mv;      /* threshold relative to rest */
+  double u_reset_mv;    /* reset relative to rest */
+  double t_ref_ms;      /* refractory period */
+  double nu_ext_hz;     /* rate of the external Poisson drive per neuron */
+  double w_ext_mv;      /* jump per external event */
+  double rate_on_hz;    /* forced raster: rate in the on phase */
+  double rate_off_hz;   /* forced raster: rate in the off phase */
+} snn_model;
+
+/* Fills the constants of snn_params that the update takes ready-made, from
+   the physical ones: alpha = fl32(exp(-dt/tau_m)); theta, u_reset, w_ext as
+   binary32; n_ref = dt-steps of t_ref rounded to nearest (ties to even);
+   poisson_thr[j] = min(floor(2^32 CDF(j)), 2^32 - 1) for the Poisson law of
+   mean nu_ext dt, j = 0..14, the CDF summed in double from exp(-lambda) by
+   the recurrence pmf(j) = pmf(j-1) lambda / j; raster_thr_on/off =
+   floor(2^32 rate dt) clamped to [0, 2^32 - 1].  Leaves every other field
+   unchanged.  SNN_ERR_INVALID_ARG for NULL pointers, dt or tau_m not
+   positive, a negative rate, t_ref or lambda, or n_ref above 255.  Host
+   only; no device work. */
+snn_status snn_setup_model_params(const snn_model* m, snn_params* p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,7 +43,7 @@ EXPORTED = [
     "snn_read_spikes", "snn_read_routes",
     "snn_read_counters", "snn_destroy", "snn_last_error",
     "snn_setup_create", "snn_setup_sizes", "snn_setup_fill_rows", "snn_setup_fill_routes",
-    "snn_setup_input_bound", "snn_setup_destroy",
+    "snn_setup_input_bound", "snn_setup_destroy", "snn_setup_model_params",
 ]
 
 u32, u64, i32, f32, f64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
@@ -81,6 +81,11 @@ class snn_setup_spec(ctypes.Structure):
         ("gpus_per_node", u32), ("weight_type", u32), ("n_threads", u32), ("verbose", u32),
         ("n_clusters", u32), ("p_in", f64),
     ]
+
+
+class snn_model(ctypes.Structure):
+    _fields_ = [(n, f64) for n in ("dt_ms", "tau_m_ms", "theta_mv", "u_reset_mv", "t_ref_ms",
+                                   "nu_ext_hz", "w_ext_mv", "rate_on_hz", "rate_off_hz")]
 
 
 class SNNError(RuntimeError):
@@ -140,6 +145,7 @@ def lib() -> ctypes.CDLL:
             "snn_setup_fill_routes": (I, [vp] * 9),
             "snn_setup_input_bound": (I, [vp, ctypes.POINTER(f32)]),
             "snn_setup_destroy": (None, [vp]),
+            "snn_setup_model_params": (I, [ctypes.POINTER(snn_model), ctypes.POINTER(snn_params)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -240,6 +246,15 @@ def snn_ring_events(h) -> int:
     n = u64()
     check(lib().snn_ring_events(h, ctypes.byref(n)))
     return n.value
+
+
+def snn_setup_model_params(params: snn_params, **model) -> snn_params:
+    """Fills params' model constants (alpha, theta, u_reset, w_ext, n_ref,
+    poisson_thr, raster thresholds) from the physical ones (snn_model's
+    fields as keywords); returns params."""
+    m = snn_model(**model)
+    check(lib().snn_setup_model_params(ctypes.byref(m), ctypes.byref(params)))
+    return params
 
 
 def snn_bin_geometry():

@@ -370,4 +370,37 @@ void snn_setup_destroy(snn_setup_handle h) {
   delete h;
 }
 
+snn_status snn_setup_model_params(const snn_model* m, snn_params* p) {
+  if (!m || !p) return fail(SNN_ERR_INVALID_ARG, "NULL argument");
+  if (!(m->dt_ms > 0) || !(m->tau_m_ms > 0))
+    return fail(SNN_ERR_INVALID_ARG, "dt_ms and tau_m_ms must be positive");
+  if (!(m->t_ref_ms >= 0) || !(m->nu_ext_hz >= 0) || !(m->rate_on_hz >= 0) ||
+      !(m->rate_off_hz >= 0))
+    return fail(SNN_ERR_INVALID_ARG, "t_ref_ms and the rates must be non-negative");
+  const double steps_ref = std::nearbyint(m->t_ref_ms / m->dt_ms);
+  if (steps_ref > 255) return fail(SNN_ERR_INVALID_ARG, "refractory period of %.0f steps > 255",
+                                   steps_ref);
+  const double lambda = m->nu_ext_hz * m->dt_ms * 1e-3;
+  p->alpha = float(std::exp(-m->dt_ms / m->tau_m_ms));
+  p->theta = float(m->theta_mv);
+  p->u_reset = float(m->u_reset_mv);
+  p->w_ext = float(m->w_ext_mv);
+  p->n_ref = uint32_t(steps_ref);
+  // floor(2^32 x), clamped to the uint32 range
+  auto q32 = [](double x) -> uint32_t {
+    const double v = std::floor(std::ldexp(x, 32));
+    if (!(v > 0)) return 0u;
+    return v >= 4294967295.0 ? 0xFFFFFFFFu : uint32_t(v);
+  };
+  double pmf = std::exp(-lambda), cdf = 0.0;
+  for (int j = 0; j < 15; ++j) {
+    if (j) pmf = pmf * lambda / j;
+    cdf += pmf;
+    p->poisson_thr[j] = q32(cdf);
+  }
+  p->raster_thr_on = q32(m->rate_on_hz * m->dt_ms * 1e-3);
+  p->raster_thr_off = q32(m->rate_off_hz * m->dt_ms * 1e-3);
+  return SNN_OK;
+}
+
 }  // extern "C"

@@ -4,7 +4,6 @@ Simulation)."""
 from __future__ import annotations
 
 import ctypes
-import math
 import sys
 import time
 
@@ -40,28 +39,18 @@ def default_caps(wl, host) -> tuple[int, int]:
 
 
 def derived_params(wl) -> dict:
-    """Constants the kernels take ready-made: the per-step decay factor
-    fl32(exp(-dt / tau_m)), the Poisson inversion table floor(2^32 CDF(j))
-    for lambda = nu_ext dt, the refractory length and the forced-raster
-    thresholds floor(2^32 rate dt)."""
-    alpha = np.float32(math.exp(-wl.dt_ms / wl.tau_m_ms))
-    lam = wl.nu_ext_hz * wl.dt_ms * 1e-3
-    thr = []
-    pmf, cdf = math.exp(-lam), 0.0
-    for j in range(15):
-        if j:
-            pmf = pmf * lam / j
-        cdf += pmf
-        thr.append(min(int(math.floor(math.ldexp(cdf, 32))), 2**32 - 1))
-
-    def raster(rate_hz):
-        v = math.floor(math.ldexp(rate_hz * wl.dt_ms * 1e-3, 32))
-        return max(0, min(v, 2**32 - 1))
-
-    return dict(alpha=float(alpha), theta=float(np.float32(wl.theta_rel_mv)),
-                u_reset=float(np.float32(wl.u_reset_mv)), w_ext=float(np.float32(wl.w_ext_mv)),
-                n_ref=int(round(wl.t_ref_ms / wl.dt_ms)), poisson_thr=thr,
-                raster_thr_on=raster(wl.rate_on_hz), raster_thr_off=raster(wl.rate_off_hz))
+    """Constants the kernels take ready-made, computed by the library from
+    the workload's physical ones (snn_setup_model_params): the per-step decay
+    factor fl32(exp(-dt / tau_m)), the Poisson inversion table
+    floor(2^32 CDF(j)) for lambda = nu_ext dt, the refractory length and the
+    forced-raster thresholds floor(2^32 rate dt)."""
+    p = _abi.snn_setup_model_params(
+        _abi.snn_params(), dt_ms=wl.dt_ms, tau_m_ms=wl.tau_m_ms, theta_mv=wl.theta_rel_mv,
+        u_reset_mv=wl.u_reset_mv, t_ref_ms=wl.t_ref_ms, nu_ext_hz=wl.nu_ext_hz,
+        w_ext_mv=wl.w_ext_mv, rate_on_hz=wl.rate_on_hz, rate_off_hz=wl.rate_off_hz)
+    return dict(alpha=float(p.alpha), theta=float(p.theta), u_reset=float(p.u_reset),
+                w_ext=float(p.w_ext), n_ref=int(p.n_ref), poisson_thr=list(p.poisson_thr),
+                raster_thr_on=int(p.raster_thr_on), raster_thr_off=int(p.raster_thr_off))
 
 
 class HostNetwork:

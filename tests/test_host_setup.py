@@ -162,3 +162,17 @@ def test_derived_params_match_oracle(name):
     assert dp["n_ref"] == oracle.n_ref(p)
     assert dp["raster_thr_on"] == oracle.raster_threshold(wl.rate_on_hz, wl.dt_ms)
     assert dp["raster_thr_off"] == oracle.raster_threshold(wl.rate_off_hz, wl.dt_ms)
+
+
+def test_model_params_rejects_bad_constants():
+    from paper_2205_07125_amd import _abi
+    good = dict(dt_ms=0.1, tau_m_ms=20.0, theta_mv=20.0, u_reset_mv=10.0, t_ref_ms=2.0,
+                nu_ext_hz=8000.0, w_ext_mv=0.1, rate_on_hz=5.0, rate_off_hz=5.0)
+    p = _abi.snn_setup_model_params(_abi.snn_params(n_neurons=7), **good)
+    assert p.n_neurons == 7 and p.n_ref == 20          # other fields untouched
+    assert list(p.poisson_thr) == sorted(p.poisson_thr)
+    for bad in (dict(dt_ms=0.0), dict(tau_m_ms=-1.0), dict(nu_ext_hz=-1.0),
+                dict(rate_on_hz=-5.0), dict(t_ref_ms=26.0), dict(dt_ms=float("nan"))):
+        with pytest.raises(_abi.SNNError) as e:
+            _abi.snn_setup_model_params(_abi.snn_params(), **dict(good, **bad))
+        assert e.value.status == _abi.SNN_ERR_INVALID_ARG
