@@ -131,7 +131,11 @@ def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_bytes, w
     import statistics
 
     def per_kernel(d, counter):
-        rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        import glob
+        files = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+        if not files:
+            raise FileNotFoundError(f"no *counter_collection.csv under {d}")
+        rows = list(csv.DictReader(open(files[0])))
         vals = {}
         for r in rows:
             if r["Counter_Name"] != counter:
@@ -183,8 +187,13 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shapes by timing (autotune.tune) before the timed "
                          "region")
+    ap.add_argument("--tuning", default="", metavar="U,S,M",
+                    help="launch shapes to use (snn_tuning): update_blocks, recv_split, "
+                         "recv_merged; overridden by --autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-steps", type=int, default=100)
+    ap.add_argument("--tile-neurons", type=int, default=0,
+                    help="neurons per tile (snn_params.tile_neurons; 0: the library's default)")
     ap.add_argument("--neurons", type=int, default=0,
                     help="run the workload's structure at this many neurons (quick checks)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -232,14 +241,19 @@ def main():
     t1 = time.time()
     sim = Simulation(wl, host=host, log_steps=total_steps,
                      log_cap=int(wl.n_neurons * max(wl.rate_on_hz, 50.0) * wl.dt_ms * 1e-3 * 4
-                                 * total_steps) + (1 << 20))
+                                 * total_steps) + (1 << 20), tile_neurons=args.tile_neurons)
     nnz = host.nnz
+    sim_tile = sim.tile_neurons
     del host
     sim.host = None
     log(f"device upload {time.time() - t1:.1f}s")
 
     use_graph = args.graph
     tuned = None
+    if args.tuning:
+        u, r, m = (int(x) for x in args.tuning.split(","))
+        sim.set_tuning(update_blocks=u, recv_split=r, recv_merged=m)
+        log(f"tuning: {sim.tuning()}")
     if args.autotune:
         from paper_2205_07125_amd import autotune
         tuned = autotune.tune(sim, mode, log=log)
@@ -328,14 +342,24 @@ def main():
     # events it writes and reads back are the implementation's, not the
     # method's, and are not counted)
     fused_x = mode == SNN_ROUTE_TWO_LEVEL and kt.get("expand", 0.0) == 0.0
+    # the receive side as two launches: k_recv_local (expansion, staging, own-
+    # partition delivery), then k_deliver_remote, which reads the staged remote
+    # synapses back (8 B each, the implementation's queue) and bins them
+    split_x = fused_x and kt.get("deliver", 0.0) > 0.0
     if fused_x:
         alg["recv_stage"] += alg["expand"] + alg["deliver"]
+        if split_x:
+            alg["deliver"] = 8.0 * e_rem
     kernels = {k: {"ms": kt[k], "alg_bytes": alg[k],
                    "gbs": alg[k] / (kt[k] * 1e-3) / 1e9 if kt[k] > 0 else None}
                for k in kt if kt[k] > 0}
     if fused:
         kernels["update"]["includes"] = "two-level routing of the tile's fired neurons"
-    if fused_x:
+    if fused_x and split_x:
+        kernels["recv_stage"]["includes"] = ("mask expansion of the node's messages and staging; "
+                                             "delivery of the own-partition synapses")
+        kernels["deliver"]["includes"] = "the staged remote synapses (queue read back)"
+    elif fused_x:
         kernels["recv_stage"]["includes"] = ("mask expansion of the node's messages; delivery of "
                                              "the own-partition and the staged remote synapses")
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
@@ -349,7 +373,8 @@ def main():
         h = kernel_source_hash()
         # counters are keyed by kernel symbol; the combined receive-side
         # launch and the remote-only deliver have their own
-        symbol = {"recv_stage": "recv_deliver"} if fused_x else {}
+        symbol = ({"recv_stage": "recv_local", "deliver": "deliver_remote"} if split_x
+                  else {"recv_stage": "recv_deliver"} if fused_x else {})
         for k, v in kernels.items():
             ent = tj.get(symbol.get(k, k))
             v["traffic_bytes"] = ent["bytes_per_launch"] if ent and ent.get("kernel_hash") == h else None
@@ -372,7 +397,8 @@ def main():
         "config": {"workload": wl.name, "n_neurons": N, "in_degree": wl.k_in,
                    "partitions": wl.n_partitions, "gpus_per_node": wl.gpus_per_node,
                    "remote_frac": wl.remote_frac, "rate_hz": wl.rate_on_hz if wl.forced else None,
-                   "route": args.mode, "graph": use_graph, "synapses": int(nnz)},
+                   "route": args.mode, "graph": use_graph, "synapses": int(nnz),
+                   "tile_neurons": sim_tile},
         "routed_msgs_per_s": (msgs if mode == SNN_ROUTE_TWO_LEVEL else flat) / sec,
         "recv_entries_per_s": entries / sec,
         "spikes_per_step": spikes / args.steps,
@@ -408,6 +434,8 @@ def main():
     if tuned is not None:
         out["tuning"] = {"choice": tuned["tuning"], "cached": tuned["cached"],
                          "candidates": len(tuned.get("timings", []))}
+    elif args.tuning:
+        out["tuning"] = {"choice": sim.tuning(), "cached": False, "candidates": 0}
     sim.close()
     del sim
     torch.cuda.empty_cache()

@@ -174,6 +174,11 @@ typedef struct {
                                  events beyond it take the (slower) dense-ring path */
   uint64_t stage_cap;         /* remote events per (delay, receive-side block) and step,
                                  see snn_bin_geometry; beyond it, the dense-ring path */
+  uint32_t tile_neurons;      /* neurons per tile (the update's block and the bins' unit):
+                                 0 for the default, 8192, or where that gives fewer than
+                                 512 tiles (two update blocks per CU of a 256-CU part) the
+                                 neurons spread over 512 tiles, rounded up to a multiple of
+                                 64, at least 2048; else a multiple of 64 in [64, 8192] */
 } snn_params;
 
 /* Network arrays in device memory.  nnz = row_ptr[n_neurons]; pairs =
@@ -355,12 +360,16 @@ snn_status snn_ring_events(snn_handle h, uint64_t* n);
    snn_step. */
 snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg_ms);
 
-/* Geometry of the binned delivery, for sizing snn_params.bin_cap and
-   stage_cap: *tile_neurons neurons share a bin; each (step slot, tile, delay)
-   has *deliver_blocks sub-bins (one per writing block), each of bin_cap
-   events; each delay has *stage_blocks receive queues of stage_cap events.
-   Any pointer may be NULL. */
-void snn_bin_geometry(uint32_t* tile_neurons, uint32_t* deliver_blocks, uint32_t* stage_blocks);
+/* Geometry of the binned delivery for a network of params->n_neurons neurons
+   and the requested params->tile_neurons (the only fields read), for sizing
+   snn_params.bin_cap and stage_cap: *tile_neurons neurons share a bin (the
+   tile size the library will use); each (step slot, tile, delay) has
+   *deliver_blocks sub-bins (one per writing block), each of bin_cap events;
+   each delay has *stage_blocks receive queues of stage_cap events.  Any
+   output pointer may be NULL.  SNN_ERR_INVALID_ARG for an invalid tile size
+   or neuron count. */
+snn_status snn_bin_geometry(const snn_params* params, uint32_t* tile_neurons,
+                            uint32_t* deliver_blocks, uint32_t* stage_blocks);
 
 /* Steps completed so far (host-side count of enqueued steps). */
 uint64_t snn_time(snn_handle h);

@@ -59,7 +59,7 @@ class snn_params(ctypes.Structure):
         ("raster_thr_on", u32), ("raster_thr_off", u32), ("raster_period", u32), ("raster_on", u32),
         ("bucket_total", u64), ("recv_total", u64),
         ("log_steps", u32), ("input_bound", f32), ("log_cap", u64),
-        ("bin_cap", u64), ("stage_cap", u64),
+        ("bin_cap", u64), ("stage_cap", u64), ("tile_neurons", u32),
     ]
 
 
@@ -132,7 +132,7 @@ def lib() -> ctypes.CDLL:
             "snn_sync": (I, [vp]),
             "snn_ring_events": (I, [vp, ctypes.POINTER(u64)]),
             "snn_time": (u64, [vp]),
-            "snn_bin_geometry": (None, [ctypes.POINTER(u32)] * 3),
+            "snn_bin_geometry": (I, [ctypes.POINTER(snn_params)] + [ctypes.POINTER(u32)] * 3),
             "snn_read_spikes": (I, [vp, u64, u32, vp, u64, vp, ctypes.POINTER(u64)]),
             "snn_read_routes": (I, [vp, I, vp, vp, u64, ctypes.POINTER(u64)]),
             "snn_read_counters": (I, [vp, u64, u32, vp]),
@@ -257,10 +257,13 @@ def snn_setup_model_params(params: snn_params, **model) -> snn_params:
     return params
 
 
-def snn_bin_geometry():
-    """-> (tile_neurons, deliver_blocks, stage_blocks) of the binned delivery."""
+def snn_bin_geometry(n_neurons: int, tile_neurons: int = 0):
+    """-> (tile_neurons, deliver_blocks, stage_blocks) of the binned delivery
+    for n_neurons neurons and a requested tile size (0: the default)."""
+    p = snn_params(n_neurons=n_neurons, tile_neurons=tile_neurons)
     a, b, c = u32(), u32(), u32()
-    lib().snn_bin_geometry(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    check(lib().snn_bin_geometry(ctypes.byref(p), ctypes.byref(a), ctypes.byref(b),
+                                 ctypes.byref(c)))
     return a.value, b.value, c.value
 
 

@@ -29,7 +29,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2205_0712
 def shape_key(sim) -> str:
     import torch
     wl = sim.wl
-    tiles = (wl.n_neurons + 8191) // 8192
+    tiles = -(-wl.n_neurons // sim.tile_neurons)
     nnz = int(sim.host.nnz) if sim.host is not None else -1
     dev = torch.cuda.get_device_name(sim.device)
     return (f"{dev}|N={wl.n_neurons}|P={wl.n_partitions}|G={wl.gpus_per_node}|tiles={tiles}|"
@@ -44,7 +44,7 @@ def candidates(sim, cu_count: int | None = None) -> list[dict]:
     recv_merged: both forms of the receive side."""
     import torch
     wl = sim.wl
-    tiles = (wl.n_neurons + 8191) // 8192
+    tiles = -(-wl.n_neurons // sim.tile_neurons)
     if cu_count is None:
         cu_count = torch.cuda.get_device_properties(sim.device).multi_processor_count
     ub = [0] + [k * cu_count for k in (1, 2, 3) if k * cu_count < tiles]

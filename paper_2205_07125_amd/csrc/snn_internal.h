@@ -16,16 +16,17 @@ enum : uint32_t {
   ERR_FLAT = 4u,     // a flat receive list overflowed
   ERR_LOG = 8u,      // a step had more spikes than the spike log holds
   ERR_ROUTE = 16u,   // a receive entry names a partition its source does not reach
-  ERR_TIMEOUT = 32u  // a wait between blocks of one launch gave up (a block it waited for
+  ERR_TIMEOUT = 32u, // a wait between blocks of one launch gave up (a block it waited for
                      // never arrived)
+  ERR_XCD = 64u      // a block of the one-launch receive side ran on another XCD than
+                     // its index implies (its hand-off would not be coherent)
 };
 
 // Words of the in-launch synchronisation area (KParams::sync), each on a
-// 64-byte line of its own; every launch that uses one leaves it at zero.
+// 64-byte line of its own; they hold tagged values, so nothing clears them.
 enum : uint32_t {
-  SYNC_STAGED = 0,    // staging blocks of the receive launch that are done
-  SYNC_RETIRED = 16,  // delivery blocks of that launch that are done
-  SYNC_WORDS = 64
+  SYNC_STRIDE = 16,   // words per line
+  SYNC_WORDS = 256 * SYNC_STRIDE    // word SYNC_STRIDE * b: staging block b's flag
 };
 
 // Device-resident step state.  Every step-dependent value lives here so that
@@ -55,13 +56,21 @@ struct DevState {
 // Stream ids of the counter-based generator.
 enum : uint32_t { STREAM_POISSON = 1u, STREAM_RASTER = 2u };
 
-// Geometry.  Neurons are grouped in tiles of TILE neurons: the update kernel
-// runs one block per tile and accumulates the tile's arriving input in LDS;
-// synaptic events are binned per (ring slot, tile).
-constexpr int TILE_SHIFT = 13;
-constexpr uint32_t TILE = 1u << TILE_SHIFT;         // 8192 neurons
+// Geometry.  Neurons are grouped in tiles of T neurons (KParams::tile, a
+// multiple of TILE_ALIGN up to TILE_MAX, fixed per network): the update
+// kernel runs one block per tile and accumulates the tile's arriving input
+// in LDS; synaptic events are binned per (ring slot, tile).  The default T
+// is the largest (TILE_MAX), unless that leaves fewer than TILE_MIN_COUNT
+// tiles (two update blocks per CU of a 256-CU part); then the neurons are
+// spread over TILE_MIN_COUNT tiles, down to TILE_MIN_DEFAULT neurons each.
+// Larger tiles mean fewer sub-bins, so longer runs per sub-bin in the
+// delivery; more tiles keep every CU busy where the network is small.
+constexpr uint32_t TILE_MAX = 8192;
+constexpr uint32_t TILE_ALIGN = 64;
+constexpr uint32_t TILE_MIN_DEFAULT = 2048;
+constexpr uint32_t TILE_MIN_COUNT = 2 * 256;
 constexpr int UPDATE_THREADS = 512;
-constexpr int UPDATE_NPT = TILE / UPDATE_THREADS;   // 16 neurons per thread
+constexpr int UPDATE_NPT = TILE_MAX / UPDATE_THREADS;   // 16 neurons per thread at most
 constexpr int ROUTE_THREADS = 256;
 constexpr int DELIVER_THREADS = 512;
 constexpr uint32_t CNT_STRIDE = 16;                 // counters padded to 64 bytes
@@ -69,6 +78,11 @@ constexpr uint32_t ROUTE_STAGE = 2048;              // pairs per routing window
 constexpr uint32_t ROUTE_BLOCKS = 256;              // two-level routing blocks
 constexpr uint32_t ROUTE_MAX_NODES_LDS = 4096;      // more nodes: unstaged routing
 constexpr uint32_t DELIVER_BLOCKS = 32;             // deliver blocks per delay
+// XCDs of the chip (each with its own L2): workgroup b of a launch runs on XCD
+// (b + c) mod N_XCD for a c fixed per launch, so blocks whose indices differ
+// by a multiple of N_XCD share an XCD.  The one-launch receive side relies on
+// that (and checks it at run time).
+constexpr uint32_t N_XCD = 8;
 constexpr uint32_t STAGE_BLOCKS = 256;              // receive-side blocks (one queue each)
 constexpr uint32_t STAGE_PARTS = 256;               // partitions per receive-side block, at most
 static_assert(STAGE_PARTS * STAGE_BLOCKS >= SNN_MAX_PARTITIONS, "receive blocks must cover P");
@@ -125,6 +139,8 @@ struct KParams {
   // model
   uint32_t N, P, G, D, n_nodes, n_tiles;
   uint32_t g_magic;          // ceil(2^32 / G) for G >= 2: node of a partition by one multiply
+  uint32_t tile;             // neurons per tile, T
+  uint32_t tile_magic, tile_shift;   // x / T = umulhi(x, tile_magic) >> tile_shift, x < 2^27
   uint32_t n_ref;
   uint64_t ring_stride;
   float alpha, theta, u_reset, w_ext;
@@ -182,7 +198,7 @@ struct KParams {
   uint64_t* flat;       // [recv_total]
   uint32_t* stage_cnt;  // [max_delay * CNT_STRIDE] remote events staged per delay
   Event* stage;         // [max_delay][stage_cap] (global target ids)
-  uint32_t* bin_cnt;    // [D * n_tiles * CNT_STRIDE]
+  uint32_t* bin_cnt;    // [D * n_tiles * max_delay * DELIVER_BLOCKS], see subbin()
   uint32_t* dirty;      // [D * n_tiles] ring tile holds events
   Event* bins;          // [D][n_tiles][bin_cap]
   uint64_t* stats;      // [log_steps + 1][STAT_LANES][STAT_LANE_WORDS]
@@ -193,7 +209,10 @@ struct KParams {
 // Launchers (snn_kernels.hip); all enqueue on `s` and return the launch error.
 // With non-null marks, events marks[2k], marks[2k + 1] are recorded around
 // each launch of kernel kind k (SNN_KERNEL_*).
-uint32_t tiles_of(uint32_t n);
+// Tile size for n neurons and a requested size (0: the default rule), and
+// the multiplier and shift that divide by it.
+uint32_t tile_size(uint32_t n, uint32_t requested);
+void tile_divider(uint32_t t, uint32_t* magic, uint32_t* shift);
 hipError_t prepare_kernels(KParams& p);   // LDS limits of the kernels, once per handle
 // With route, the update kernel also routes the step two-level where the node
 // count allows (fused_route_ok); launch_route is then told so (routed) and

@@ -1,7 +1,7 @@
 // snn_kernels.hip — the per-step kernels for gfx950 (wave64, CDNA4).
 //
 // The work of a step, as device functions shared by the kernels:
-//   k_update       one block per tile of TILE neurons: sums the tile's arriving
+//   k_update       one block per tile of T neurons: sums the tile's arriving
 //                  synaptic events into LDS from its bins, runs the LIF update
 //                  and threshold, compacts fired ids in ascending order (wave
 //                  ballots, block scan, decoupled look-back across tiles)
@@ -24,11 +24,16 @@
 //     own-partition delivery, then the staged remote synapses in a launch of
 //     their own, appended after the counts the local part published;
 //   k_recv_deliver: the same in one launch, the delivery blocks waiting for
-//     the staging blocks and then binning the staged remote synapses too; the
-//     queues pass between the blocks through device-coherent loads and
-//     stores (the sc1 form of global access, which goes past the
-//     non-coherent per-XCD L2 caches), since a device-scope release and
-//     acquire per block would write back or invalidate a whole L2 each time.
+//     the staging blocks and then binning the staged remote synapses too.
+//     Every queue is written and read by blocks on the same XCD (workgroups
+//     are dealt out to the XCDs in turn, and the queue of staging block b is
+//     binned by delivery blocks whose index is b mod 8 apart from it by a
+//     multiple of 8), so the queues pass through that XCD's L2 with plain
+//     stores and loads: no write-back of the (non-coherent, per-XCD) L2,
+//     which a device-scope release per block would cost, and no
+//     write-through stores.  Each staging block publishes the XCD it ran on
+//     with its flag, and a delivery block flags ERR_XCD for a queue staged
+//     on another XCD than its own.
 // The step-by-step entry points use one kernel per job instead
 // (k_update<false>, k_route_two_level, k_expand, k_recv_stage, k_deliver).
 //
@@ -109,20 +114,9 @@ __device__ __forceinline__ float load_weight(const KParams& p, uint64_t e) {
   }
 }
 
-// Device-coherent access for data handed between blocks of one launch: the
-// access goes to the coherence point instead of a possibly stale line of the
-// XCD's own L2, so no cache-wide write-back or invalidation is needed.
-__device__ __forceinline__ void store_coherent(uint64_t* a, uint64_t v) {
-  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_coherent(uint32_t* a, uint32_t v) {
-  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t load_coherent(const uint64_t* a) {
-  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t load_coherent(const uint32_t* a) {
-  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// XCD (XCC) the calling wave runs on: hardware register XCC_ID, bits 3:0.
+__device__ __forceinline__ uint32_t xcc_id() {
+  return __builtin_amdgcn_s_getreg((31 << 11) | 20) & 0xFu;
 }
 
 // Adds the block's sum of two per-thread counters into two global u64s with
@@ -201,12 +195,17 @@ __device__ __forceinline__ float dequantize_w(const KParams& p, int32_t q) {
   return static_cast<float>(static_cast<double>(q) * p.wq_inv);
 }
 
+// Tile of neuron x (x < 2^27) by one multiply: floor(x / T).
+__device__ __forceinline__ uint32_t tile_of(const KParams& p, uint32_t x) {
+  return __umulhi(x, p.tile_magic) >> p.tile_shift;
+}
+
 // An event that does not fit its bin goes to the dense overflow ring, which
 // holds fixed-point sums (integer atomics: exact in any order, like the
 // update's own sums); the tile is flagged so the update reads that slice.
 __device__ void ring_fallback(const KParams& p, uint32_t slot, uint32_t tgt, int32_t wq) {
   atomicAdd(p.ovf + slot * p.ring_stride + tgt, wq);
-  p.dirty[slot * p.n_tiles + (tgt >> TILE_SHIFT)] = 1u;
+  p.dirty[slot * p.n_tiles + tile_of(p, tgt)] = 1u;
   atomicAdd(reinterpret_cast<unsigned long long*>(&p.st->ring_events), 1ull);
 }
 
@@ -558,7 +557,7 @@ __device__ uint32_t lookback_resolve(uint64_t* lb, uint32_t b, uint32_t agg, uin
 // launch is needed; the LDS of the input sums and the Poisson lookup, free by
 // then, holds the routing's arrays.
 static_assert(UPDATE_NPT % 4 == 0 && UPDATE_NPT <= 32, "fire bits of a thread fit 32 bits");
-constexpr size_t UPDATE_BIG_LDS = TILE * sizeof(int32_t) + POIS_LUT_SIZE;
+constexpr size_t UPDATE_BIG_LDS = TILE_MAX * sizeof(int32_t) + POIS_LUT_SIZE;
 static_assert(route_lds_bytes(UPDATE_THREADS, FUSED_ROUTE_WINDOW, FUSED_MAX_NODES, false) <=
                   UPDATE_BIG_LDS,
               "the fused routing's arrays fit the update's LDS");
@@ -570,11 +569,11 @@ template <bool ROUTE, bool PERSIST>
 __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   constexpr int NQ = UPDATE_NPT / 4;
   constexpr int NW = UPDATE_THREADS / 64;
-  // input sums (TILE int32, fixed point in units of 2^-F) and the Poisson
+  // input sums (T int32, fixed point in units of 2^-F) and the Poisson
   // inversion lookup (bytes); the routing's arrays afterwards
   __shared__ uint4 s_big[UPDATE_BIG_LDS / 16];
   int32_t* s_acc = reinterpret_cast<int32_t*>(s_big);
-  uint4* s_lut4 = s_big + TILE / 4;
+  uint4* s_lut4 = s_big + TILE_MAX / 4;
   __shared__ uint32_t s_cnt[NQ][NW];    // spikes per (quad, wave)
   __shared__ uint32_t s_qoff[NQ][NW];   // their offsets in the block's order
   __shared__ uint32_t s_bcnt[MAX_SUBBINS];
@@ -609,7 +608,10 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   // taken by running blocks.
   uint32_t tile = p.tile0 + blockIdx.x;
   while (true) {
-  const uint32_t blk0 = tile * TILE;
+  const uint32_t T = p.tile;
+  const uint32_t blk0 = tile * T;
+  // the neurons of this tile the launch updates
+  const uint32_t lo_t = max(p.lo, blk0), hi_t = min(p.hi, blk0 + T);
 
   // Per-step counters of the routing: the bucket counters of step t + 1 (this
   // step's routing counts into the other set) and the receive-list counters.
@@ -630,20 +632,26 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   const uint32_t md = p.D - 1;
   const uint32_t n_sub = md * DELIVER_BLOCKS;
   const uint32_t bc_raw = tid < n_sub ? p.bin_cnt[subbin(p, slot, tile, 1, 0) + tid] : 0u;
-  for (uint32_t i = tid; i < TILE; i += UPDATE_THREADS) s_acc[i] = 0;
+  for (uint32_t i = tid; i < T; i += UPDATE_THREADS) s_acc[i] = 0;
   if (tid == 0) s_dirty = p.dirty[slot * p.n_tiles + tile];
   for (uint32_t i = tid; i < POIS_LUT_SIZE / 16; i += UPDATE_THREADS)
     s_lut4[i] = reinterpret_cast<const uint4*>(p.pois_lut)[i];
   if (tid < 15) s_thr[tid] = p.thr[tid];
   const uint8_t* s_lut = reinterpret_cast<const uint8_t*>(s_lut4);
 
-  // State of quad q of the thread's neurons (4 consecutive neurons).  The
+  // State of quad q of the thread's neurons (4 consecutive neurons; T is a
+  // multiple of 4, so a quad lies inside the tile or past its end).  The
   // branch on a whole tile in range is uniform, so loads carry no divergent
-  // merge; past N a lane reads neuron N - 1 (never stored back, never fires).
-  const bool tile_full = blk0 >= p.lo && blk0 + TILE <= p.hi;
+  // merge; past the launch's range a lane reads an in-range neuron (never
+  // stored back, never fires); quads past the tile's end load nothing.
+  const bool tile_full = lo_t == blk0 && hi_t == blk0 + T;
   auto load_quad = [&](int q, float4& u4, uint32_t& r4) {
-    const uint32_t i0 = blk0 + q * (4 * UPDATE_THREADS) + 4 * tid;
-    if (tile_full) {
+    const uint32_t l0 = q * (4 * UPDATE_THREADS) + 4 * tid;
+    const uint32_t i0 = blk0 + l0;
+    if (l0 >= T) {
+      u4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      r4 = 0;
+    } else if (tile_full) {
       u4 = *reinterpret_cast<const float4*>(p.u + i0);
       r4 = *reinterpret_cast<const uint32_t*>(p.ref + i0);
     } else {
@@ -651,7 +659,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
       uint32_t r = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint32_t ik = min(max(i0 + k, p.lo), p.hi - 1);
+        const uint32_t ik = min(max(i0 + k, lo_t), hi_t - 1);
         v[k] = p.u[ik];
         r |= static_cast<uint32_t>(p.ref[ik]) << (8 * k);
       }
@@ -722,7 +730,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   int32_t* ovf_slot = p.ovf + static_cast<uint64_t>(slot) * p.ring_stride;
   const bool dirty = s_dirty != 0;
   // (cleared by the launch that holds the tile's last neuron)
-  if (dirty && tid == 0 && min(blk0 + TILE, p.N) <= p.hi) p.dirty[slot * p.n_tiles + tile] = 0u;
+  if (dirty && tid == 0 && min(blk0 + T, p.N) <= p.hi) p.dirty[slot * p.n_tiles + tile] = 0u;
 
   uint32_t thr_raster = 0;
   if (p.forced) thr_raster = phase < p.raster_on ? p.raster_on_thr : p.raster_off_thr;
@@ -753,7 +761,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     if (dirty) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (i0 + k >= p.lo && i0 + k < p.hi) {
+        if (i0 + k >= lo_t && i0 + k < hi_t) {
           acc[k] += ovf_slot[i0 + k];
           ovf_slot[i0 + k] = 0;
         }
@@ -787,7 +795,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
       const float un = integrating ? u_int : uu[k];
       const uint32_t rn = integrating ? 0u : rf[k] - 1u;
       bool s = p.forced ? (r2[k] < thr_raster) : (integrating && un >= p.theta);
-      s = s && (i0 + k >= p.lo && i0 + k < p.hi);
+      s = s && (i0 + k >= lo_t && i0 + k < hi_t);
       uu[k] = s ? p.u_reset : un;
       rf[k] = s ? p.n_ref : rn;
       fire_bits |= static_cast<uint32_t>(s) << (4 * q + k);
@@ -797,12 +805,15 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     for (int k = 0; k < 4; ++k) cnt_q += __popcll(__ballot((fire_bits >> (4 * q + k)) & 1u));
     if (lane == 0) s_cnt[q][wave] = cnt_q;
     if (tile_full) {
-      *reinterpret_cast<float4*>(p.u + i0) = make_float4(uu[0], uu[1], uu[2], uu[3]);
-      *reinterpret_cast<uint32_t*>(p.ref + i0) = rf[0] | (rf[1] << 8) | (rf[2] << 16) | (rf[3] << 24);
+      if (l0 < T) {
+        *reinterpret_cast<float4*>(p.u + i0) = make_float4(uu[0], uu[1], uu[2], uu[3]);
+        *reinterpret_cast<uint32_t*>(p.ref + i0) =
+            rf[0] | (rf[1] << 8) | (rf[2] << 16) | (rf[3] << 24);
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (i0 + k >= p.lo && i0 + k < p.hi) {
+        if (i0 + k >= lo_t && i0 + k < hi_t) {
           p.u[i0 + k] = uu[k];
           p.ref[i0 + k] = static_cast<uint8_t>(rf[k]);
         }
@@ -1017,7 +1028,6 @@ struct StageCtx {
   uint64_t* s_seg;     // [RECV_BATCH] second synapse of each entry's segment
   uint32_t* s_epre;    // [RECV_BATCH] remaining synapses: starts in the concatenation
   uint32_t* s_wsum;    // [RECV_THREADS / 64]
-  bool coherent;       // the queues are read by other blocks of the same launch
 };
 
 // One synapse (tgt_delay, weight) into the queue of its delay (position from
@@ -1033,12 +1043,7 @@ __device__ __forceinline__ void stage_emit(const KParams& p, const StageCtx& c, 
   const Event ev{td & 0x07FFFFFFu, quantize_w(p, w)};
   const uint32_t pos = atomicAdd(&c.l_pos[d1], 1u);
   if (pos < p.stage_cap) {
-    Event* q = c.queue + d1 * c.qstride + pos;
-    if (c.coherent)
-      store_coherent(reinterpret_cast<uint64_t*>(q),
-                     ev.tgt | (static_cast<uint64_t>(static_cast<uint32_t>(ev.wq)) << 32));
-    else
-      *q = ev;
+    c.queue[d1 * c.qstride + pos] = ev;
   } else {
     uint32_t slot = c.slot0 + d1 + 1;
     if (slot >= p.D) slot -= p.D;
@@ -1149,7 +1154,7 @@ __global__ __launch_bounds__(RECV_THREADS) void k_recv_stage(KParams p, int use_
   __syncthreads();
   const StageCtx ctx{p.stage + static_cast<uint64_t>(b) * p.stage_cap,
                      static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap, p.st->cur_slot, l_pos,
-                     s_seg, s_epre, s_wsum, false};
+                     s_seg, s_epre, s_wsum};
   uint64_t events = 0;
   for (uint32_t b0 = 0; b0 < n_ent; b0 += RECV_BATCH) {
     const uint32_t nb = min(n_ent - b0, RECV_BATCH);
@@ -1202,7 +1207,7 @@ __device__ __forceinline__ uint32_t split_of(const KParams& p, uint32_t nblocks)
   return p.recv_split ? min(s, p.recv_split) : s;
 }
 
-template <bool BF16, bool STAGE, bool WIDE, bool COHERENT>
+template <bool BF16, bool STAGE, bool WIDE>
 __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblocks, uint64_t* dyn) {
   using MaskT = std::conditional_t<WIDE, uint64_t, uint32_t>;
   constexpr uint32_t NW = RECV_THREADS / 64;
@@ -1229,7 +1234,7 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
   if (tid < SNN_MAX_DELAY) l_pos[tid] = 0;
   const StageCtx ctx{p.stage + static_cast<uint64_t>(b) * p.stage_cap,
                      static_cast<uint64_t>(STAGE_BLOCKS) * p.stage_cap, p.st->cur_slot, l_pos,
-                     s_seg, s_epre, s_wsum, COHERENT};
+                     s_seg, s_epre, s_wsum};
   uint64_t events = 0, entries = 0;
   // stages the n buffered entries (uniform n)
   auto stage_buffer = [&](uint32_t n) {
@@ -1358,8 +1363,7 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
   stage_buffer(n_buf);
   if (STAGE && tid < md) {
     const uint32_t c = static_cast<uint32_t>(min(static_cast<uint64_t>(l_pos[tid]), p.stage_cap));
-    if (COHERENT) store_coherent(p.stage_cnt + tid * STAGE_BLOCKS + b, c);
-    else p.stage_cnt[tid * STAGE_BLOCKS + b] = c;
+    p.stage_cnt[tid * STAGE_BLOCKS + b] = c;
   }
   uint64_t* sc = stat_copy(p, row);
   add_stats(sc + SNN_STAT_REMOTE_EVENTS, events, sc + SNN_STAT_RECV_ENTRIES, entries, s_red);
@@ -1368,8 +1372,8 @@ __device__ void expand_stage_block(const KParams& p, uint32_t b, uint32_t nblock
 // Mask expansion alone (the step-by-step path): expansion blocks over the
 // nodes, the receive lists as output.
 __global__ __launch_bounds__(RECV_THREADS) void k_expand(KParams p) {
-  if (p.G > NARROW_G) expand_stage_block<false, false, true, false>(p, blockIdx.x, gridDim.x, nullptr);
-  else expand_stage_block<false, false, false, false>(p, blockIdx.x, gridDim.x, nullptr);
+  if (p.G > NARROW_G) expand_stage_block<false, false, true>(p, blockIdx.x, gridDim.x, nullptr);
+  else expand_stage_block<false, false, false>(p, blockIdx.x, gridDim.x, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1395,9 +1399,9 @@ __global__ __launch_bounds__(RECV_THREADS) void k_expand(KParams p) {
 // the queues complete at launch); DELIVER_LOCAL takes the sources only
 // (beside the staging, which is still filling the queues) and
 // DELIVER_REMOTE the queues only, appended after the counts DELIVER_LOCAL
-// published; DELIVER_SPLIT takes the sources, waits for every staging block
-// of the same launch to have published its queues (wait_staged), then takes
-// the queues with device-coherent loads, appending to the same runs.
+// published; DELIVER_SPLIT takes the sources, waits for the staging blocks
+// of the same launch whose queues it bins (wait_staged), then takes the
+// queues, appending to the same runs.
 // dyn holds deliver_lds_bytes(n_tiles) bytes.
 enum DeliverPart { DELIVER_ALL, DELIVER_LOCAL, DELIVER_REMOTE, DELIVER_SPLIT };
 constexpr uint32_t DELIVER_ROUND = GATHER_UNROLL * DELIVER_THREADS;
@@ -1407,46 +1411,52 @@ static_assert(DELIVER_ROUND <= 65536, "window positions fit 16 bits");
 // ERR_TIMEOUT (each poll sleeps about 128 cycles): every wait ends.
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
+// The hand-off of the one-launch receive side.  Staging block b publishes
+// flag word b (its own 64-byte line) once its queues and counts are stored:
+// tag << 4 | the XCD it ran on, the tag being the step counter as this
+// launch reads it, so a word left by an earlier launch never matches.
+__device__ __forceinline__ uint32_t staged_word(const KParams& p, uint32_t xcc) {
+  return (static_cast<uint32_t>(p.st->t) << 4) | xcc;
+}
+
 // Called by every thread of a staging block once its queues and their
-// counts are stored (device-coherently): waits for its own stores to
-// complete, then the block counts itself in.
+// counts are stored: waits for its own stores to complete (the L1 writes
+// through, so they are then in its XCD's L2), then publishes its flag with a
+// device-coherent store.
 __device__ void signal_staged(const KParams& p) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0)
-    __hip_atomic_fetch_add(p.sync + SYNC_STAGED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p.sync + SYNC_STRIDE * blockIdx.x, staged_word(p, xcc_id()),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until all STAGE_BLOCKS staging blocks of this launch are counted in.
-// Every thread calls it.
-__device__ void wait_staged(const KParams& p) {
-  if (threadIdx.x == 0) {
-    uint32_t spins = 0;
-    while (__hip_atomic_load(p.sync + SYNC_STAGED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-           STAGE_BLOCKS) {
+// Waits for the staging blocks whose queues delivery block w bins (w, w +
+// DELIVER_BLOCKS, ...), checks that each ran on this block's XCD (so that
+// its queue stores are in the L2 this block reads through; ERR_XCD where
+// not), then drops this CU's L1 copies (an agent-scope acquire, which
+// invalidates without writing anything back).  Every thread calls it.
+__device__ void wait_staged(const KParams& p, uint32_t w) {
+  static_assert(STAGE_BLOCKS % N_XCD == 0 && DELIVER_BLOCKS % N_XCD == 0,
+                "a queue's staging and delivery blocks are a multiple of N_XCD apart");
+  constexpr uint32_t QPB = STAGE_BLOCKS / DELIVER_BLOCKS;
+  static_assert(QPB <= 64, "one lane per queue");
+  if (threadIdx.x < QPB) {
+    const uint32_t b = w + threadIdx.x * DELIVER_BLOCKS;
+    const uint32_t want = staged_word(p, 0) >> 4;
+    uint32_t spins = 0, v;
+    while (((v = __hip_atomic_load(p.sync + SYNC_STRIDE * b, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT)) >> 4) != (want & 0x0FFFFFFFu)) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins == SPIN_LIMIT) {
         atomicOr(&p.st->error, ERR_TIMEOUT);
         break;
       }
     }
+    if ((v & 0xFu) != xcc_id()) atomicOr(&p.st->error, ERR_XCD);
   }
   __syncthreads();
-}
-
-// Called by every thread of a delivery block of the combined launch when it
-// is done; the last of the n_deliver blocks clears the launch's counters for
-// the next launch (the launch boundary makes that visible to it).
-__device__ void retire_deliver(const KParams& p, uint32_t n_deliver) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t old =
-        __hip_atomic_fetch_add(p.sync + SYNC_RETIRED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == n_deliver - 1) {
-      __hip_atomic_store(p.sync + SYNC_STAGED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(p.sync + SYNC_RETIRED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 template <DeliverPart PART, bool BF16>
@@ -1470,7 +1480,7 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
   if (slot >= p.D) slot -= p.D;
   const uint32_t row = p.st->cur_srow;   // counter row
   const uint32_t D = p.D;
-  constexpr bool COHERENT = PART == DELIVER_SPLIT;   // queues staged by this launch
+  constexpr bool WAITS = PART == DELIVER_SPLIT;   // queues staged by this launch
   constexpr bool LOCAL = PART != DELIVER_REMOTE;
   constexpr bool REMOTE = PART != DELIVER_LOCAL;
   for (uint32_t i = tid; i < p.n_tiles; i += NT) {
@@ -1488,7 +1498,7 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
     uint32_t rk[GATHER_UNROLL];
 #pragma unroll
     for (int v = 0; v < GATHER_UNROLL; ++v)
-      rk[v] = on[v] ? atomicAdd(&l_cnt[tg[v] >> TILE_SHIFT], 1u) : 0u;
+      rk[v] = on[v] ? atomicAdd(&l_cnt[tile_of(p, tg[v])], 1u) : 0u;
     __syncthreads();
     {
       // exclusive scan of the round's per-tile counts into l_pre
@@ -1506,15 +1516,15 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < GATHER_UNROLL; ++v)
-      if (on[v]) s_sorted[l_pre[tg[v] >> TILE_SHIFT] + rk[v]] = Event{tg[v], wq[v]};
+      if (on[v]) s_sorted[l_pre[tile_of(p, tg[v])] + rk[v]] = Event{tg[v], wq[v]};
     __syncthreads();
     for (uint32_t j = tid; j < n; j += NT) {
       const Event ev = s_sorted[j];
-      const uint32_t tile = ev.tgt >> TILE_SHIFT;
+      const uint32_t tile = tile_of(p, ev.tgt);
       const uint64_t pos = static_cast<uint64_t>(l_run[tile]) + (j - l_pre[tile]);
       if (pos < p.bin_cap)
         p.bins[bin_data(p, slot, tile, static_cast<uint32_t>(dw)) + pos] =
-            Event{ev.tgt & (TILE - 1), ev.wq};
+            Event{ev.tgt - tile * p.tile, ev.wq};
       else
         ring_fallback(p, slot, ev.tgt, ev.wq);
     }
@@ -1548,15 +1558,9 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
         const uint32_t k = owner_of<NT / 2>(s_pre, nseg, e);
         const uint64_t x = s_base[k] + (e - s_pre[k]);
         if constexpr (QUEUE) {
-          if constexpr (COHERENT) {
-            const uint64_t ev = load_coherent(reinterpret_cast<const uint64_t*>(q0 + x));
-            tg[v] = static_cast<uint32_t>(ev);
-            wq[v] = static_cast<int32_t>(static_cast<uint32_t>(ev >> 32));
-          } else {
-            const Event ev = q0[x];
-            tg[v] = ev.tgt;
-            wq[v] = ev.wq;
-          }
+          const Event ev = q0[x];
+          tg[v] = ev.tgt;
+          wq[v] = ev.wq;
         } else {
           tg[v] = p.tgt_delay[x] & 0x07FFFFFFu;
           wq[v] = quantize_w(p, load_weight<BF16>(p, x));
@@ -1583,14 +1587,14 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
     }
     take_runs(nsrc, len, std::false_type{});
   }
-  if constexpr (COHERENT) wait_staged(p);
+  if constexpr (WAITS) wait_staged(p, w);
   // the staged remote synapses of delay d: queues w, w + DELIVER_BLOCKS, ...
   if constexpr (REMOTE) {
     uint32_t len = 0;
     if (tid < QPB) {
       s_base[tid] = static_cast<uint64_t>(tid) * DELIVER_BLOCKS * p.stage_cap;
       const uint32_t* c = p.stage_cnt + (d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS;
-      len = COHERENT ? load_coherent(c) : *c;
+      len = *c;
     }
     take_runs(QPB, len, std::true_type{});
   }
@@ -1624,7 +1628,7 @@ __global__ __launch_bounds__(RECV_THREADS) __attribute__((amdgpu_waves_per_eu(6)
 void k_recv_local(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   if (blockIdx.x < STAGE_BLOCKS) {
-    expand_stage_block<BF16, true, WIDE, false>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
+    expand_stage_block<BF16, true, WIDE>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
   } else {
     const uint32_t i = blockIdx.x - STAGE_BLOCKS;
     deliver_block<DELIVER_LOCAL, BF16>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
@@ -1633,7 +1637,7 @@ void k_recv_local(KParams p) {
 
 // The receive side and the delivery of a step in one launch: blocks
 // [0, STAGE_BLOCKS) expand and stage the two-level messages
-// (expand_stage_block) and count themselves in when their queues are
+// (expand_stage_block) and publish their flags when their queues are
 // stored; the rest (block STAGE_BLOCKS + i takes (w, d) =
 // (i mod DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1)) deliver the fired sources'
 // local synapses meanwhile (they need only the fired list), wait for the
@@ -1646,12 +1650,11 @@ __global__ __launch_bounds__(RECV_THREADS) __attribute__((amdgpu_waves_per_eu(6)
 void k_recv_deliver(KParams p) {
   extern __shared__ uint64_t lds_u64[];
   if (blockIdx.x < STAGE_BLOCKS) {
-    expand_stage_block<BF16, true, WIDE, true>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
+    expand_stage_block<BF16, true, WIDE>(p, blockIdx.x, STAGE_BLOCKS, lds_u64);
     signal_staged(p);
   } else {
     const uint32_t i = blockIdx.x - STAGE_BLOCKS;
     deliver_block<DELIVER_SPLIT, BF16>(p, i % DELIVER_BLOCKS, i / DELIVER_BLOCKS + 1, lds_u64);
-    retire_deliver(p, gridDim.x - STAGE_BLOCKS);
   }
 }
 
@@ -1665,15 +1668,15 @@ void k_recv_deliver(KParams p) {
 // that step only if d > k (it is written at step s - d); the others still
 // hold input already consumed.
 __global__ __launch_bounds__(256) void k_flush(KParams p) {
-  __shared__ int32_t s_acc[TILE];
+  __shared__ int32_t s_acc[TILE_MAX];
   const uint32_t tile = blockIdx.x, slot = blockIdx.y;
   const uint32_t next = p.st->slot;
   const uint32_t ahead = slot >= next ? slot - next : slot + p.D - next;
   const uint32_t md = p.D - 1;
-  const uint32_t blk0 = tile << TILE_SHIFT;
-  const uint32_t nt = min(TILE, p.N - blk0);
+  const uint32_t blk0 = tile * p.tile;
+  const uint32_t nt = min(p.tile, p.N - blk0);
   const uint64_t row = static_cast<uint64_t>(slot) * p.ring_stride + blk0;
-  for (uint32_t i = threadIdx.x; i < TILE; i += 256) s_acc[i] = i < nt ? p.ovf[row + i] : 0;
+  for (uint32_t i = threadIdx.x; i < p.tile; i += 256) s_acc[i] = i < nt ? p.ovf[row + i] : 0;
   __syncthreads();
   for (uint32_t d = ahead + 1; d <= md; ++d) {
     for (uint32_t w = 0; w < DELIVER_BLOCKS; ++w) {
@@ -1720,7 +1723,23 @@ __global__ __launch_bounds__(256) void k_pois_lut(KParams p, uint8_t* lut) {
 // ---------------------------------------------------------------------------
 // launchers
 
-uint32_t tiles_of(uint32_t n) { return (n + TILE - 1) / TILE; }
+uint32_t tile_size(uint32_t n, uint32_t requested) {
+  if (requested) return requested;
+  const uint32_t per = (n + TILE_MIN_COUNT - 1) / TILE_MIN_COUNT;
+  const uint32_t t = (per + TILE_ALIGN - 1) / TILE_ALIGN * TILE_ALIGN;
+  return std::min(std::max(t, TILE_MIN_DEFAULT), TILE_MAX);
+}
+
+void tile_divider(uint32_t t, uint32_t* magic, uint32_t* shift) {
+  // c = ceil(log2 t); magic = ceil(2^(31 + c) / t) < 2^32.  For x < 2^27 the
+  // error of x * magic / 2^(31 + c) against x / t is below 2^27 / 2^(31 + c)
+  // <= 1 / (16 t), too small to carry x / t past the next integer.
+  uint32_t c = 0;
+  while ((1u << c) < t) ++c;
+  const uint64_t k = uint64_t(1) << (31 + c);
+  *magic = static_cast<uint32_t>((k + t - 1) / t);
+  *shift = c - 1;
+}
 
 // Optional timing marks: when marks is non-null, events marks[2k] and
 // marks[2k + 1] are recorded on the stream around each launch of kernel kind

@@ -63,7 +63,8 @@ Layout layout(const snn_params* p) {
     o = align256(o + bytes);
     return at;
   };
-  const uint64_t D = p->max_delay + 1, md = p->max_delay, tiles = tiles_of(p->n_neurons);
+  const uint32_t T = tile_size(p->n_neurons, p->tile_neurons);
+  const uint64_t D = p->max_delay + 1, md = p->max_delay, tiles = (p->n_neurons + T - 1) / T;
   L.st = take(sizeof(DevState));
   L.tickets = take(sizeof(uint32_t) * 2);
   L.sync = take(sizeof(uint32_t) * SYNC_WORDS);
@@ -115,10 +116,20 @@ int input_shift(float bound) {
   return f;
 }
 
-snn_status check_params(const snn_params* p) {
-  if (!p) return fail(SNN_ERR_INVALID_ARG, "params is NULL");
+snn_status check_tile(const snn_params* p) {
   if (p->n_neurons == 0 || p->n_neurons > SNN_MAX_NEURONS)
     return fail(SNN_ERR_INVALID_ARG, "n_neurons=%u outside [1, 2^27]", p->n_neurons);
+  const uint32_t t = p->tile_neurons;
+  if (t && (t % TILE_ALIGN || t > TILE_MAX))
+    return fail(SNN_ERR_INVALID_ARG, "tile_neurons=%u is not a multiple of %u in [%u, %u]", t,
+                TILE_ALIGN, TILE_ALIGN, TILE_MAX);
+  return SNN_OK;
+}
+
+snn_status check_params(const snn_params* p) {
+  if (!p) return fail(SNN_ERR_INVALID_ARG, "params is NULL");
+  snn_status st = check_tile(p);
+  if (st != SNN_OK) return st;
   if (p->n_partitions == 0 || p->n_partitions > SNN_MAX_PARTITIONS)
     return fail(SNN_ERR_INVALID_ARG, "n_partitions=%u outside [1, 65535]", p->n_partitions);
   if (p->gpus_per_node == 0 || p->gpus_per_node > SNN_MAX_GPUS_PER_NODE)
@@ -236,7 +247,9 @@ snn_status init_ctx(snn_ctx* c, const snn_params* params, const snn_network_dev*
   k.g_magic = k.G >= 2 ? static_cast<uint32_t>(((uint64_t(1) << 32) + k.G - 1) / k.G) : 0u;
   k.D = params->max_delay + 1;
   k.n_nodes = n_nodes_of(params);
-  k.n_tiles = tiles_of(params->n_neurons);
+  k.tile = tile_size(params->n_neurons, params->tile_neurons);
+  tile_divider(k.tile, &k.tile_magic, &k.tile_shift);
+  k.n_tiles = (params->n_neurons + k.tile - 1) / k.tile;
   k.tile0 = 0;
   k.tile_end = k.n_tiles;
   k.lo = 0;
@@ -464,8 +477,8 @@ static hipError_t launch_step_partitioned(const KParams& kp, int mode, hipStream
     KParams q = kp;
     q.lo = start[p];
     q.hi = start[p + 1];
-    q.tile0 = q.lo / TILE;
-    q.tile_end = (q.hi - 1) / TILE + 1;
+    q.tile0 = q.lo / kp.tile;
+    q.tile_end = (q.hi - 1) / kp.tile + 1;
     q.step_ends = p == last ? 1u : 0u;
     e = launch_update(q, s, nullptr, fused);
   }
@@ -702,6 +715,10 @@ static snn_status sync_and_check(snn_handle h, DevState* out) {
     return fail(SNN_ERR_HIP, "receive entry without a matching destination partition");
   if (st.error & ERR_TIMEOUT)
     return fail(SNN_ERR_HIP, "a wait between blocks of one launch timed out");
+  if (st.error & ERR_XCD)
+    return fail(SNN_ERR_UNSUPPORTED, "the one-launch receive side found a block on another XCD "
+                "than its index implies (workgroups are not dealt out to the XCDs in turn on "
+                "this device); use the two-launch receive side (recv_merged = 0)");
   if (st.error)
     return fail(SNN_ERR_CAPACITY, "device capacity overflow (bits 0x%x: 1 bucket, 2 receive "
                 "list, 4 flat list, 8 spike log)", st.error);
@@ -715,10 +732,15 @@ snn_status snn_sync(snn_handle h) {
 
 uint64_t snn_time(snn_handle h) { return h ? h->t_host : 0; }
 
-void snn_bin_geometry(uint32_t* tile_neurons, uint32_t* deliver_blocks, uint32_t* stage_blocks) {
-  if (tile_neurons) *tile_neurons = TILE;
+snn_status snn_bin_geometry(const snn_params* params, uint32_t* tile_neurons,
+                            uint32_t* deliver_blocks, uint32_t* stage_blocks) {
+  if (!params) return fail(SNN_ERR_INVALID_ARG, "params is NULL");
+  snn_status st = check_tile(params);
+  if (st != SNN_OK) return st;
+  if (tile_neurons) *tile_neurons = tile_size(params->n_neurons, params->tile_neurons);
   if (deliver_blocks) *deliver_blocks = DELIVER_BLOCKS;
   if (stage_blocks) *stage_blocks = STAGE_BLOCKS;
+  return SNN_OK;
 }
 
 snn_status snn_ring_events(snn_handle h, uint64_t* n) {

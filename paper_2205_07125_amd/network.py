@@ -18,7 +18,7 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_P)
 
 
-def default_caps(wl, host) -> tuple[int, int]:
+def default_caps(wl, host, tile_neurons: int = 0) -> tuple[int, int]:
     """Bin and staging capacities sized at four times the expected events per
     bin at the workload's highest rate (50 Hz assumed for LIF-driven spikes);
     events beyond them take the dense-ring path, so these set speed, not
@@ -30,7 +30,7 @@ def default_caps(wl, host) -> tuple[int, int]:
     e_local = spikes * local
     e_remote = spikes * (outdeg - local)
     md = wl.max_delay
-    tile, deliver_blocks, stage_blocks = _abi.snn_bin_geometry()
+    tile, deliver_blocks, stage_blocks = _abi.snn_bin_geometry(wl.n_neurons, tile_neurons)
     tiles = (wl.n_neurons + tile - 1) // tile
     per_bin = (e_local + e_remote) / (md * deliver_blocks * tiles)
     per_queue = e_remote / (md * stage_blocks)

@@ -24,10 +24,12 @@ class Simulation:
     def __init__(self, wl, host: HostNetwork | None = None, device: str = "cuda",
                  log_steps: int | None = None, log_cap: int | None = None,
                  bucket_off=None, recv_off=None, bin_cap: int | None = None,
-                 stage_cap: int | None = None, verbose: bool = False, static: bool = False):
+                 stage_cap: int | None = None, verbose: bool = False, static: bool = False,
+                 tile_neurons: int = 0):
         """static: the handle comes from snn_create_static (workspace in the
         library's static device scratch, nothing allocated by the call; one such
-        handle per device at a time, small networks only)."""
+        handle per device at a time, small networks only).  tile_neurons: neurons
+        per tile (0: the library's default)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the simulation runs only in libsnn's HIP kernels")
@@ -64,7 +66,8 @@ class Simulation:
         self.ring = torch.zeros(D * self.ring_stride, dtype=torch.float32, device=self.device)
 
         dp = derived_params(wl)
-        cb, cs = default_caps(wl, host)
+        cb, cs = default_caps(wl, host, tile_neurons)
+        self.tile_neurons = _abi.snn_bin_geometry(N, tile_neurons)[0]
         bin_cap = cb if bin_cap is None else bin_cap
         stage_cap = cs if stage_cap is None else stage_cap
         forced = bool(wl.forced)
@@ -83,7 +86,7 @@ class Simulation:
             raster_period=max(wl.period_steps, 1), raster_on=wl.on_steps,
             bucket_total=int(bucket_off[-1]), recv_total=int(recv_off[-1]),
             log_steps=log_steps, input_bound=host.input_bound, log_cap=log_cap, bin_cap=bin_cap,
-            stage_cap=stage_cap)
+            stage_cap=stage_cap, tile_neurons=tile_neurons)
         self.ws_bytes = _abi.snn_workspace_size(self.params)
         self.static = static
         if not static:

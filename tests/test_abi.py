@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2205_07125_amd import _abi
@@ -81,9 +82,38 @@ def test_input_bound_too_large_unsupported():
 
 
 def test_bin_geometry():
-    tile, deliver_blocks, stage_blocks = _abi.snn_bin_geometry()
-    assert tile > 0 and tile & (tile - 1) == 0
+    tile, deliver_blocks, stage_blocks = _abi.snn_bin_geometry(5_000_000)
     assert deliver_blocks > 0 and stage_blocks % deliver_blocks == 0
+    # default: 8192, or the neurons spread over 512 tiles (rounded up to 64, at least 2048)
+    assert tile == 8192
+    assert _abi.snn_bin_geometry(5_800_000)[0] == 8192
+    assert _abi.snn_bin_geometry(1_000_000)[0] == 2048
+    assert _abi.snn_bin_geometry(3_000_000)[0] == 5888 and -(-3_000_000 // 5888) <= 512
+    assert _abi.snn_bin_geometry(1_000)[0] == 2048
+    assert _abi.snn_bin_geometry(1_000, 64)[0] == 64
+    assert _abi.snn_bin_geometry(100_000_000)[0] == 8192
+    assert _abi.snn_bin_geometry(5_000_000, 8192)[0] == 8192
+    for bad in (100, 8256, 16384):
+        with pytest.raises(_abi.SNNError):
+            _abi.snn_bin_geometry(5_000_000, bad)
+
+
+def test_tile_divider_formula():
+    """floor(x / T) as umulhi(x, M) >> (c - 1), M = ceil(2^(31+c) / T), c =
+    ceil(log2 T): exact for every neuron id below 2^27 (checked at the
+    multiples of T and their neighbours, where an error would show first, and
+    at random ids)."""
+    rng = np.random.default_rng(3)
+    for t in list(range(64, 8193, 64)):
+        c = (t - 1).bit_length()
+        m = -(-(1 << (31 + c)) // t)
+        assert m < 1 << 32
+        q = np.arange(0, (1 << 27) // t + 2, dtype=np.uint64)
+        x = np.concatenate([q * t, q * t + t - 1, q * t - 1, rng.integers(0, 1 << 27, 4096,
+                                                                        dtype=np.uint64)])
+        x = x[(x < (1 << 27))]
+        got = ((x * np.uint64(m)) >> np.uint64(32)) >> np.uint64(c - 1)
+        assert np.array_equal(got, x // np.uint64(t)), t
 
 
 def test_nonmonotone_poisson_table_rejected():

@@ -81,12 +81,13 @@ def _same_routes(sim, orc, wl, where, mode=ROUTE_BOTH):
 
 
 def _lockstep(wl, n_steps, route_every, state_every, mode=ROUTE_BOTH, fused=False,
-              fp64_bound=1e-4, part_map=None):
+              fp64_bound=1e-4, part_map=None, tile_neurons=0):
     """fused: each step as snn_step_route + snn_deliver (two-level routing in
     the update kernel) instead of snn_step, snn_route, snn_deliver.
     fp64_bound: largest |u - u_fp64| allowed (mV); None reports it only.
-    part_map: explicit neuron -> partition map of the network."""
-    sim, orc = _pair(wl, part_map=part_map, log_steps=n_steps)
+    part_map: explicit neuron -> partition map of the network.
+    tile_neurons: neurons per tile (0: the library's default)."""
+    sim, orc = _pair(wl, part_map=part_map, log_steps=n_steps, tile_neurons=tile_neurons)
     stats_o = np.zeros((n_steps, 7), np.uint64)
     fired_o = []
     for t in range(n_steps):
@@ -196,16 +197,31 @@ def test_link_traffic_matches_fired_sources(name):
 
 
 def test_fused_route_many_spikes_per_tile():
-    """60 % of one tile firing per step: more fired neurons than a routing batch
-    holds (512) and more pairs than a window (1,024), so the batch and window
-    loops of the fused routing run, with runs of one node cut by a window's
-    end; each node gets more messages than one expansion round loads (2,048)
-    and more entries than the staging buffer holds (4,096)."""
+    """60 % of one tile firing per step (the whole network as one 8,192-neuron
+    tile): more fired neurons than a routing batch holds (512) and more pairs
+    than a window (1,024), so the batch and window loops of the fused routing
+    run, with runs of one node cut by a window's end; each node gets more
+    messages than one expansion round loads (2,048) and more entries than the
+    staging buffer holds (4,096)."""
     wl = synth.get_workload("tiny").replace(name="tiny_dense", forced=1, rate_on_hz=6000.0,
                                             rate_off_hz=6000.0, period_steps=1, on_steps=1)
-    _, _, stats = _lockstep(wl, 30, route_every=1, state_every=10, mode=ROUTE_BOTH, fused=True)
+    _, _, stats = _lockstep(wl, 30, route_every=1, state_every=10, mode=ROUTE_BOTH, fused=True,
+                            tile_neurons=8192)
     assert stats[:, 0].min() > 2048
     assert stats[:, 6].min() > 2 * 2 * 4096    # two nodes, each over two buffers
+
+
+@pytest.mark.parametrize("tile", [64, 320, 1216, 8192])
+def test_tile_sizes_match_oracle(tile):
+    """Tiles of 64 neurons (64 tiles), of sizes that are no power of two and
+    leave a partial last tile (320: 13 tiles, the last of 256 neurons; 1,216:
+    4 tiles, the last of 448), and the whole network in one tile: the update's
+    partial quads, the division of target ids by the tile size in the delivery,
+    and the look-back over many tiles, in both step forms."""
+    wl = synth.get_workload("tiny_active")
+    _lockstep(wl, 40, route_every=7, state_every=20, mode=ROUTE_BOTH, tile_neurons=tile)
+    _lockstep(wl, 40, route_every=7, state_every=20, mode=ROUTE_TWO_LEVEL, fused=True,
+              tile_neurons=tile)
 
 
 def test_unfused_fallback_many_nodes():
