@@ -87,17 +87,29 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def _one_thread():
+    # each oracle process computes on one thread; the seeded generator's
+    # OpenMP set-up is kept to one as well (read when libgomp loads)
+    os.environ["OMP_NUM_THREADS"] = "1"
+
+
 def cpu_baseline(wl_full, seconds_budget=10.0):
     """The oracle (plain C, FP64 + binary32 trajectories, one thread per
     process) on the same structure at 1/100 of the neurons (same in-degree,
     partitions, rate): one process alone, then one process per available
-    core at once, each on its own seeded network; value = the all-core rate."""
+    core at once, each on its own seeded network; value = the all-core rate.
+    The processes are started fresh (spawn), so they inherit no OpenMP or
+    GPU runtime state of this process."""
     import multiprocessing as mp
     n = max(wl_full.n_neurons // 100, 1000)
     name = wl_full.name
-    ev1, st1, dt1 = _oracle_sample((name, n, 0, seconds_budget))
+    ctx = mp.get_context("spawn")
+    log(f"cpu baseline (oracle): one process on {n:,} neurons for {seconds_budget:.0f} s")
+    with ctx.Pool(1, initializer=_one_thread) as pool:
+        ev1, st1, dt1 = pool.apply(_oracle_sample, ((name, n, 0, seconds_budget),))
     cores = min(len(os.sched_getaffinity(0)), 16)
-    with mp.get_context("fork").Pool(cores) as pool:
+    log(f"cpu baseline: {ev1 / dt1:.3g} events/s on one process; now {cores} processes")
+    with ctx.Pool(cores, initializer=_one_thread) as pool:
         res = pool.map(_oracle_sample, [(name, n, i, seconds_budget) for i in range(cores)])
     ev = sum(r[0] for r in res)
     steps = sum(r[1] for r in res)
@@ -217,9 +229,16 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import synth
+    wl0 = synth.get_workload(args.workload)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # first, before this process starts OpenMP threads or touches the GPU
+        cpu = cpu_baseline(wl0.scaled(args.neurons) if args.neurons else wl0)
+        log(f"cpu baseline: {cpu['value']:.3g} events/s on {cpu['cores']} processes")
+
+    import torch
     from paper_2205_07125_amd import SNN_ROUTE_FLAT, SNN_ROUTE_TWO_LEVEL, HostNetwork, Simulation
     from paper_2205_07125_amd.sim import Simulation as _Sim  # noqa: F401
 
@@ -439,9 +458,8 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
