@@ -238,11 +238,11 @@ constexpr uint32_t ARRIVE_GROUPS = UPDATE_THREADS / ARRIVE_LANES;
 constexpr int ARRIVE_UNROLL = 10;
 constexpr int ROUTE_UNROLL = 8;           // destination-list loads in flight per thread
 // Two-level routing inside the update kernel (one tile's fired neurons per
-// block): window of pairs, and the node count up to which its counters fit
-// the LDS the update leaves free.
-constexpr uint32_t FUSED_ROUTE_WINDOW = 1024;
+// block): the node count up to which its counters fit the LDS the update
+// leaves free, and destination-list loads in flight per thread (the window
+// of pairs is sized per network, fused_window).
 constexpr uint32_t FUSED_MAX_NODES = 512;
-constexpr int FUSED_ROUTE_UNROLL = FUSED_ROUTE_WINDOW / UPDATE_THREADS;   // one load round per window
+constexpr int FUSED_ROUTE_UNROLL = 3;
 
 // ---------------------------------------------------------------------------
 // route
@@ -557,10 +557,20 @@ __device__ uint32_t lookback_resolve(uint64_t* lb, uint32_t b, uint32_t agg, uin
 // launch is needed; the LDS of the input sums and the Poisson lookup, free by
 // then, holds the routing's arrays.
 static_assert(UPDATE_NPT % 4 == 0 && UPDATE_NPT <= 32, "fire bits of a thread fit 32 bits");
-constexpr size_t UPDATE_BIG_LDS = TILE_MAX * sizeof(int32_t) + POIS_LUT_SIZE;
-static_assert(route_lds_bytes(UPDATE_THREADS, FUSED_ROUTE_WINDOW, FUSED_MAX_NODES, false) <=
-                  UPDATE_BIG_LDS,
-              "the fused routing's arrays fit the update's LDS");
+// The input sums and the Poisson lookup, plus room that lets the routing's
+// window hold a tile's usual fired neurons at once (three blocks per CU still
+// fit the CU's LDS).
+constexpr size_t UPDATE_BIG_LDS = TILE_MAX * sizeof(int32_t) + POIS_LUT_SIZE + 4096;
+// Pairs per routing window inside the update: as many as fit UPDATE_BIG_LDS
+// beside the per-source and per-node arrays of n_nodes nodes (a multiple of
+// 64).  On the share (250 nodes) 1,536 pairs, about eight sources' lists, so
+// that a tile's fired neurons (about four) are routed in one window.
+__host__ __device__ constexpr uint32_t fused_window(uint32_t n_nodes) {
+  const size_t fixed = route_lds_bytes(UPDATE_THREADS, 0, n_nodes, false);
+  const size_t per_pair = route_lds_bytes(UPDATE_THREADS, 1, n_nodes, false) - fixed;
+  return static_cast<uint32_t>((UPDATE_BIG_LDS - fixed) / per_pair) / 64 * 64;
+}
+static_assert(fused_window(FUSED_MAX_NODES) >= 1024, "the fused routing's arrays fit the update's LDS");
 // PERSIST: a grid smaller than the launch's tiles, whose blocks take further
 // tiles by ticket (a separate instantiation: the loop carried across tiles
 // costs registers, 106 VGPRs against 73, so two blocks per CU instead of
@@ -858,7 +868,7 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   if constexpr (ROUTE) {
     // the tile's fired neurons, UPDATE_THREADS at a time, routed into the
     // bucket set of this step
-    const RouteLds L = route_lds(s_big, UPDATE_THREADS, FUSED_ROUTE_WINDOW, p.n_nodes, false);
+    const RouteLds L = route_lds(s_big, UPDATE_THREADS, fused_window(p.n_nodes), p.n_nodes, false);
     uint32_t* bcnt = bucket_counts(p, t32 & 1u);
     uint64_t l1 = 0, l2 = 0;
     for (uint32_t b0 = 0; b0 < btot; b0 += UPDATE_THREADS) {

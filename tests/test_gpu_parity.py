@@ -199,7 +199,8 @@ def test_link_traffic_matches_fired_sources(name):
 def test_fused_route_many_spikes_per_tile():
     """60 % of one tile firing per step (the whole network as one 8,192-neuron
     tile): more fired neurons than a routing batch holds (512) and more pairs
-    than a window (1,024), so the batch and window loops of the fused routing
+    than a window holds (1,728 at this node count), so the batch and window
+    loops of the fused routing
     run, with runs of one node cut by a window's end; each node gets more
     messages than one expansion round loads (2,048) and more entries than the
     staging buffer holds (4,096)."""
