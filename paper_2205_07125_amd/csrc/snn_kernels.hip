@@ -355,7 +355,10 @@ constexpr uint32_t NARROW_G = 8;
 // node) then reserves the node's bucket space.  A window has at most as many
 // messages as pairs, so the stage never overflows.  Every thread of the block
 // calls it; it ends with a barrier.
-template <uint32_t NT, int U, bool WIDE>
+// PRE: the caller may have loaded a source's list bounds and node already:
+// then L.j0 holds j0 | len << 32 with bit 63 set and L.own its node (L.j0
+// of the other sources is non-negative).
+template <uint32_t NT, int U, bool WIDE, bool PRE = false>
 __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uint32_t* bcnt,
                             uint64_t& l1, uint64_t& l2) {
   __shared__ uint32_t l_total, s_prev_node;
@@ -364,11 +367,18 @@ __device__ void route_batch(const KParams& p, const RouteLds& L, uint32_t n, uin
   const uint32_t G = p.G;
   uint32_t len = 0;
   if (tid < n) {
-    const uint32_t s = L.src[tid];
-    const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
-    L.own[tid] = static_cast<uint16_t>(node_of(p, static_cast<uint32_t>(p.part[s])));
-    L.j0[tid] = j0;
-    len = static_cast<uint32_t>(j1 - j0);
+    const int64_t pre = PRE ? L.j0[tid] : 0;
+    if (pre < 0) {
+      const uint64_t v = static_cast<uint64_t>(pre);
+      L.j0[tid] = static_cast<int64_t>(v & 0xFFFFFFFFull);
+      len = static_cast<uint32_t>(v >> 32) & 0x7FFFFFFFu;
+    } else {
+      const uint32_t s = L.src[tid];
+      const int64_t j0 = p.vp_ptr[s], j1 = p.vp_ptr[s + 1];
+      L.own[tid] = static_cast<uint16_t>(node_of(p, static_cast<uint32_t>(p.part[s])));
+      L.j0[tid] = j0;
+      len = static_cast<uint32_t>(j1 - j0);
+    }
   }
   uint32_t tot;
   const uint32_t ex = block_excl_scan(len, s_wsum, &tot);
@@ -746,6 +756,12 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
   if (p.forced) thr_raster = phase < p.raster_on ? p.raster_on_thr : p.raster_off_thr;
 
   uint32_t fire_bits = 0;   // bit 4q + k: neuron k of quad q fired
+  // With ROUTE, the list bounds and node of the thread's first fired neuron,
+  // loaded as soon as it fires, so that they arrive while the block finishes
+  // its other quads and the compaction (the routing then skips that round
+  // trip for it).  Pair indices are below 2^32 (checked at create).
+  uint32_t pf_id = 0xFFFFFFFFu, pf_part = 0;
+  int64_t pf_j0 = 0, pf_j1 = 0;
   // One quad per iteration, the next quad's loads issued before this quad's
   // arithmetic (not unrolled: keeps the kernel within 128 VGPRs, two blocks
   // per CU).
@@ -814,6 +830,15 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) cnt_q += __popcll(__ballot((fire_bits >> (4 * q + k)) & 1u));
     if (lane == 0) s_cnt[q][wave] = cnt_q;
+    if constexpr (ROUTE) {
+      const uint32_t qb = (fire_bits >> (4 * q)) & 0xFu;
+      if (qb && pf_id == 0xFFFFFFFFu) {
+        pf_id = i0 + static_cast<uint32_t>(__ffs(qb) - 1);
+        pf_j0 = p.vp_ptr[pf_id];
+        pf_j1 = p.vp_ptr[pf_id + 1];
+        pf_part = static_cast<uint32_t>(p.part[pf_id]);
+      }
+    }
     if (tile_full) {
       if (l0 < T) {
         *reinterpret_cast<float4*>(p.u + i0) = make_float4(uu[0], uu[1], uu[2], uu[3]);
@@ -873,10 +898,20 @@ __global__ __launch_bounds__(UPDATE_THREADS) void k_update(KParams p) {
     uint64_t l1 = 0, l2 = 0;
     for (uint32_t b0 = 0; b0 < btot; b0 += UPDATE_THREADS) {
       for_each_fired([&](uint32_t r, uint32_t id) {
-        if (r - b0 < UPDATE_THREADS) L.src[r - b0] = id;
+        if (r - b0 < UPDATE_THREADS) {
+          L.src[r - b0] = id;
+          if (id == pf_id) {
+            L.j0[r - b0] = static_cast<int64_t>(static_cast<uint64_t>(pf_j0) |
+                                                (static_cast<uint64_t>(pf_j1 - pf_j0) << 32) |
+                                                (uint64_t(1) << 63));
+            L.own[r - b0] = static_cast<uint16_t>(node_of(p, pf_part));
+          } else {
+            L.j0[r - b0] = 0;
+          }
+        }
       });
       __syncthreads();
-      route_batch<UPDATE_THREADS, FUSED_ROUTE_UNROLL, false>(
+      route_batch<UPDATE_THREADS, FUSED_ROUTE_UNROLL, false, true>(
           p, L, min(btot - b0, static_cast<uint32_t>(UPDATE_THREADS)), bcnt, l1, l2);
     }
     uint64_t* sc = stat_copy(p, srow);
@@ -1493,6 +1528,11 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
   constexpr bool WAITS = PART == DELIVER_SPLIT;   // queues staged by this launch
   constexpr bool LOCAL = PART != DELIVER_REMOTE;
   constexpr bool REMOTE = PART != DELIVER_LOCAL;
+  // queue lengths, when the queues are complete at launch: loaded with the
+  // sub-bin counts below, in the same round trip
+  const uint32_t* qcnt = p.stage_cnt + (d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS;
+  uint32_t qlen = 0;
+  if (PART != DELIVER_SPLIT && REMOTE && tid < QPB) qlen = *qcnt;
   for (uint32_t i = tid; i < p.n_tiles; i += NT) {
     l_run[i] = LOCAL ? 0u : p.bin_cnt[subbin(p, slot, i, d, w)];
     l_cnt[i] = 0;
@@ -1600,13 +1640,11 @@ __device__ void deliver_block(const KParams& p, uint32_t w, uint32_t d, uint64_t
   if constexpr (WAITS) wait_staged(p, w);
   // the staged remote synapses of delay d: queues w, w + DELIVER_BLOCKS, ...
   if constexpr (REMOTE) {
-    uint32_t len = 0;
     if (tid < QPB) {
       s_base[tid] = static_cast<uint64_t>(tid) * DELIVER_BLOCKS * p.stage_cap;
-      const uint32_t* c = p.stage_cnt + (d - 1) * STAGE_BLOCKS + w + tid * DELIVER_BLOCKS;
-      len = *c;
+      if (PART == DELIVER_SPLIT) qlen = *qcnt;
     }
-    take_runs(QPB, len, std::true_type{});
+    take_runs(QPB, qlen, std::true_type{});
   }
 
   // publish this block's counts for slot `slot`, every tile (zeros included)
