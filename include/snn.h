@@ -327,7 +327,11 @@ typedef struct {
   uint32_t recv_merged;     /* 0: the receive side of a whole step is two launches
                                (expansion and staging beside the own-partition delivery,
                                then the received synapses); 1: one launch, whose
-                               delivery blocks wait for its staging blocks */
+                               delivery blocks wait for its staging blocks and read
+                               their queues through the L2 of the XCD they share
+                               (workgroups are dealt out to the XCDs in turn); where a
+                               queue turns out to have been staged on another XCD, the
+                               next synchronising call reports SNN_ERR_UNSUPPORTED */
 } snn_tuning;
 
 /* Sets / reads the handle's launch shapes.  Setting synchronises the stream
