@@ -18,8 +18,8 @@ enum : uint32_t {
   ERR_ROUTE = 16u,   // a receive entry names a partition its source does not reach
   ERR_TIMEOUT = 32u, // a wait between blocks of one launch gave up (a block it waited for
                      // never arrived)
-  ERR_XCD = 64u      // a block of the one-launch receive side ran on another XCD than
-                     // its index implies (its hand-off would not be coherent)
+  ERR_XCD = 64u      // a queue of the one-launch receive side was staged on another XCD
+                     // than the block that bins it (the hand-off needs a shared L2)
 };
 
 // Words of the in-launch synchronisation area (KParams::sync), each on a

@@ -716,9 +716,10 @@ static snn_status sync_and_check(snn_handle h, DevState* out) {
   if (st.error & ERR_TIMEOUT)
     return fail(SNN_ERR_HIP, "a wait between blocks of one launch timed out");
   if (st.error & ERR_XCD)
-    return fail(SNN_ERR_UNSUPPORTED, "the one-launch receive side found a block on another XCD "
-                "than its index implies (workgroups are not dealt out to the XCDs in turn on "
-                "this device); use the two-launch receive side (recv_merged = 0)");
+    return fail(SNN_ERR_UNSUPPORTED, "the one-launch receive side found a queue staged on "
+                "another XCD than the block that bins it (workgroups are not dealt out to the "
+                "XCDs in turn on this device); use the two-launch receive side "
+                "(recv_merged = 0)");
   if (st.error)
     return fail(SNN_ERR_CAPACITY, "device capacity overflow (bits 0x%x: 1 bucket, 2 receive "
                 "list, 4 flat list, 8 spike log)", st.error);
