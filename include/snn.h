@@ -326,7 +326,7 @@ typedef struct {
                                256 receive-side blocks allow, 1 = one block per node */
   uint32_t recv_merged;     /* 0: the receive side of a whole step is two launches
                                (expansion and staging beside the own-partition delivery,
-                               then the received synapses); 1: one launch, whose
+                               then the received synapses); 1 (the default): one launch, whose
                                delivery blocks wait for its staging blocks and read
                                their queues through the L2 of the XCD they share
                                (workgroups are dealt out to the XCDs in turn); where a

@@ -19,7 +19,8 @@
 //
 // A whole step is two or three launches: k_update<true> (update, compaction
 // and the tile's own two-level routing, which overlaps the look-back), then
-// the receive side in one of two forms (snn_tuning.recv_merged):
+// the receive side in one of two forms (snn_tuning.recv_merged, one launch
+// by default):
 //   k_recv_local + k_deliver_remote: expansion and staging beside the
 //     own-partition delivery, then the staged remote synapses in a launch of
 //     their own, appended after the counts the local part published;
@@ -1479,8 +1480,10 @@ __device__ void signal_staged(const KParams& p) {
 // Waits for the staging blocks whose queues delivery block w bins (w, w +
 // DELIVER_BLOCKS, ...), checks that each ran on this block's XCD (so that
 // its queue stores are in the L2 this block reads through; ERR_XCD where
-// not), then drops this CU's L1 copies (an agent-scope acquire, which
-// invalidates without writing anything back).  Every thread calls it.
+// not), then drops this CU's L1 copies (buffer_inv sc0: the vector L1 only).
+// An agent-scope acquire (buffer_inv sc1) would also invalidate the XCD's
+// L2, which then holds the sub-bin runs being written: measured, it made the
+// remote part three times slower.  Every thread calls it.
 __device__ void wait_staged(const KParams& p, uint32_t w) {
   static_assert(STAGE_BLOCKS % N_XCD == 0 && DELIVER_BLOCKS % N_XCD == 0,
                 "a queue's staging and delivery blocks are a multiple of N_XCD apart");
@@ -1501,7 +1504,7 @@ __device__ void wait_staged(const KParams& p, uint32_t w) {
     if ((v & 0xFu) != xcc_id()) atomicOr(&p.st->error, ERR_XCD);
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  asm volatile("buffer_inv sc0" ::: "memory");
 }
 
 template <DeliverPart PART, bool BF16>

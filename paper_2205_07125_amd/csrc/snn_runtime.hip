@@ -255,6 +255,7 @@ snn_status init_ctx(snn_ctx* c, const snn_params* params, const snn_network_dev*
   k.lo = 0;
   k.hi = k.N;
   k.step_ends = 1;
+  k.recv_merged = 1;   // the receive side as one launch (snn_tuning)
   k.n_ref = params->n_ref;
   k.ring_stride = snn_ring_stride(params->n_neurons);
   k.alpha = params->alpha;

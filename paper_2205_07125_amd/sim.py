@@ -144,8 +144,14 @@ class Simulation:
             starts[0] = 0
         _abi.snn_run_partitioned(self.h, n_steps, mode, use_graph, starts)
 
-    def set_tuning(self, update_blocks: int = 0, recv_split: int = 0, recv_merged: int = 0):
-        _abi.snn_set_tuning(self.h, update_blocks, recv_split, recv_merged)
+    def set_tuning(self, update_blocks: int | None = None, recv_split: int | None = None,
+                   recv_merged: int | None = None):
+        """Sets the given launch shapes (snn_tuning); the others keep their values."""
+        cur = self.tuning()
+        new = {k: cur[k] if v is None else v for k, v in
+               (("update_blocks", update_blocks), ("recv_split", recv_split),
+                ("recv_merged", recv_merged))}
+        _abi.snn_set_tuning(self.h, **new)
 
     def tuning(self) -> dict:
         return _abi.snn_get_tuning(self.h)

@@ -118,11 +118,14 @@ def test_recv_split_matches(name, split):
 @pytest.mark.parametrize("name", ["tiny_active", "batched", "paper_share"])
 def test_recv_merged_matches(name):
     """The receive side as one launch (delivery blocks wait for the staging
-    blocks and read their queues device-coherently) against two launches."""
+    blocks on their XCD and read their queues through its L2; the default)
+    against two launches."""
     wl = _wl(name)
     n = 60
     a, b = _sims(wl, n, recv_merged=1)
+    a.set_tuning(recv_merged=0)
     b.set_tuning(recv_merged=1)
+    assert a.tuning()["recv_merged"] == 0 and b.tuning()["recv_merged"] == 1
     a.run(n, TWO_LEVEL, use_graph=False)
     b.run(n, TWO_LEVEL, use_graph=True)
     _same(a, b, wl, n, "one receive launch")
