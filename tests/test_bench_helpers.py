@@ -78,3 +78,18 @@ def test_pmc_summary_scales_by_the_copy(bench, tmp_path, capsys):
     bench.pmc_summary(fetch, write, cf, cw, 1 << 20, "other", str(out))
     assert set(json.load(open(out))) == {"demo", "other"}
     capsys.readouterr()
+
+
+def test_cpu_baseline_runs_in_spawned_workers():
+    """The oracle leg starts its workers fresh (spawn), one OpenMP thread each,
+    and reports both legs; a short budget on the tiny network."""
+    import sys
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import bench as bench_main
+    import synth
+    r = bench_main.cpu_baseline(synth.get_workload("tiny"), seconds_budget=0.3)
+    assert r["kind"] == "oracle" and r["unit"] == "synaptic events/s"
+    assert r["value"] > 0 and r["single_thread_value"] > 0
+    assert 1 <= r["cores"] <= 16
+    assert "processes of one thread each" in r["sample"]
