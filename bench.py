@@ -398,7 +398,7 @@ def main():
             ent = tj.get(symbol.get(k, k))
             v["traffic_bytes"] = ent["bytes_per_launch"] if ent and ent.get("kernel_hash") == h else None
         traffic = kernels[dom].get("traffic_bytes")
-    # whole step (survey's per-step algorithmic bytes, ring RMW excluded)
+    # whole step: the sum of the launches' algorithmic bytes defined above
     step_bytes = sum(v["alg_bytes"] for v in kernels.values())
     out = {
         "metric": "synaptic events/s + routed spike msgs/s per GPU; % of HBM peak BW",
