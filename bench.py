@@ -225,7 +225,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs one GPU's share on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU exchange is design only in this build)", file=sys.stderr)
+              "(no exchange between GPUs is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
