@@ -1460,7 +1460,10 @@ constexpr uint32_t SPIN_LIMIT = 1u << 22;
 // The hand-off of the one-launch receive side.  Staging block b publishes
 // flag word b (its own 64-byte line) once its queues and counts are stored:
 // tag << 4 | the XCD it ran on, the tag being the step counter as this
-// launch reads it, so a word left by an earlier launch never matches.
+// launch reads it (at least 1: the update has advanced it), so neither the
+// zeroed words of a new handle nor the words of the previous step match.  The
+// tag keeps the counter's low 28 bits: a word written by a one-launch receive
+// side exactly k * 2^28 steps earlier, with none in between, would match.
 __device__ __forceinline__ uint32_t staged_word(const KParams& p, uint32_t xcc) {
   return (static_cast<uint32_t>(p.st->t) << 4) | xcc;
 }
