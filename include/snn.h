@@ -332,9 +332,9 @@ typedef struct {
                                (workgroups are dealt out to the XCDs in turn); where a
                                queue turns out to have been staged on another XCD, the
                                next synchronising call reports SNN_ERR_UNSUPPORTED.
-                               Its hand-off tags steps modulo 2^28: a handle that ran
-                               a nonzero multiple of 2^28 steps without it since its
-                               last one-launch step must take one step with 0 first */
+                               Its hand-off tags steps modulo 2^28; a step a nonzero
+                               multiple of 2^28 steps after the last one-launch step
+                               takes the two-launch form (the runtime sees to it) */
 } snn_tuning;
 
 /* Sets / reads the handle's launch shapes.  Setting synchronises the stream

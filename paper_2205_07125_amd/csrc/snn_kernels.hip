@@ -1463,7 +1463,8 @@ constexpr uint32_t SPIN_LIMIT = 1u << 22;
 // launch reads it (at least 1: the update has advanced it), so neither the
 // zeroed words of a new handle nor the words of the previous step match.  The
 // tag keeps the counter's low 28 bits: a word written by a one-launch receive
-// side exactly k * 2^28 steps earlier, with none in between, would match.
+// side exactly k * 2^28 steps earlier, with none in between, would match, so
+// the host runs such a step's receive side as two launches instead.
 __device__ __forceinline__ uint32_t staged_word(const KParams& p, uint32_t xcc) {
   return (static_cast<uint32_t>(p.st->t) << 4) | xcc;
 }

@@ -170,6 +170,7 @@ struct snn_ctx {
   int route_mode;     // mode of the step in flight
   bool expand_deferred;  // snn_step_route left the mask expansion to snn_deliver
   uint64_t t_host;    // steps enqueued
+  uint64_t handoff_t;  // step counter read by the last one-launch receive side (0: none)
   uint64_t routed_t;  // step whose routes are in the buffers (+1), 0 = none
   // captured steps, per layout (0: one update launch per step, 1: one per
   // partition) and route mode: one step, GRAPH_STEPS steps
@@ -184,6 +185,25 @@ struct snn_ctx {
 // Steps captured in the long graph: replaying several steps per launch spreads
 // the graph launch cost (several microseconds) over them.
 constexpr uint32_t GRAPH_STEPS = 16;
+
+// The one-launch receive side tags its hand-off flags with the low 28 bits of
+// the step counter it reads, which is t_host + 1 during step t_host.  The
+// flags keep the tag of the last such launch (0 in a new workspace), so a
+// launch a nonzero multiple of 2^28 steps later, with none in between, would
+// take them as current.  The runtime gives that one step the three-launch
+// receive side (same results, flags left alone); the steps after it differ
+// from the stored tag again.
+constexpr uint64_t HANDOFF_TAG_MASK = (uint64_t(1) << 28) - 1;
+
+static bool handoff_tag_repeats(const snn_ctx* h) {
+  const uint64_t t = h->t_host + 1;
+  return t != h->handoff_t && ((t - h->handoff_t) & HANDOFF_TAG_MASK) == 0;
+}
+
+// The receive side of a whole step in `mode` runs as one launch.
+static bool handoff_used(const snn_ctx* h, int mode) {
+  return mode != SNN_ROUTE_FLAT && h->kp.recv_merged;
+}
 
 // Scratch of the allocation-free entry point (snn_create_static): the whole
 // workspace of one handle, at most SNN_STATIC_SCRATCH_BYTES.  Each device that
@@ -496,7 +516,14 @@ static hipError_t launch_step_as(snn_handle h, int layout, int mode) {
 snn_status snn_deliver(snn_handle h) {
   if (!h) return fail(SNN_ERR_INVALID_ARG, "handle is NULL");
   if (h->phase != 2) return fail(SNN_ERR_BAD_STATE, "snn_deliver must follow snn_route");
-  HIP_TRY(launch_deliver(h->kp, h->route_mode, h->stream, nullptr, h->expand_deferred));
+  if (h->expand_deferred && handoff_used(h, h->route_mode) && handoff_tag_repeats(h)) {
+    KParams q = h->kp;
+    q.recv_merged = 0;
+    HIP_TRY(launch_deliver(q, h->route_mode, h->stream, nullptr, true));
+  } else {
+    HIP_TRY(launch_deliver(h->kp, h->route_mode, h->stream, nullptr, h->expand_deferred));
+    if (h->expand_deferred && handoff_used(h, h->route_mode)) h->handoff_t = h->t_host + 1;
+  }
   h->expand_deferred = false;
   h->phase = 0;
   h->t_host += 1;
@@ -548,6 +575,17 @@ static snn_status run_steps(snn_handle h, uint32_t n_steps, int mode, int use_gr
     return fail(SNN_ERR_UNSUPPORTED, "snn_run: a handle from snn_create_static runs without "
                 "HIP graphs (instantiating one allocates)");
   if (n_steps == 0) return SNN_OK;
+  const bool handoff = handoff_used(h, mode);
+  if (handoff && handoff_tag_repeats(h)) {
+    KParams q = h->kp;
+    q.recv_merged = 0;
+    HIP_TRY(layout ? launch_step_partitioned(q, mode, h->stream, h->part_start)
+                   : launch_step(q, mode, h->stream, nullptr));
+    h->route_mode = mode;
+    h->t_host += 1;
+    h->routed_t = h->t_host;
+    if (--n_steps == 0) return SNN_OK;
+  }
   if (!use_graph) {
     for (uint32_t i = 0; i < n_steps; ++i) HIP_TRY(launch_step_as(h, layout, mode));
   } else if (use_graph == 2) {
@@ -578,6 +616,7 @@ static snn_status run_steps(snn_handle h, uint32_t n_steps, int mode, int use_gr
   h->route_mode = mode;
   h->t_host += n_steps;
   h->routed_t = h->t_host;
+  if (handoff) h->handoff_t = h->t_host;
   return SNN_OK;
 }
 
@@ -671,9 +710,13 @@ snn_status snn_kernel_times(snn_handle h, uint32_t n_steps, int mode, float* avg
     }
   }
   double total[SNN_NKERNEL] = {};
+  const bool handoff = handoff_used(h, mode);
   for (uint32_t i = 0; i < n_steps && st == SNN_OK; ++i) {
     hipEvent_t* m = marks.data() + size_t(2) * SNN_NKERNEL * i;
-    hipError_t r = launch_step(h->kp, mode, h->stream, m);
+    KParams q = h->kp;
+    if (handoff && handoff_tag_repeats(h)) q.recv_merged = 0;   // see handoff_tag_repeats
+    else if (handoff) h->handoff_t = h->t_host + 1;
+    hipError_t r = launch_step(q, mode, h->stream, m);
     if (r != hipSuccess) st = fail(SNN_ERR_HIP, "timed step: %s", hipGetErrorString(r));
     h->t_host += 1;
     h->route_mode = mode;
