@@ -45,3 +45,30 @@ def test_forced_raster_partial_range_and_schedule():
                            oracle.forced_raster(params, 3, 1234, 5000)])
     assert np.array_equal(full, part) and len(full) > 0
     assert len(oracle.forced_raster(params, 7)) == 0      # off phase, rate 0
+
+
+def test_burst_schedule_and_rate_from_the_workload_definition():
+    """The heavy workload's bursts (rate_on for the first on_steps of every
+    period_steps, silence otherwise), pinned by what that definition implies
+    rather than by the oracle's formula: a step has spikes exactly when
+    t mod period < on_steps, in the network simulation and in the any-size
+    raster alike, and the spikes of the on steps are Binomial(N * steps, p)
+    with p = rate_on * dt, within 4 sigma."""
+    wl = synth.get_workload("heavy").scaled(6000, k_in=10, period_steps=20, on_steps=5)
+    assert wl.rate_off_hz == 0.0
+    N, T = wl.n_neurons, 60
+    p = wl.rate_on_hz * wl.dt_ms * 1e-3
+    gen = synth.Generator(wl)
+    params = oracle.params_from_workload(wl)
+    sim = oracle.Sim(params, gen.edges(), gen.part_map(), synth.initial_u(wl))
+    counts = []
+    for t in range(T):
+        sim.step()
+        counts.append(len(sim.fired()))
+        assert len(oracle.forced_raster(params, t)) == counts[-1]
+    on = [t for t in range(T) if t % 20 < 5]
+    # an on step without spikes has probability (1 - p)^N, about e^-60
+    assert [t for t in range(T) if counts[t] > 0] == on
+    n = N * len(on)
+    total = sum(counts[t] for t in on)
+    assert abs(total - n * p) < 4 * np.sqrt(n * p * (1 - p)), (total, n * p)

@@ -10,7 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_rng.py", "tests/test_oracle_lif.py",
              "tests/test_oracle_routing.py", "tests/test_oracle_delivery.py",
-             "tests/test_oracle_accuracy.py"]
+             "tests/test_oracle_accuracy.py", "tests/test_oracle_forced.py"]
 
 MUTANTS = {
     "philox_word_swap": ("uint32_t y0 = hi1 ^ x1 ^ k0;", "uint32_t y0 = hi1 ^ x3 ^ k0;"),
@@ -36,6 +36,16 @@ MUTANTS = {
     "no_slot_clear": ("s->ring[(size_t)slot * s->N + i] = 0.0f;", ""),
     "fp64_weight": ("s->ring64[at] += s->e_w64[e];",
                     "s->ring64[at] += (double)(float)s->e_w64[e] * 1.0000001;"),
+    # the forced raster
+    "raster_phase": ("forced && (t % s->p.period_steps) < s->p.on_steps ? s->thr_on : s->thr_off",
+                     "forced && (t % s->p.period_steps) <= s->p.on_steps ? s->thr_on : s->thr_off"),
+    "raster_phase_any_size": ("double rate = (t % p->period_steps) < p->on_steps ?",
+                              "double rate = (t % p->period_steps) <= p->on_steps ?"),
+    "raster_rates_swapped": ("? s->thr_on : s->thr_off;", "? s->thr_off : s->thr_on;"),
+    "raster_threshold_scale": ("floor(ldexp(rate_hz * dt_ms * 1e-3, 32))",
+                               "floor(ldexp(rate_hz * dt_ms * 1e-3, 31))"),
+    "raster_stream": ("forced_spike = draw(s->p.seed, i, t, STREAM_RASTER)",
+                      "forced_spike = draw(s->p.seed, i, t, STREAM_POISSON)"),
     # the accuracy report
     "acc_no_max_dv": ("if (dv > s->max_dv) s->max_dv = dv;", "(void)dv;"),
     "acc_no_first_div": ("s->first_div = (int64_t)t;", "(void)t;"),
