@@ -46,6 +46,12 @@ MUTANTS = {
                                "floor(ldexp(rate_hz * dt_ms * 1e-3, 31))"),
     "raster_stream": ("forced_spike = draw(s->p.seed, i, t, STREAM_RASTER)",
                       "forced_spike = draw(s->p.seed, i, t, STREAM_POISSON)"),
+    "forced_neuron_delay": ("arrive[ts + in_delay[m]] = f32((double)arrive[ts + in_delay[m]] + "
+                            "(double)w);",
+                            "arrive[ts + in_delay[m] - 1] = f32((double)arrive[ts + in_delay[m] - 1] "
+                            "+ (double)w);"),
+    "forced_neuron_pending": ("pending[d - 1] = arrive[n_steps - 1 + d];",
+                              "pending[d - 1] = arrive[n_steps - 2 + d];"),
     # the accuracy report
     "acc_no_max_dv": ("if (dv > s->max_dv) s->max_dv = dv;", "(void)dv;"),
     "acc_no_first_div": ("s->first_div = (int64_t)t;", "(void)t;"),
