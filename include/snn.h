@@ -315,9 +315,9 @@ snn_status snn_run(snn_handle h, uint32_t n_steps, int mode, int use_graph);
 snn_status snn_run_partitioned(snn_handle h, uint32_t n_steps, int mode, int use_graph,
                                const uint32_t* part_start);
 
-/* Launch-shape choices that leave every result unchanged; 0 in a field is
-   the library's default.  Picked per network shape by measurement (the
-   package's autotuner). */
+/* Launch-shape choices that leave every result unchanged; the library's
+   defaults are update_blocks = 0, recv_split = 0 and recv_merged = 1.
+   Picked per network shape by measurement (the package's autotuner). */
 typedef struct {
   uint32_t update_blocks;   /* blocks of a whole-step update launch: 0 = one per tile of
                                neurons; fewer = persistent blocks that take tiles in turn */

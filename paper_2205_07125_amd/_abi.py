@@ -216,8 +216,9 @@ def snn_run_partitioned(h, n_steps: int, mode: int, use_graph, part_start):
 
 
 def snn_set_tuning(h, update_blocks: int = 0, recv_split: int = 0, recv_merged: int = 1):
-    """Defaults are the library's own: one update block per tile, one
-    receive block per node, the receive side as one launch."""
+    """Defaults are the library's own: one update block per tile, as many
+    receive blocks per node as the receive launch holds, the receive side as
+    one launch."""
     t = snn_tuning(update_blocks=update_blocks, recv_split=recv_split, recv_merged=recv_merged)
     check(lib().snn_set_tuning(h, ctypes.byref(t)))
 
