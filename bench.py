@@ -415,7 +415,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n_neurons": N, "in_degree": wl.k_in,
                    "partitions": wl.n_partitions, "gpus_per_node": wl.gpus_per_node,
-                   "remote_frac": wl.remote_frac, "rate_hz": wl.rate_on_hz if wl.forced else None,
+                   # uneven partitions draw each one's cross fraction from a range
+                   "remote_frac": ([wl.cross_lo, wl.cross_hi] if wl.cross_hi > 0
+                                   else wl.remote_frac), "rate_hz": wl.rate_on_hz if wl.forced else None,
                    "route": args.mode, "graph": use_graph, "synapses": int(nnz),
                    "tile_neurons": sim_tile},
         "routed_msgs_per_s": (msgs if mode == SNN_ROUTE_TWO_LEVEL else flat) / sec,
